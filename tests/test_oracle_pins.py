@@ -1,0 +1,315 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and mathematics.
+
+None of these compares the oracle with itself: each checks it against a
+brute-force computation, an invariant, a closed form or the paper's own
+arithmetic, chosen so that a dropped term, a wrong sign or index, or a
+transposed operand fails at least one test.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _rng(k):
+    return np.random.default_rng(12345 + k)
+
+
+# ---------------------------------------------------------------------------
+# Bispectrum definition (Sections 2 and 3.2, speckle masking).
+# ---------------------------------------------------------------------------
+def test_bispectrum_equals_bruteforce_triple_correlation_8x8():
+    """B(u1,u2) = I(u1) I(u2) conj I(u1+u2) is the 4-D DFT of the circular
+    triple correlation T(x1,x2) = sum_x i(x) i(x+x1) i(x+x2), computed here
+    with explicit exponentials (no FFT) on an 8x8 non-symmetric image."""
+    N = 8
+    img = _rng(0).random((N, N))
+    q = img - img.mean()
+    # triple correlation, brute force
+    T = np.zeros((N, N, N, N))
+    for y1 in range(N):
+        for x1 in range(N):
+            s1 = np.roll(q, (-y1, -x1), axis=(0, 1))
+            for y2 in range(N):
+                for x2 in range(N):
+                    s2 = np.roll(q, (-y2, -x2), axis=(0, 1))
+                    T[y1, x1, y2, x2] = np.sum(q * s1 * s2)
+    # all (w, v) with components in [-3, 3]
+    rng = range(-3, 4)
+    wv = np.array([(wx, wy, vx, vy) for wx in rng for wy in rng for vx in rng for vy in rng])
+    I, mu = oracle.patch_spectra(img[None], window=0)
+    assert abs(mu[0] - img.mean()) < 1e-15
+    B = oracle.bispectrum(I, wv)
+    n = np.arange(N)
+    for k in _rng(1).choice(len(wv), 200, replace=False):
+        wx, wy, vx, vy = wv[k]
+        u1 = (wx - vx, wy - vy)
+        u2 = (vx, vy)
+        e1 = np.exp(-2j * np.pi * (u1[0] * n[None, :] + u1[1] * n[:, None]) / N)  # [y1][x1]
+        e2 = np.exp(-2j * np.pi * (u2[0] * n[None, :] + u2[1] * n[:, None]) / N)  # [y2][x2]
+        ref = np.einsum("abcd,ab,cd->", T, e1, e2)
+        assert abs(B[k] - ref) <= 1e-12 * max(1.0, abs(ref)), (wv[k], B[k], ref)
+
+
+def test_bispectrum_invariant_under_integer_frame_shifts():
+    N, F = 16, 4
+    Wset, S, woff = oracle.bispectrum_set(7, 4)
+    frames = _rng(2).random((F, N, N))
+    shifted = np.stack([np.roll(frames[f], tuple(_rng(10 + f).integers(0, N, 2)), axis=(0, 1))
+                        for f in range(F)])
+    B0 = oracle.accumulate_patch(frames, oracle.Params(patch=N, v_radius=4, window=0), S)["B"]
+    B1 = oracle.accumulate_patch(shifted, oracle.Params(patch=N, v_radius=4, window=0), S)["B"]
+    scale = np.max(np.abs(B0))
+    assert np.max(np.abs(B0 - B1)) <= 1e-12 * scale
+    # a non-shift change (transpose of one frame) must change it
+    frames[0] = frames[0].T
+    B2 = oracle.accumulate_patch(frames, oracle.Params(patch=N, v_radius=4, window=0), S)["B"]
+    assert np.max(np.abs(B0 - B2)) > 1e-3 * scale
+
+
+def test_bispectrum_symmetries():
+    N = 16
+    I, _ = oracle.patch_spectra(_rng(3).random((3, N, N)), window=1)
+    Wset, S, woff = oracle.bispectrum_set(7, 5)
+    B = oracle.bispectrum(I, S)
+    wx, wy, vx, vy = (S[:, i] for i in range(4))
+    # Hermitian: B(-w, -v) = conj B(w, v)
+    Bneg = oracle.bispectrum(I, np.stack([-wx, -wy, -vx, -vy], 1))
+    np.testing.assert_allclose(Bneg, np.conj(B), rtol=0, atol=1e-12 * np.abs(B).max())
+    # exchange of the two short sides: B(w, v) = B(w, w - v)
+    Bsw = oracle.bispectrum(I, np.stack([wx, wy, wx - vx, wy - vy], 1))
+    np.testing.assert_allclose(Bsw, B, rtol=0, atol=1e-12 * np.abs(B).max())
+    # B(u1, u2) = B(-u1-u2, u2):  (w, v) -> (v - w, v)
+    Bp = oracle.bispectrum(I, np.stack([vx - wx, vy - wy, vx, vy], 1))
+    np.testing.assert_allclose(Bp, B, rtol=0, atol=1e-12 * np.abs(B).max())
+
+
+# ---------------------------------------------------------------------------
+# The index sets.
+# ---------------------------------------------------------------------------
+def _gauss_circle(r):
+    """Lattice points with x^2 + y^2 <= r^2 (column sums of the disk)."""
+    return sum(2 * math.isqrt(r * r - x * x) + 1 for x in range(-r, r + 1))
+
+
+@pytest.mark.parametrize("uc,R", [(7, 3), (31, 8), (63, 12)])
+def test_bispectrum_set_definition(uc, R):
+    Wset, S, woff = oracle.bispectrum_set(uc, R)
+    # |W| is half the punctured disk (Gauss circle count)
+    assert len(Wset) == (_gauss_circle(uc) - 1) // 2
+    n2 = (Wset ** 2).sum(1)
+    assert np.all(np.diff(n2) >= 0)
+    assert np.all((Wset[:, 1] > 0) | ((Wset[:, 1] == 0) & (Wset[:, 0] > 0)))
+    assert woff[-1] == len(S)
+    # every sample is a triangle with two strictly shorter nonzero sides
+    w2 = S[:, 0] ** 2 + S[:, 1] ** 2
+    v2 = S[:, 2] ** 2 + S[:, 3] ** 2
+    d2 = (S[:, 0] - S[:, 2]) ** 2 + (S[:, 1] - S[:, 3]) ** 2
+    assert np.all((v2 > 0) & (v2 < w2) & (v2 <= R * R) & (d2 > 0) & (d2 < w2))
+    # completeness against a direct set-builder for a sample of w
+    for i in _rng(4).choice(len(Wset), 30, replace=False):
+        wx, wy = Wset[i]
+        ref = {(vx, vy) for vx in range(-R, R + 1) for vy in range(-R, R + 1)
+               if 0 < vx * vx + vy * vy <= R * R and vx * vx + vy * vy < wx * wx + wy * wy
+               and 0 < (wx - vx) ** 2 + (wy - vy) ** 2 < wx * wx + wy * wy}
+        got = {(int(a), int(b)) for a, b in S[woff[i]:woff[i + 1], 2:4]}
+        assert got == ref
+        assert np.all(S[woff[i]:woff[i + 1], 0] == wx)
+    # only (1,0) and (0,1) have no samples
+    empty = [tuple(Wset[i]) for i in range(len(Wset)) if woff[i + 1] == woff[i]]
+    assert sorted(empty) == [(0, 1), (1, 0)]
+
+
+# ---------------------------------------------------------------------------
+# Phase recursion: exact recovery up to translation.
+# ---------------------------------------------------------------------------
+def _recovery_case(transfer):
+    N, F, uc, R = 16, 6, 7, 3
+    rng = _rng(5)
+    obj = rng.random((N, N))
+    O = np.fft.fft2(obj)
+    frames = []
+    for f in range(F):
+        sh = tuple(rng.integers(0, N, 2))
+        img = np.roll(obj, sh, axis=(0, 1))
+        if transfer:
+            # real, positive per-frame transfer function (Gaussian blur)
+            k = np.fft.fftfreq(N)
+            g = np.exp(-(k[None, :] ** 2 + k[:, None] ** 2) * (1.0 + 3.0 * rng.random()))
+            img = np.real(np.fft.ifft2(np.fft.fft2(img) * g))
+        frames.append(img)
+    frames = np.stack(frames)
+    p = oracle.Params(patch=N, u_cut=uc, v_radius=R, window=0)
+    Wset, S, woff = oracle.bispectrum_set(uc, R)
+    acc = oracle.accumulate_patch(frames, p, S)
+    e = oracle.phase_recursion(acc["B"], 1.0, 1.0, Wset, S, woff, N)
+    phi = np.angle(O)
+    ref = phi[Wset[:, 1] % N, Wset[:, 0] % N] - Wset[:, 0] * phi[0, 1] - Wset[:, 1] * phi[1, 0]
+    d = np.angle(e * np.exp(-1j * ref))
+    return np.max(np.abs(d))
+
+
+def test_phase_recursion_recovers_object_up_to_translation():
+    assert _recovery_case(False) < 1e-10
+
+
+def test_phase_recursion_recovers_object_through_real_positive_transfer():
+    assert _recovery_case(True) < 1e-10
+
+
+def test_phase_recursion_weights_by_bispectrum_modulus():
+    """w = (1,1) has two samples, v = (1,0) and v = (0,1).  With the seeds at
+    phase 0 and B = 1 and 3i, the |B|-weighted phasor sum is 1 - 3i, so
+    arg e(1,1) = -atan(3) (an unweighted average would give -pi/4)."""
+    N = 8
+    Wset, S, woff = oracle.bispectrum_set(2, 1)
+    i11 = [k for k, w in enumerate(Wset) if tuple(w) == (1, 1)][0]
+    B = np.zeros(len(S), dtype=complex)
+    seg = S[woff[i11]:woff[i11 + 1]]
+    assert sorted(map(tuple, seg[:, 2:4])) == [(0, 1), (1, 0)]
+    B[woff[i11]:woff[i11 + 1]] = [1.0 if tuple(v) == (1, 0) else 3j for v in seg[:, 2:4]]
+    e = oracle.phase_recursion(B, 1.0, 1.0, Wset, S, woff, N)
+    assert abs(np.angle(e[i11]) + math.atan(3.0)) < 1e-14
+    # the seeds come from the mean spectrum phase
+    e = oracle.phase_recursion(B, 2.0 * np.exp(0.3j), -1.0, Wset, S, woff, N)
+    i10 = [k for k, w in enumerate(Wset) if tuple(w) == (1, 0)][0]
+    i01 = [k for k, w in enumerate(Wset) if tuple(w) == (0, 1)][0]
+    assert abs(e[i10] - np.exp(0.3j)) < 1e-15 and abs(e[i01] + 1.0) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Fourier modulus, Eq. 1.
+# ---------------------------------------------------------------------------
+def test_amplitude_eq1_closed_form():
+    """Noiseless periodic frames o (*) h_f, no taper: <|I|^2> / <|H|^2> =
+    |O|^2 exactly when the STF is the sample mean of |H_f|^2."""
+    N, F = 32, 8
+    rng = _rng(6)
+    obj = 1.0 + 0.1 * rng.standard_normal((N, N))
+    O = np.fft.fft2(obj)
+    H = []
+    frames = []
+    for f in range(F):
+        h = rng.random((N, N)) ** 8
+        h /= h.sum()
+        Hf = np.fft.fft2(h)
+        H.append(Hf)
+        frames.append(np.real(np.fft.ifft2(O * Hf)))
+    stf = np.mean(np.abs(np.stack(H)) ** 2, axis=0)
+    p = oracle.Params(patch=N, window=0, v_radius=4)
+    acc = oracle.accumulate_patch(np.stack(frames), p)
+    Wset = oracle.frequency_half_disk(p.u_cut)
+    amp = oracle.amplitude(acc["P"], stf, Wset, 0.0, 1e-12)
+    ref = np.abs(O[Wset[:, 1] % N, Wset[:, 0] % N])
+    np.testing.assert_allclose(amp, ref, rtol=1e-10)
+    # the floor zeroes the modulus and the bias is subtracted before the root
+    stf2 = stf.copy()
+    stf2[Wset[0, 1] % N, Wset[0, 0] % N] = 1e-9
+    amp2 = oracle.amplitude(acc["P"], stf2, Wset, 0.0, 1e-6)
+    assert amp2[0] == 0.0
+    big = float(acc["P"].max()) * 2
+    assert np.all(oracle.amplitude(acc["P"], stf, Wset, big, 1e-12) == 0.0)
+
+
+def test_noise_bias_reads_the_corners_only():
+    N = 64
+    k = np.fft.fftfreq(N) * N
+    r = np.hypot(k[None, :], k[:, None])
+    P = 7.5 + np.where(r <= N / 2, 1e6 * np.exp(-r / 5.0), 0.0)
+    assert abs(oracle.noise_bias(P) - 7.5) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Synthesis and mosaic (Section 3.2).
+# ---------------------------------------------------------------------------
+def test_diffraction_filter_is_the_disk_overlap():
+    N = 64
+    Wset = np.array([[0, 1], [5, 3], [12, 10], [20, 21], [31, 1], [40, 0]])
+    T = oracle.diffraction_filter(Wset, N)
+    # overlap area of two unit disks at distance 2 rho, grid integration
+    g = np.linspace(-1, 1, 1601)
+    X, Y = np.meshgrid(g, g)
+    inside = X ** 2 + Y ** 2 <= 1.0
+    for (wx, wy), t in zip(Wset, T):
+        rho = math.hypot(wx, wy) / (N / 2)
+        if rho >= 1:
+            assert t == 0.0
+            continue
+        ov = inside & ((X - 2 * rho) ** 2 + Y ** 2 <= 1.0)
+        assert abs(ov.sum() / inside.sum() - t) < 5e-3
+
+
+def test_hann_taper_is_cola_at_half_overlap():
+    h = oracle.hann(32)
+    s = h[:16] + h[16:]
+    np.testing.assert_allclose(s, 1.0, atol=1e-15)
+
+
+def _sinusoid_image(H, W, N):
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    img = 3.0 + 0.0 * x
+    for (kx, ky, a, th) in [(1, 0, 0.5, 0.3), (2, 3, 0.2, 1.0), (-3, 2, 0.1, -0.7), (0, 4, 0.3, 2.0)]:
+        img += a * np.cos(2 * np.pi * (kx * x + ky * y) / N + th)
+    return img
+
+
+@pytest.mark.parametrize("clampcase", [False, True])
+def test_synthesis_and_mosaic_reproduce_a_band_limited_image(clampcase):
+    """Feeding the true tapered patch spectra through synthesis and the
+    mosaic returns the image wherever the summed taper is nonzero.  The
+    image holds sinusoids periodic in the patch, so each tapered patch's
+    spectrum lies inside |u| <= u_cut."""
+    N, s = 16, 8
+    H, W = (48, 52) if clampcase else (48, 48)
+    img = _sinusoid_image(H, W, N)
+    ys, xs = oracle.tiling(H, W, N, s)
+    Wset = oracle.frequency_half_disk(N // 2 - 1)
+    pat = np.zeros((len(ys), len(xs), N, N))
+    for i, y0 in enumerate(ys):
+        for j, x0 in enumerate(xs):
+            I, mu = oracle.patch_spectra(img[None, y0:y0 + N, x0:x0 + N], window=1)
+            vals = I[0][Wset[:, 1] % N, Wset[:, 0] % N]
+            amp = np.abs(vals)
+            ph = np.where(amp > 0, vals / np.where(amp > 0, amp, 1), 1.0)
+            pat[i, j] = oracle.synthesize_patch(amp, ph, Wset, N, mu[0], 1)
+    out = oracle.mosaic(pat, ys, xs, H, W, 1)
+    np.testing.assert_allclose(out[1:, 1:], img[1:, 1:], atol=1e-10)
+    assert np.all(out[0, :] == 0) and np.all(out[:, 0] == 0)
+
+
+def test_constant_image_stays_constant():
+    N = 16
+    img = np.full((40, 40), 5.25)
+    ys, xs = oracle.tiling(40, 40, N, 8)
+    Wset = oracle.frequency_half_disk(N // 2 - 1)
+    pat = np.zeros((len(ys), len(xs), N, N))
+    for i, y0 in enumerate(ys):
+        for j, x0 in enumerate(xs):
+            I, mu = oracle.patch_spectra(img[None, y0:y0 + N, x0:x0 + N], window=1)
+            assert np.max(np.abs(I)) < 1e-12
+            pat[i, j] = oracle.synthesize_patch(np.zeros(len(Wset)), np.ones(len(Wset)), Wset, N, mu[0], 1)
+    out = oracle.mosaic(pat, ys, xs, 40, 40, 1)
+    np.testing.assert_allclose(out[1:, 1:], 5.25, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Tiling: the paper's own arithmetic (Sections 3.2 and 4).
+# ---------------------------------------------------------------------------
+def test_tiling_matches_the_papers_cube_counts():
+    # 1110 overlapping 256x256 cubes from 2560x2160 (Sections 3.2, 4)
+    ys, xs = oracle.tiling(2160, 2560, 256, 64, clamp=False)
+    assert len(ys) * len(xs) == 1110 and (len(xs), len(ys)) == (37, 30)
+    # the 2368x1920 mosaic is the central 64x64 of every cube (Section 4)
+    assert (len(xs) * 64, len(ys) * 64) == (2368, 1920)
+    # 80 non-overlapping 256x256 seeing cubes (Section 3.2)
+    ys, xs = oracle.tiling(2160, 2560, 256, 256, clamp=False)
+    assert len(ys) * len(xs) == 80
+    # the reconstruction grids used here: 128 px patches at 50 % overlap
+    ys, xs = oracle.tiling(1024, 1024, 128, 64)
+    assert (len(ys), len(xs)) == (15, 15)
+    ys, xs = oracle.tiling(2160, 2560, 128, 64)
+    assert (len(ys), len(xs)) == (33, 39) and ys[-1] == 2160 - 128 and xs[-1] == 2560 - 128
+    # "around 55 GB" of cubes holds for 8-byte pixels (Section 4)
+    assert abs(1110 * 100 * 256 * 256 * 8 / 1e9 - 58.2) < 0.1
