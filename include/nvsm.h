@@ -1,0 +1,177 @@
+/*
+ * nvsm.h - speckle-masking burst reconstruction on one AMD MI355X (gfx950).
+ *
+ * A burst of short-exposure frames goes in, one reconstructed image comes
+ * out (Li et al., "High Performance Parallel Image Reconstruction for New
+ * Vacuum Solar Telescope", Section 1: one burst of at least 100 short
+ * exposures gives one image).  The burst is cut into partially overlapping
+ * subimages (Section 3.2); for each, the mean power spectrum and the mean
+ * bispectrum are accumulated over the frames, the Fourier modulus follows
+ * from Labeyrie's relation (Eq. 1) with a speckle transfer function (STF)
+ * table, the Fourier phase from the speckle-masking recursion (Sections 2
+ * and 3.2), and the inverse transforms are merged into a mosaic
+ * (Section 3.2).
+ *
+ * Conventions used throughout:
+ *  - frames are [F][H][W] with x (the W axis) fastest; rows are
+ *    row_pitch elements apart (row_pitch >= W);
+ *  - a frequency u = (ux, uy) is stored at [uy mod N][ux mod N] of an
+ *    N x N array ("DFT order");
+ *  - the forward transform is exp(-2 pi i u.x / N), unnormalised;
+ *  - W is the set of frequencies 0 < |w| <= u_cut with wy > 0 or
+ *    (wy == 0 and wx > 0), ordered by |w|^2, then wy, then wx;
+ *  - S is the set of bispectrum samples (w, v): w in W, 0 < |v| <= R,
+ *    |v|^2 < |w|^2 and 0 < |w - v|^2 < |w|^2, ordered by w (as in W) then
+ *    by (vy, vx);  B(w, v) = <I(w - v) I(v) conj I(w)> over frames;
+ *  - patches are numbered row-major over the tile grid: row k starts at
+ *    y = min(k * stride, H - N), column l at x = min(l * stride, W - N).
+ *
+ * Ownership: every buffer passed to a compute call is owned by the caller
+ * and must stay valid until the work on `stream` has finished.  Device
+ * buffers are device pointers on the context's device.  The context owns
+ * only small constant tables (index sets, twiddles, work lists) that it
+ * builds and uploads the first time a parameter set is used (or in
+ * nvsm_prepare); compute calls allocate no device memory after that.
+ *
+ * Errors: every call returns an nvsm_status.  Arguments are validated
+ * before anything is launched; a failed call has launched nothing.  Device
+ * faults surface at the caller's next synchronisation.  Calls are
+ * asynchronous on `stream` (a hipStream_t; NULL = the default stream).
+ * A context is not thread-safe: use one per host thread.
+ */
+#ifndef NVSM_H
+#define NVSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NVSM_OK = 0,
+    NVSM_ERR_INVALID_ARG = -1,   /* null pointer, bad enum, bad parameter   */
+    NVSM_ERR_SHAPE = -2,         /* sizes inconsistent with the parameters  */
+    NVSM_ERR_WORKSPACE = -3,     /* workspace smaller than nvsm_plan says   */
+    NVSM_ERR_OOM = -4,           /* host or device allocation failed        */
+    NVSM_ERR_HIP = -5,           /* a HIP runtime call or launch failed     */
+    NVSM_ERR_NOT_IMPLEMENTED = -6
+} nvsm_status;
+
+typedef enum { NVSM_U16 = 0, NVSM_F32 = 1 } nvsm_dtype;
+
+typedef struct nvsm_context nvsm_context;
+
+/* Reconstruction parameters.  nvsm_default_params fills the defaults. */
+typedef struct {
+    int32_t patch;        /* N, the subimage size: 64 or 128                */
+    int32_t stride;       /* tile step, 1..N (default N/2: 50 % overlap)    */
+    int32_t u_cut;        /* largest |w| reconstructed, < N/2 (default N/2-1) */
+    int32_t v_radius;     /* R, largest |v| in the bispectrum, 1..16, < u_cut */
+    int32_t window;       /* 0 none, 1 periodic Hann taper (default 1)      */
+    int32_t phase_method; /* 0 recursive speckle-masking solve              */
+    int32_t noise_bias;   /* 0 off, 1 subtract the mean power beyond |u| > N/2+2 */
+    int32_t filter;       /* 0 none, 1 diffraction-limited OTF of the pupil  */
+    double  stf_floor;    /* modulus 0 where STF < stf_floor (default 1e-6) */
+} nvsm_params;
+
+/* Sizes derived from parameters and a burst shape (nvsm_plan). */
+typedef struct {
+    int32_t patches_y, patches_x; /* tile grid                              */
+    int64_t patches;              /* patches_y * patches_x                  */
+    int64_t w_count;              /* |W|                                    */
+    int64_t s_count;              /* |S|                                    */
+    int32_t shells;               /* distinct |w|^2 in W                    */
+    int32_t frame_chunks;         /* frame groups of the accumulation       */
+    size_t  ws_accumulate;        /* workspace bytes for nvsm_accumulate    */
+    size_t  ws_solve;             /* workspace bytes for nvsm_solve         */
+    size_t  ws_synthesize;        /* workspace bytes for nvsm_synthesize    */
+    size_t  ws_reconstruct;       /* workspace bytes for nvsm_reconstruct   */
+} nvsm_plan_info;
+
+/* Context on HIP device `hip_device`.  *out is NULL on failure. */
+nvsm_status nvsm_create(int hip_device, nvsm_context **out);
+/* Frees the context and its tables (waits for nothing: synchronise first). */
+void nvsm_destroy(nvsm_context *ctx);
+/* Static text for a status code. */
+const char *nvsm_status_string(nvsm_status s);
+/* Text describing the context's last failure ("" if none). */
+const char *nvsm_last_error(const nvsm_context *ctx);
+
+/* Defaults for patch size N (64 or 128): stride N/2, u_cut N/2-1, R 10,
+ * Hann window, recursive phase, no noise bias, no filter, floor 1e-6. */
+nvsm_status nvsm_default_params(int32_t patch, nvsm_params *out);
+
+/* Validates params against an H x W x F burst and fills *out.  Host only. */
+nvsm_status nvsm_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t F,
+                      nvsm_plan_info *out);
+
+/* The set W in its storage order: w[i*2 + 0] = wx, w[i*2 + 1] = wy.
+ * Host buffer of 2*w_count int32; w_count must equal |W|.  Host only. */
+nvsm_status nvsm_w_index(const nvsm_params *p, int32_t *w, int64_t w_count);
+
+/* The set S in its storage order: wv[i*4 + 0..3] = (wx, wy, vx, vy).
+ * Host buffer of 4*s_count int32; s_count must equal |S|.  Host only. */
+nvsm_status nvsm_bispectrum_index(const nvsm_params *p, int32_t *wv, int64_t s_count);
+
+/* Builds and uploads the context's tables for `p` (synchronous).  Optional:
+ * the compute calls do it on first use of a parameter set. */
+nvsm_status nvsm_prepare(nvsm_context *ctx, const nvsm_params *p);
+
+/* Accumulation over the burst (Eq. 1 numerator and the speckle-masking
+ * bispectrum).  For every patch k, with p_f the N x N cut of frame f and
+ * t the taper: mu_f = sum(t p_f) / sum(t), I_f = FFT2((p_f - mu_f) t).
+ * Outputs (device, caller-owned):
+ *   power     [P][N][N] float   <|I_f(u)|^2>, DFT order
+ *   mean_spec [P][2][2] float   <I_f(1,0)> and <I_f(0,1)> as (re, im)
+ *   mu        [P]       float   <mu_f>
+ *   bispec    [P][|S|][2] float <I_f(w-v) I_f(v) conj I_f(w)> in S order,
+ *             or NULL to skip the bispectrum.
+ * frames: device [F][H][row_pitch] of uint16 or float32.
+ * Arithmetic: FP32; sums over frames use compensated (Kahan) summation. */
+nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p,
+                            const void *frames, nvsm_dtype dtype, int32_t F,
+                            int32_t H, int32_t W, int64_t row_pitch,
+                            float *power, float *mean_spec, float *mu, float *bispec,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Modulus and phase per patch, FP64 (Eq. 1; speckle-masking recursion).
+ *   amp[k][i]    = sqrt(max(power(w_i) - n, 0) / stf(w_i)), 0 where
+ *                  stf(w_i) < stf_floor; n is the noise level (0 unless
+ *                  noise_bias).  double [P][|W|].
+ *   phasor[k][i] = e(w_i) (re, im), double [P][|W|][2]: e(1,0), e(0,1) are
+ *                  the unit phasors of mean_spec, and every other w takes the
+ *                  phase of sum_v e(w-v) e(v) conj B(w,v) over its samples,
+ *                  in increasing |w| (e(-u) = conj e(u); 1 when the sum is 0).
+ * Inputs: power, mean_spec, bispec as produced by nvsm_accumulate for
+ * `patches` patches; stf: device double [N][N] in DFT order. */
+nvsm_status nvsm_solve(nvsm_context *ctx, const nvsm_params *p, int64_t patches,
+                       const float *power, const float *mean_spec, const float *bispec,
+                       const double *stf, double *amp, double *phasor,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* Inverse transform and mosaic (Section 3.2).  For each patch the spectrum
+ * filter(w) amp e(w) on W (conjugate at -w, 0 elsewhere) is transformed
+ * back (FP32), mu * taper is added, and the mosaic is
+ *   out(x) = sum_k r_k(x - o_k) / sum_k t(x - o_k)  (0 where the sum < 1e-3).
+ * patches_out: device float [P][N][N] to keep the subimages, or NULL (then
+ * the workspace holds them).  out: device float [H][W]. */
+nvsm_status nvsm_synthesize(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W,
+                            const double *amp, const double *phasor, const float *mu,
+                            float *patches_out, float *out,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* The whole path: frames (device) in, image out (device float [H][W]).
+ * Equivalent to accumulate + solve + synthesize with all intermediates in
+ * the workspace (nvsm_plan_info.ws_reconstruct bytes). */
+nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p,
+                             const void *frames, nvsm_dtype dtype, int32_t F,
+                             int32_t H, int32_t W, int64_t row_pitch,
+                             const double *stf, float *out,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NVSM_H */

@@ -1,0 +1,13 @@
+"""Speckle-masking burst reconstruction on AMD MI355X (gfx950).
+
+The computation lives in ``libnvsm.so`` (hand-written HIP kernels behind a
+C ABI, declared in ``include/nvsm.h``).  This package is the thin Python
+binding: ``_lib`` mirrors the C entry points one to one, and ``Session``
+only allocates the device buffers (torch tensors) those calls need.
+"""
+from ._lib import (  # noqa: F401
+    EXPORTS, LIB_PATH, NVSM_F32, NVSM_U16, NvsmError, Params, PlanInfo, default_params, lib,
+    nvsm_accumulate, nvsm_bispectrum_index, nvsm_create, nvsm_destroy, nvsm_last_error, nvsm_plan,
+    nvsm_prepare, nvsm_reconstruct, nvsm_solve, nvsm_synthesize, nvsm_w_index, status_string,
+)
+from .session import Session  # noqa: F401

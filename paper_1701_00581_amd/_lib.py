@@ -1,0 +1,217 @@
+"""ctypes binding of libnvsm.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and passes
+its arguments through: plain integers, device pointers (taken from torch
+tensors with ``data_ptr()``) and the HIP stream.  All computation happens
+in the library's HIP kernels; if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnvsm.so")
+
+NVSM_OK = 0
+NVSM_ERR_INVALID_ARG = -1
+NVSM_ERR_SHAPE = -2
+NVSM_ERR_WORKSPACE = -3
+NVSM_ERR_OOM = -4
+NVSM_ERR_HIP = -5
+NVSM_ERR_NOT_IMPLEMENTED = -6
+NVSM_U16 = 0
+NVSM_F32 = 1
+
+EXPORTS = [
+    "nvsm_create", "nvsm_destroy", "nvsm_status_string", "nvsm_last_error",
+    "nvsm_default_params", "nvsm_plan", "nvsm_w_index", "nvsm_bispectrum_index",
+    "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
+]
+
+
+class NvsmError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({status_string(status)}) {detail}".strip())
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("patch", ctypes.c_int32), ("stride", ctypes.c_int32), ("u_cut", ctypes.c_int32),
+        ("v_radius", ctypes.c_int32), ("window", ctypes.c_int32), ("phase_method", ctypes.c_int32),
+        ("noise_bias", ctypes.c_int32), ("filter", ctypes.c_int32), ("stf_floor", ctypes.c_double),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("patches_y", ctypes.c_int32), ("patches_x", ctypes.c_int32), ("patches", ctypes.c_int64),
+        ("w_count", ctypes.c_int64), ("s_count", ctypes.c_int64), ("shells", ctypes.c_int32),
+        ("frame_chunks", ctypes.c_int32), ("ws_accumulate", ctypes.c_size_t),
+        ("ws_solve", ctypes.c_size_t), ("ws_synthesize", ctypes.c_size_t),
+        ("ws_reconstruct", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1701_00581_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        c_p, c_i32, c_i64, c_sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        P = ctypes.POINTER(Params)
+        L.nvsm_create.argtypes = [ctypes.c_int, ctypes.POINTER(c_p)]
+        L.nvsm_destroy.argtypes = [c_p]
+        L.nvsm_destroy.restype = None
+        L.nvsm_status_string.argtypes = [ctypes.c_int]
+        L.nvsm_status_string.restype = ctypes.c_char_p
+        L.nvsm_last_error.argtypes = [c_p]
+        L.nvsm_last_error.restype = ctypes.c_char_p
+        L.nvsm_default_params.argtypes = [c_i32, P]
+        L.nvsm_plan.argtypes = [P, c_i32, c_i32, c_i32, ctypes.POINTER(PlanInfo)]
+        L.nvsm_w_index.argtypes = [P, c_p, c_i64]
+        L.nvsm_bispectrum_index.argtypes = [P, c_p, c_i64]
+        L.nvsm_prepare.argtypes = [c_p, P]
+        L.nvsm_accumulate.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64,
+                                      c_p, c_p, c_p, c_p, c_p, c_sz, c_p]
+        L.nvsm_solve.argtypes = [c_p, P, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]
+        L.nvsm_synthesize.argtypes = [c_p, P, c_i32, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]
+        L.nvsm_reconstruct.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64,
+                                       c_p, c_p, c_p, c_sz, c_p]
+        for name in EXPORTS:
+            if name not in ("nvsm_destroy", "nvsm_status_string", "nvsm_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    return lib().nvsm_status_string(int(status)).decode()
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor / array / int; None -> NULL."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    if hasattr(t, "ctypes"):
+        return t.ctypes.data
+    raise TypeError(f"cannot take the address of {type(t)}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status, where, ctx=None):
+    if status != NVSM_OK:
+        detail = ""
+        if ctx is not None:
+            detail = lib().nvsm_last_error(ctx).decode()
+        raise NvsmError(status, where, detail)
+
+
+def default_params(patch, **kw):
+    p = Params()
+    _check(lib().nvsm_default_params(int(patch), ctypes.byref(p)), "nvsm_default_params")
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def nvsm_create(device=0):
+    h = ctypes.c_void_p()
+    _check(lib().nvsm_create(int(device), ctypes.byref(h)), "nvsm_create")
+    return h.value
+
+
+def nvsm_destroy(ctx):
+    lib().nvsm_destroy(ctx)
+
+
+def nvsm_last_error(ctx):
+    return lib().nvsm_last_error(ctx).decode()
+
+
+def nvsm_plan(params, H, W, F):
+    info = PlanInfo()
+    _check(lib().nvsm_plan(ctypes.byref(params), int(H), int(W), int(F), ctypes.byref(info)), "nvsm_plan")
+    return info
+
+
+def nvsm_w_index(params):
+    import numpy as np
+    info = nvsm_plan(params, params.patch, params.patch, 1)
+    out = np.zeros((info.w_count, 2), dtype=np.int32)
+    _check(lib().nvsm_w_index(ctypes.byref(params), out.ctypes.data, info.w_count), "nvsm_w_index")
+    return out
+
+
+def nvsm_bispectrum_index(params):
+    import numpy as np
+    info = nvsm_plan(params, params.patch, params.patch, 1)
+    out = np.zeros((info.s_count, 4), dtype=np.int32)
+    _check(lib().nvsm_bispectrum_index(ctypes.byref(params), out.ctypes.data, info.s_count),
+           "nvsm_bispectrum_index")
+    return out
+
+
+def nvsm_prepare(ctx, params):
+    _check(lib().nvsm_prepare(ctx, ctypes.byref(params)), "nvsm_prepare", ctx)
+
+
+def frames_dtype(frames):
+    import torch
+    if frames.dtype in (torch.int16, torch.uint16):
+        return NVSM_U16
+    if frames.dtype == torch.float32:
+        return NVSM_F32
+    raise TypeError("frames must be uint16 (or int16 holding uint16 bits) or float32")
+
+
+def nvsm_accumulate(ctx, params, frames, power, mean_spec, mu, bispec, workspace, stream=None,
+                    row_pitch=None):
+    F, H, W = frames.shape
+    pitch = frames.stride(1) if row_pitch is None else row_pitch
+    st = lib().nvsm_accumulate(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W, pitch,
+                               _ptr(power), _ptr(mean_spec), _ptr(mu), _ptr(bispec), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream))
+    _check(st, "nvsm_accumulate", ctx)
+
+
+def nvsm_solve(ctx, params, patches, power, mean_spec, bispec, stf, amp, phasor, workspace=None,
+               stream=None):
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    st = lib().nvsm_solve(ctx, ctypes.byref(params), int(patches), _ptr(power), _ptr(mean_spec), _ptr(bispec),
+                          _ptr(stf), _ptr(amp), _ptr(phasor), _ptr(workspace), ws_bytes, _stream(stream))
+    _check(st, "nvsm_solve", ctx)
+
+
+def nvsm_synthesize(ctx, params, H, W, amp, phasor, mu, patches_out, out, workspace=None, stream=None):
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    st = lib().nvsm_synthesize(ctx, ctypes.byref(params), int(H), int(W), _ptr(amp), _ptr(phasor), _ptr(mu),
+                               _ptr(patches_out), _ptr(out), _ptr(workspace), ws_bytes, _stream(stream))
+    _check(st, "nvsm_synthesize", ctx)
+
+
+def nvsm_reconstruct(ctx, params, frames, stf, out, workspace, stream=None, row_pitch=None):
+    F, H, W = frames.shape
+    pitch = frames.stride(1) if row_pitch is None else row_pitch
+    st = lib().nvsm_reconstruct(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W, pitch,
+                                _ptr(stf), _ptr(out), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream))
+    _check(st, "nvsm_reconstruct", ctx)

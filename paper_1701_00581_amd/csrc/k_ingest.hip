@@ -1,0 +1,185 @@
+// Ingest: subimage cut, taper, 2-D FFT and the power/mean accumulation of
+// the Eq. 1 numerator.  One workgroup per (patch, group of frames).
+//
+// Two real frames a, b are transformed together as z = qa + i qb; with
+// Z = FFT2(z), Ia(u) = (Z(u) + conj Z(-u)) / 2 and
+// Ib(u) = (Z(u) - conj Z(-u)) / (2i).
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace nvsm {
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
+
+template <int N, typename T>
+__global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int F, int H, int W,
+                                               int64_t pitch, int nx, int stride, int chunk_frames,
+                                               int nchunks, int total, int window, float inv_wsum,
+                                               const float2 *__restrict__ twiddle,
+                                               const float *__restrict__ hann,
+                                               float2 *__restrict__ spectra, float *__restrict__ ppart,
+                                               float *__restrict__ mpart, float *__restrict__ mupart) {
+    constexpr int P = LdsPitch<N>::v;
+    constexpr int HALF = N / 2;
+    constexpr int NP = (HALF + 1) * N;           // power rows 0..N/2
+    constexpr int NPT = (NP + NT - 1) / NT;
+    constexpr int PPT = N * N / NT;              // pixels per thread
+    __shared__ float2 z[N * P];
+    __shared__ float2 tw[N];
+    __shared__ float hw[N];
+    __shared__ float red[2][NT / 64];
+
+    const int L = xcd_remap(blockIdx.x, total);
+    const int patch = L / nchunks, chunk = L % nchunks;
+    const int py = patch / nx, px = patch % nx;
+    const int y0 = min(py * stride, H - N), x0 = min(px * stride, W - N);
+    const int f0 = chunk * chunk_frames, f1 = min(F, f0 + chunk_frames);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += NT) {
+        tw[i] = twiddle[i];
+        hw[i] = window ? hann[i] : 1.0f;
+    }
+    float ps[NPT], pc[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) { ps[i] = 0.f; pc[i] = 0.f; }
+    float m10s[2] = {0.f, 0.f}, m10c[2] = {0.f, 0.f}, m01s[2] = {0.f, 0.f}, m01c[2] = {0.f, 0.f};
+    float mus = 0.f, muc = 0.f;
+    const size_t spec_patch = (size_t)patch * F * HALF * N;
+    __syncthreads();
+
+    for (int fa = f0; fa < f1; fa += 2) {
+        const int fb = fa + 1;
+        const bool hasb = fb < f1;
+        const T *pa = frames + (size_t)fa * H * pitch + (size_t)y0 * pitch + x0;
+        const T *pb = frames + (size_t)(hasb ? fb : fa) * H * pitch + (size_t)y0 * pitch + x0;
+        // load, weighted sums (compensated), raw pixels to LDS
+        float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
+#pragma unroll 4
+        for (int j = 0; j < PPT; ++j) {
+            const int i = j * NT + tid, y = i / N, x = i % N;
+            const float va = to_f(pa[(size_t)y * pitch + x]);
+            const float vb = hasb ? to_f(pb[(size_t)y * pitch + x]) : 0.f;
+            const float w = hw[y] * hw[x];
+            kahan_add(sa, ca, w * va);
+            kahan_add(sb, cb, w * vb);
+            z[y * P + x] = make_float2(va, vb);
+        }
+        float ra = wave_sum(sa - ca), rb = wave_sum(sb - cb);
+        if ((tid & 63) == 0) { red[0][tid >> 6] = ra; red[1][tid >> 6] = rb; }
+        __syncthreads();
+        float mua = 0.f, mub = 0.f;
+#pragma unroll
+        for (int k = 0; k < NT / 64; ++k) { mua += red[0][k]; mub += red[1][k]; }
+        mua *= inv_wsum;
+        mub *= inv_wsum;
+        if (tid == 0) {
+            kahan_add(mus, muc, mua);
+            if (hasb) kahan_add(mus, muc, mub);
+        }
+        // taper the mean-removed pixels
+#pragma unroll 4
+        for (int j = 0; j < PPT; ++j) {
+            const int i = j * NT + tid, y = i / N, x = i % N;
+            const float w = hw[y] * hw[x];
+            const float2 v = z[y * P + x];
+            z[y * P + x] = make_float2((v.x - mua) * w, hasb ? (v.y - mub) * w : 0.f);
+        }
+        __syncthreads();
+        fft2d_lds<N, NT>(z, tw);
+        // split the two spectra, write rows 0..N/2-1, accumulate |I|^2
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int j = k * NT + tid;
+            if (j < NP) {
+                const int uy = j / N, ux = j % N;
+                const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
+                const float2 Zm = z[fft_pos<N>((N - uy) & (N - 1)) * P + fft_pos<N>((N - ux) & (N - 1))];
+                const float2 Ia = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+                const float2 Ib = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+                kahan_add(ps[k], pc[k], Ia.x * Ia.x + Ia.y * Ia.y);
+                if (hasb) kahan_add(ps[k], pc[k], Ib.x * Ib.x + Ib.y * Ib.y);
+                if (uy < HALF) {
+                    spectra[spec_patch + (size_t)fa * HALF * N + j] = Ia;
+                    if (hasb) spectra[spec_patch + (size_t)fb * HALF * N + j] = Ib;
+                }
+                if (j == 1) {          // u = (1, 0)
+                    kahan_add(m10s[0], m10c[0], Ia.x); kahan_add(m10s[1], m10c[1], Ia.y);
+                    if (hasb) { kahan_add(m10s[0], m10c[0], Ib.x); kahan_add(m10s[1], m10c[1], Ib.y); }
+                }
+                if (j == N) {          // u = (0, 1)
+                    kahan_add(m01s[0], m01c[0], Ia.x); kahan_add(m01s[1], m01c[1], Ia.y);
+                    if (hasb) { kahan_add(m01s[0], m01c[0], Ib.x); kahan_add(m01s[1], m01c[1], Ib.y); }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // partial sums of this frame group
+    float *pp = ppart + ((size_t)patch * nchunks + chunk) * NP;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int j = k * NT + tid;
+        if (j < NP) pp[j] = ps[k] - pc[k];
+    }
+    float *mp = mpart + ((size_t)patch * nchunks + chunk) * 4;
+    if (tid == 1 % NT) { mp[0] = m10s[0] - m10c[0]; mp[1] = m10s[1] - m10c[1]; }
+    if (tid == N % NT) { mp[2] = m01s[0] - m01c[0]; mp[3] = m01s[1] - m01c[1]; }
+    if (tid == 0) mupart[(size_t)patch * nchunks + chunk] = mus - muc;
+}
+
+// Sums the frame groups (compensated) and divides by F; mirrors the power
+// spectrum rows N/2+1..N-1 from P(-u) = P(u).
+template <int N>
+__global__ __launch_bounds__(NT) void k_acc_finalize(int nchunks, float invF,
+                                                     const float *__restrict__ ppart,
+                                                     const float *__restrict__ mpart,
+                                                     const float *__restrict__ mupart,
+                                                     float *__restrict__ power, float *__restrict__ mean_spec,
+                                                     float *__restrict__ mu) {
+    constexpr int HALF = N / 2, NP = (HALF + 1) * N;
+    const int patch = blockIdx.x;
+    const float *pp = ppart + (size_t)patch * nchunks * NP;
+    for (int j = threadIdx.x; j < N * N; j += NT) {
+        const int uy = j / N, ux = j % N;
+        const int src = uy <= HALF ? j : ((N - uy) * N + ((N - ux) & (N - 1)));
+        float s = 0.f, c = 0.f;
+        for (int k = 0; k < nchunks; ++k) kahan_add(s, c, pp[(size_t)k * NP + src]);
+        power[(size_t)patch * N * N + j] = (s - c) * invF;
+    }
+    if (threadIdx.x < 4) {
+        float s = 0.f, c = 0.f;
+        for (int k = 0; k < nchunks; ++k) kahan_add(s, c, mpart[((size_t)patch * nchunks + k) * 4 + threadIdx.x]);
+        mean_spec[(size_t)patch * 4 + threadIdx.x] = (s - c) * invF;
+    }
+    if (threadIdx.x == 4) {
+        float s = 0.f, c = 0.f;
+        for (int k = 0; k < nchunks; ++k) kahan_add(s, c, mupart[(size_t)patch * nchunks + k]);
+        mu[patch] = (s - c) * invF;
+    }
+}
+
+template <int N, typename T>
+hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
+    const int total = a.patches * a.nchunks;
+    hipLaunchKernelGGL((k_ingest<N, T>), dim3(total), dim3(NT), 0, st, (const T *)a.frames, a.F, a.H,
+                       a.W, a.pitch, a.nx, a.stride, a.chunk_frames, a.nchunks, total, a.window,
+                       a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart, a.mupart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_acc_finalize<N>), dim3(a.patches), dim3(NT), 0, st, a.nchunks, 1.0f / a.F,
+                       a.ppart, a.mpart, a.mupart, a.power, a.mean_spec, a.mu);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_ingest(const IngestArgs &a, hipStream_t st) {
+    if (a.N == 128) return a.f32 ? launch_ingest_t<128, float>(a, st) : launch_ingest_t<128, uint16_t>(a, st);
+    return a.f32 ? launch_ingest_t<64, float>(a, st) : launch_ingest_t<64, uint16_t>(a, st);
+}
+
+}  // namespace nvsm

@@ -1,0 +1,440 @@
+// C-ABI of the speckle-masking library: context, validation, plan cache,
+// workspace layout and the launch sequence on the caller's stream.
+#include "nvsm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace nvsm;
+
+namespace {
+
+constexpr int CHUNK_FRAMES = 20;     // frames per ingest workgroup (even)
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct DevicePlan {
+    HostPlan h;
+    int nshell = 0, max_sw = 0;
+    std::vector<void *> bufs;
+    int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *items = nullptr, *slot = nullptr,
+        *out_idx = nullptr;
+    unsigned *code = nullptr;
+    float2 *twiddle = nullptr;
+    float *hann = nullptr, *filt = nullptr;
+    ~DevicePlan() {
+        for (void *p : bufs) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct nvsm_context {
+    int device = 0;
+    std::string err;
+    std::map<std::tuple<int, int, int>, std::unique_ptr<DevicePlan>> plans;
+};
+
+namespace {
+
+nvsm_status fail(nvsm_context *ctx, nvsm_status s, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+nvsm_status check_params(const nvsm_params *p, std::string *msg) {
+    if (!p) { *msg = "params is NULL"; return NVSM_ERR_INVALID_ARG; }
+    if (p->patch != 64 && p->patch != 128) { *msg = "patch must be 64 or 128"; return NVSM_ERR_INVALID_ARG; }
+    if (p->stride < 1 || p->stride > p->patch) { *msg = "stride must be in [1, patch]"; return NVSM_ERR_INVALID_ARG; }
+    if (p->u_cut < 2 || p->u_cut >= p->patch / 2) { *msg = "u_cut must be in [2, patch/2)"; return NVSM_ERR_INVALID_ARG; }
+    if (p->v_radius < 1 || p->v_radius > 16 || p->v_radius >= p->u_cut) {
+        *msg = "v_radius must be in [1, min(16, u_cut))";
+        return NVSM_ERR_INVALID_ARG;
+    }
+    if (p->window != 0 && p->window != 1) { *msg = "window must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
+    if (p->phase_method != 0) { *msg = "only the recursive phase solve (0) is available"; return NVSM_ERR_NOT_IMPLEMENTED; }
+    if (p->noise_bias != 0 && p->noise_bias != 1) { *msg = "noise_bias must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
+    if (p->filter != 0 && p->filter != 1) { *msg = "filter must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
+    if (!(p->stf_floor >= 0.0) || !std::isfinite(p->stf_floor)) { *msg = "stf_floor must be finite and >= 0"; return NVSM_ERR_INVALID_ARG; }
+    return NVSM_OK;
+}
+
+nvsm_status check_shape(const nvsm_params *p, int H, int W, int F, std::string *msg) {
+    if (F < 1) { *msg = "F must be >= 1"; return NVSM_ERR_SHAPE; }
+    if (H < p->patch || W < p->patch) { *msg = "frames smaller than a patch"; return NVSM_ERR_SHAPE; }
+    if ((int64_t)H * W > ((int64_t)1 << 31) - 1) { *msg = "frame too large"; return NVSM_ERR_SHAPE; }
+    return NVSM_OK;
+}
+
+struct Sizes {
+    Tiling t;
+    int64_t P = 0, nW = 0, S = 0;
+    int shells = 0, chunks = 0;
+    size_t spectra = 0, ppart = 0, mpart = 0, mupart = 0;      // accumulate scratch
+    size_t power = 0, mean = 0, mu = 0, bispec = 0, amp = 0, phasor = 0, patches = 0;
+};
+
+void sizes_of(const nvsm_params *p, int H, int W, int F, int64_t nW, int64_t S, int shells, Sizes *z) {
+    make_tiling(H, W, p->patch, p->stride, &z->t);
+    const int64_t N = p->patch;
+    z->P = (int64_t)z->t.ny * z->t.nx;
+    z->nW = nW;
+    z->S = S;
+    z->shells = shells;
+    z->chunks = (F + CHUNK_FRAMES - 1) / CHUNK_FRAMES;
+    z->spectra = align_up((size_t)z->P * F * (N / 2) * N * 8);
+    z->ppart = align_up((size_t)z->P * z->chunks * (N / 2 + 1) * N * 4);
+    z->mpart = align_up((size_t)z->P * z->chunks * 4 * 4);
+    z->mupart = align_up((size_t)z->P * z->chunks * 4);
+    z->power = align_up((size_t)z->P * N * N * 4);
+    z->mean = align_up((size_t)z->P * 4 * 4);
+    z->mu = align_up((size_t)z->P * 4);
+    z->bispec = align_up((size_t)z->P * S * 8);
+    z->amp = align_up((size_t)z->P * nW * 8);
+    z->phasor = align_up((size_t)z->P * nW * 16);
+    z->patches = align_up((size_t)z->P * N * N * 4);
+}
+
+size_t ws_acc(const Sizes &z) { return z.spectra + z.ppart + z.mpart + z.mupart; }
+size_t ws_rec(const Sizes &z) {
+    return z.power + z.mean + z.mu + z.bispec + z.amp + z.phasor + z.patches + ws_acc(z);
+}
+
+void count_sets(const nvsm_params *p, int64_t *nW, int64_t *S, int *shells) {
+    std::vector<int32_t> w, wv;
+    enumerate_W(p->u_cut, &w);
+    enumerate_S(p->u_cut, p->v_radius, &wv);
+    *nW = (int64_t)w.size() / 2;
+    *S = (int64_t)wv.size() / 4;
+    *shells = count_shells(w);
+}
+
+template <typename T>
+nvsm_status upload(DevicePlan *dp, const std::vector<T> &v, T **out, std::string *msg) {
+    void *d = nullptr;
+    size_t bytes = std::max<size_t>(v.size() * sizeof(T), 4);
+    if (hipMalloc(&d, bytes) != hipSuccess) { *msg = "hipMalloc failed for a table"; return NVSM_ERR_OOM; }
+    dp->bufs.push_back(d);
+    if (!v.empty() && hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        *msg = "table upload failed";
+        return NVSM_ERR_HIP;
+    }
+    *out = (T *)d;
+    return NVSM_OK;
+}
+
+nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) {
+    auto key = std::make_tuple(p->patch, p->u_cut, p->v_radius);
+    auto f = ctx->plans.find(key);
+    if (f != ctx->plans.end()) { *out = f->second.get(); return NVSM_OK; }
+    std::unique_ptr<DevicePlan> dp;
+    try {
+        dp.reset(new DevicePlan());
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, NVSM_ERR_OOM, "host allocation failed");
+    }
+    std::string msg;
+    try {
+        if (!build_plan(p->patch, p->u_cut, p->v_radius, &dp->h, &msg)) return fail(ctx, NVSM_ERR_INVALID_ARG, msg);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, NVSM_ERR_OOM, "host allocation failed while planning");
+    }
+    const HostPlan &h = dp->h;
+    dp->nshell = (int)h.shell_wb.size() - 1;
+    int max_per_shell = 0;
+    for (int s = 0; s < dp->nshell; ++s) max_per_shell = std::max(max_per_shell, h.shell_wb[s + 1] - h.shell_wb[s]);
+    for (size_t i = 0; i + 1 < h.woff.size(); ++i) dp->max_sw = std::max(dp->max_sw, h.woff[i + 1] - h.woff[i]);
+    if (max_per_shell > 16 || dp->max_sw > 512) return fail(ctx, NVSM_ERR_INVALID_ARG, "shell too large for the phase kernel");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NVSM_ERR_HIP, "hipSetDevice failed");
+    nvsm_status s;
+    std::vector<float2> tw(h.N);
+    for (int k = 0; k < h.N; ++k) tw[k] = make_float2(h.twiddle[2 * k], h.twiddle[2 * k + 1]);
+    if ((s = upload(dp.get(), h.W, &dp->W, &msg)) ||
+        (s = upload(dp.get(), h.woff, &dp->woff, &msg)) ||
+        (s = upload(dp.get(), h.shell_wb, &dp->shell_wb, &msg)) ||
+        (s = upload(dp.get(), h.phase_code, &dp->code, &msg)) ||
+        (s = upload(dp.get(), h.items, &dp->items, &msg)) ||
+        (s = upload(dp.get(), h.slot_v, &dp->slot, &msg)) ||
+        (s = upload(dp.get(), h.out_idx, &dp->out_idx, &msg)) ||
+        (s = upload(dp.get(), tw, &dp->twiddle, &msg)) ||
+        (s = upload(dp.get(), h.hann, &dp->hann, &msg)) ||
+        (s = upload(dp.get(), h.filt, &dp->filt, &msg)))
+        return fail(ctx, s, msg);
+    *out = dp.get();
+    ctx->plans[key] = std::move(dp);
+    return NVSM_OK;
+}
+
+hipError_t run_accumulate(DevicePlan *dp, const nvsm_params *p, const Sizes &z, const void *frames,
+                          nvsm_dtype dtype, int F, int H, int W, int64_t pitch, float *power,
+                          float *mean_spec, float *mu, float *bispec, char *ws, hipStream_t st) {
+    IngestArgs a;
+    a.N = p->patch;
+    a.f32 = dtype == NVSM_F32;
+    a.frames = frames;
+    a.F = F; a.H = H; a.W = W; a.pitch = pitch;
+    a.patches = (int)z.P; a.nx = z.t.nx; a.stride = p->stride;
+    a.chunk_frames = CHUNK_FRAMES; a.nchunks = z.chunks; a.window = p->window;
+    a.inv_wsum = (float)(1.0 / (p->window ? dp->h.hann_sum2 : (double)p->patch * p->patch));
+    a.twiddle = dp->twiddle; a.hann = dp->hann;
+    a.spectra = (float2 *)ws;
+    a.ppart = (float *)(ws + z.spectra);
+    a.mpart = (float *)(ws + z.spectra + z.ppart);
+    a.mupart = (float *)(ws + z.spectra + z.ppart + z.mpart);
+    a.power = power; a.mean_spec = mean_spec; a.mu = mu;
+    hipError_t e = launch_ingest(a, st);
+    if (e != hipSuccess || bispec == nullptr) return e;
+    BispecArgs b;
+    b.N = p->patch; b.spectra = a.spectra; b.F = F; b.patches = (int)z.P;
+    b.n_items = dp->h.n_items; b.items = dp->items; b.slot_v = dp->slot; b.out_idx = dp->out_idx;
+    b.bispec = (float2 *)bispec; b.s_count = z.S;
+    return launch_bispec(b, st);
+}
+
+hipError_t run_solve(DevicePlan *dp, const nvsm_params *p, int64_t P, const float *power,
+                     const float *mean_spec, const float *bispec, const double *stf, double *amp,
+                     double *phasor, hipStream_t st) {
+    SolveArgs a;
+    a.N = p->patch; a.patches = (int)P; a.nW = (int)(dp->h.W.size() / 2); a.nshell = dp->nshell;
+    a.max_sw = dp->max_sw; a.shell_wb = dp->shell_wb; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
+    a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;
+    a.stf = stf; a.floor = p->stf_floor; a.noise_bias = p->noise_bias; a.amp = amp;
+    a.phasor = (double2 *)phasor;
+    return launch_solve(a, st);
+}
+
+hipError_t run_synth(DevicePlan *dp, const nvsm_params *p, const Sizes &z, int H, int W,
+                     const double *amp, const double *phasor, const float *mu, float *patch_buf,
+                     float *out, hipStream_t st) {
+    SynthArgs a;
+    a.N = p->patch; a.patches = (int)z.P; a.nW = (int)z.nW; a.window = p->window; a.Wxy = dp->W;
+    a.amp = amp; a.phasor = (const double2 *)phasor; a.filt = p->filter ? dp->filt : nullptr;
+    a.mu = mu; a.hann = dp->hann; a.twiddle = dp->twiddle; a.patch_buf = patch_buf;
+    a.H = H; a.W = W; a.ny = z.t.ny; a.nx = z.t.nx; a.stride = p->stride; a.out = out;
+    return launch_synth(a, st);
+}
+
+nvsm_status hip_fail(nvsm_context *ctx, hipError_t e, const char *where) {
+    return fail(ctx, NVSM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+nvsm_status prepare_call(nvsm_context *ctx, const nvsm_params *p, int H, int W, int F,
+                         DevicePlan **dp, Sizes *z) {
+    std::string msg;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    if ((s = check_shape(p, H, W, F, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    if ((s = get_plan(ctx, p, dp)) != NVSM_OK) return s;
+    sizes_of(p, H, W, F, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, (*dp)->nshell, z);
+    return NVSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nvsm_status nvsm_create(int hip_device, nvsm_context **out) {
+    if (!out) return NVSM_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return NVSM_ERR_HIP;
+    if (hip_device < 0 || hip_device >= n) return NVSM_ERR_INVALID_ARG;
+    nvsm_context *c = new (std::nothrow) nvsm_context();
+    if (!c) return NVSM_ERR_OOM;
+    c->device = hip_device;
+    *out = c;
+    return NVSM_OK;
+}
+
+void nvsm_destroy(nvsm_context *ctx) { delete ctx; }
+
+const char *nvsm_status_string(nvsm_status s) {
+    switch (s) {
+        case NVSM_OK: return "ok";
+        case NVSM_ERR_INVALID_ARG: return "invalid argument";
+        case NVSM_ERR_SHAPE: return "shape mismatch";
+        case NVSM_ERR_WORKSPACE: return "workspace too small";
+        case NVSM_ERR_OOM: return "out of memory";
+        case NVSM_ERR_HIP: return "HIP error";
+        case NVSM_ERR_NOT_IMPLEMENTED: return "not implemented";
+    }
+    return "unknown status";
+}
+
+const char *nvsm_last_error(const nvsm_context *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+nvsm_status nvsm_default_params(int32_t patch, nvsm_params *out) {
+    if (!out || (patch != 64 && patch != 128)) return NVSM_ERR_INVALID_ARG;
+    out->patch = patch;
+    out->stride = patch / 2;
+    out->u_cut = patch / 2 - 1;
+    out->v_radius = 10;
+    out->window = 1;
+    out->phase_method = 0;
+    out->noise_bias = 0;
+    out->filter = 0;
+    out->stf_floor = 1e-6;
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t F, nvsm_plan_info *out) {
+    std::string msg;
+    if (!out) return NVSM_ERR_INVALID_ARG;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return s;
+    if ((s = check_shape(p, H, W, F, &msg)) != NVSM_OK) return s;
+    int64_t nW, S;
+    int shells;
+    try {
+        count_sets(p, &nW, &S, &shells);
+    } catch (const std::bad_alloc &) {
+        return NVSM_ERR_OOM;
+    }
+    Sizes z;
+    sizes_of(p, H, W, F, nW, S, shells, &z);
+    out->patches_y = z.t.ny;
+    out->patches_x = z.t.nx;
+    out->patches = z.P;
+    out->w_count = nW;
+    out->s_count = S;
+    out->shells = shells;
+    out->frame_chunks = z.chunks;
+    out->ws_accumulate = ws_acc(z);
+    out->ws_solve = 0;
+    out->ws_synthesize = z.patches;
+    out->ws_reconstruct = ws_rec(z);
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_w_index(const nvsm_params *p, int32_t *w, int64_t w_count) {
+    std::string msg;
+    if (!w) return NVSM_ERR_INVALID_ARG;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return s;
+    std::vector<int32_t> v;
+    enumerate_W(p->u_cut, &v);
+    if ((int64_t)v.size() / 2 != w_count) return NVSM_ERR_SHAPE;
+    std::memcpy(w, v.data(), v.size() * sizeof(int32_t));
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_bispectrum_index(const nvsm_params *p, int32_t *wv, int64_t s_count) {
+    std::string msg;
+    if (!wv) return NVSM_ERR_INVALID_ARG;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return s;
+    std::vector<int32_t> v;
+    enumerate_S(p->u_cut, p->v_radius, &v);
+    if ((int64_t)v.size() / 4 != s_count) return NVSM_ERR_SHAPE;
+    std::memcpy(wv, v.data(), v.size() * sizeof(int32_t));
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_prepare(nvsm_context *ctx, const nvsm_params *p) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    std::string msg;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    DevicePlan *dp;
+    return get_plan(ctx, p, &dp);
+}
+
+nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
+                            int32_t F, int32_t H, int32_t W, int64_t row_pitch, float *power,
+                            float *mean_spec, float *mu, float *bispec, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!frames || !power || !mean_spec || !mu) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    if (row_pitch < W) return fail(ctx, NVSM_ERR_SHAPE, "row_pitch < W");
+    DevicePlan *dp;
+    Sizes z;
+    nvsm_status s = prepare_call(ctx, p, H, W, F, &dp, &z);
+    if (s != NVSM_OK) return s;
+    if (!workspace || workspace_bytes < ws_acc(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for accumulate");
+    hipError_t e = run_accumulate(dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean_spec, mu, bispec,
+                                  (char *)workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_solve(nvsm_context *ctx, const nvsm_params *p, int64_t patches, const float *power,
+                       const float *mean_spec, const float *bispec, const double *stf, double *amp,
+                       double *phasor, void *workspace, size_t workspace_bytes, void *stream) {
+    (void)workspace;
+    (void)workspace_bytes;
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    std::string msg;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    if (patches < 0 || patches > (1 << 24)) return fail(ctx, NVSM_ERR_SHAPE, "bad patch count");
+    if (!power || !mean_spec || !bispec || !stf || !amp || !phasor) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    DevicePlan *dp;
+    if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;
+    hipError_t e = run_solve(dp, p, patches, power, mean_spec, bispec, stf, amp, phasor, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_synthesize(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, const double *amp,
+                            const double *phasor, const float *mu, float *patches_out, float *out,
+                            void *workspace, size_t workspace_bytes, void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!amp || !phasor || !mu || !out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    DevicePlan *dp;
+    Sizes z;
+    nvsm_status s = prepare_call(ctx, p, H, W, 1, &dp, &z);
+    if (s != NVSM_OK) return s;
+    float *pb = patches_out;
+    if (!pb) {
+        if (!workspace || workspace_bytes < z.patches) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for synthesize");
+        pb = (float *)workspace;
+    }
+    hipError_t e = run_synth(dp, p, z, H, W, amp, phasor, mu, pb, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
+                             int32_t F, int32_t H, int32_t W, int64_t row_pitch, const double *stf, float *out,
+                             void *workspace, size_t workspace_bytes, void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!frames || !stf || !out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    if (row_pitch < W) return fail(ctx, NVSM_ERR_SHAPE, "row_pitch < W");
+    DevicePlan *dp;
+    Sizes z;
+    nvsm_status s = prepare_call(ctx, p, H, W, F, &dp, &z);
+    if (s != NVSM_OK) return s;
+    if (!workspace || workspace_bytes < ws_rec(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for reconstruct");
+    char *w = (char *)workspace;
+    float *power = (float *)w; w += z.power;
+    float *mean = (float *)w; w += z.mean;
+    float *mu = (float *)w; w += z.mu;
+    float *bis = (float *)w; w += z.bispec;
+    double *amp = (double *)w; w += z.amp;
+    double *ph = (double *)w; w += z.phasor;
+    float *pat = (float *)w; w += z.patches;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = run_accumulate(dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean, mu, bis, w, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
+    e = run_solve(dp, p, z.P, power, mean, bis, stf, amp, ph, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
+    e = run_synth(dp, p, z, H, W, amp, ph, mu, pat, out, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
+    return NVSM_OK;
+}
+
+}  // extern "C"

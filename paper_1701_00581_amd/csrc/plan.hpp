@@ -1,0 +1,67 @@
+// Host-side planning: index sets, the shell schedule of the phase
+// recursion and the work decomposition of the bispectrum kernel.
+// Pure C++ (no HIP), so it can be unit-tested on any host.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace nvsm {
+
+// Bispectrum kernel geometry: a wave's 64 lanes hold an 8x8 block of w, its
+// BS_SLOTS slots hold v values shared by the whole wave.
+constexpr int BS_LANES = 64;
+constexpr int BS_BLOCK = 8;
+constexpr int BS_SLOTS = 32;
+constexpr int BS_WAVES = 4;            // waves per workgroup
+constexpr int BS_MAX_REGION = 1024;    // staged points per frame per workgroup
+constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
+
+struct Tiling {
+    int ny = 0, nx = 0;
+    std::vector<int32_t> ys, xs;
+};
+
+// Rows k start at min(k*s, L-N), k < ceil((L-N)/s)+1 (last tile flush).
+bool make_tiling(int H, int W, int N, int s, Tiling *t);
+
+struct HostPlan {
+    int N = 0, uc = 0, R = 0;
+    // W in storage order as (wx, wy) pairs, and the S offset of each w.
+    std::vector<int32_t> W;
+    std::vector<int32_t> woff;          // |W|+1
+    std::vector<int32_t> shell_wb;      // shells+1: W range of each shell
+    // Per S entry: lookup codes of (w - v) and v in the phasor table
+    // (bits 0..14 index into W, bit 15 set = use the conjugate).
+    std::vector<uint32_t> phase_code;
+    int64_t s_count = 0;
+    // Bispectrum work items.  items[g*12 + 0..11] = block x0, block y0,
+    // region x0, region y0, region width, region height, region points, 0,
+    // then the slot count of each of the BS_WAVES waves.
+    int n_items = 0;
+    std::vector<int32_t> items;
+    // slot[((g*BS_WAVES + wave)*BS_SLOTS + k)*2 + 0] = vy * region_width + vx
+    // (offset of v in the staged region), [..+1] = offset of I(v) in a
+    // frame's stored half spectrum, bit 31 set when I(v) = conj of it.
+    std::vector<int32_t> slot_v;
+    // out_idx[((g*BS_WAVES + wave)*BS_SLOTS + k)*64 + lane] = S index or -1
+    std::vector<int32_t> out_idx;
+    int64_t computed_terms = 0;         // wave slots x 64 lanes actually run
+    // Constant tables.
+    std::vector<float> twiddle;         // 2N: exp(-2 pi i k / N), k < N
+    std::vector<float> hann;            // N: periodic Hann taper
+    std::vector<float> filt;            // |W|: diffraction OTF at |w|/(N/2)
+    double hann_sum2 = 0;               // sum of the 2-D taper
+};
+
+// Builds everything above; returns false with *err set on bad sizes.
+bool build_plan(int N, int uc, int R, HostPlan *out, std::string *err);
+
+// S in storage order, 4 ints per entry (wx, wy, vx, vy).
+void enumerate_S(int uc, int R, std::vector<int32_t> *wv);
+// W in storage order, 2 ints per entry.
+void enumerate_W(int uc, std::vector<int32_t> *w);
+int count_shells(const std::vector<int32_t> &W);
+
+}  // namespace nvsm

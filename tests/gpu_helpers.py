@@ -1,0 +1,76 @@
+"""Shared helpers of the GPU parity tests: inputs, metrics, tolerances."""
+import functools
+import sys
+
+import numpy as np
+
+import oracle
+import synth
+
+# Tolerances.  Bispectrum: 1e-4 relative, both normwise per patch and
+# against A(w,v) = <|I(w-v)||I(v)||I(w)|> per sample (a near-cancelling mean
+# makes the plain elementwise ratio ill-conditioned).  Phase: 1e-3 rad RMS of
+# the wrapped difference.  Power spectrum: 1e-5 normwise (FP32 FFT +
+# compensated sums are ~1e-6).  Mosaic: 1e-3 of the interior RMS contrast.
+BISPEC_TOL = 1e-4
+PHASE_RMS_TOL = 1e-3
+POWER_TOL = 1e-5
+MOSAIC_TOL = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=4)
+def burst(name, F=None, H=None, W=None):
+    cfg = synth.CONFIGS[name]
+    fr = synth.make_burst(cfg, frames=F)
+    if H is not None or W is not None:
+        fr = np.ascontiguousarray(fr[:, :H, :W])
+    return fr
+
+
+@functools.lru_cache(maxsize=4)
+def stf(name, screens=200):
+    return synth.stf_table(synth.CONFIGS[name], screens=screens)
+
+
+def to_device(fr):
+    import torch
+    if fr.dtype == np.uint16:
+        return torch.from_numpy(fr.view(np.int16)).cuda()
+    return torch.from_numpy(np.ascontiguousarray(fr)).cuda()
+
+
+def oparams(p):
+    return oracle.Params(patch=p.patch, stride=p.stride, u_cut=p.u_cut, v_radius=p.v_radius,
+                         window=p.window, noise_bias=p.noise_bias, filter=p.filter, stf_floor=p.stf_floor)
+
+
+def cube(frames, p, k):
+    F, H, W = frames.shape
+    ys, xs = oracle.tiling(H, W, p.patch, p.stride)
+    i, j = divmod(k, len(xs))
+    return frames[:, ys[i]:ys[i] + p.patch, xs[j]:xs[j] + p.patch].astype(np.float64)
+
+
+def abs_bispectrum(I, S):
+    """A(w,v) = <|I(w-v)| |I(v)| |I(w)|>, the scale of each sample."""
+    return oracle.bispectrum(np.abs(I).astype(np.complex128), S).real
+
+
+def bispec_errors(bg, bo, A):
+    d = np.abs(bg - bo)
+    return float(np.linalg.norm(d) / np.linalg.norm(bo)), float(np.max(d / np.maximum(A, 1e-300)))
+
+
+def phase_rms(eg, eo):
+    d = np.angle(eg * np.conj(eo))
+    return float(np.sqrt(np.mean(d * d))), float(np.max(np.abs(d)))
+
+
+def as_complex(t):
+    a = t.detach().cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1]

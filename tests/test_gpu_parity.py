@@ -1,0 +1,235 @@
+"""GPU path versus the FP64 oracle, element by element, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import (BISPEC_TOL, MOSAIC_TOL, PHASE_RMS_TOL, POWER_TOL, abs_bispectrum, as_complex,
+                         bispec_errors, burst, cube, oparams, phase_rms, say, stf, to_device)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1701_00581_amd as nv
+    nv.lib()  # the HIP library must be there: no fallback
+    return torch
+
+
+def _session(p, H, W, F):
+    import paper_1701_00581_amd as nv
+    return nv.Session(p, H, W, F)
+
+
+def _check_accumulate(s, frames, p, patches, Sset, label):
+    """Power, mean spectrum, mean level and bispectrum of chosen patches."""
+    op = oparams(p)
+    P = s.power.cpu().numpy()
+    M = s.mean_spec.cpu().numpy()
+    mu = s.mu.cpu().numpy()
+    B = as_complex(s.bispec)
+    for k in patches:
+        c = cube(frames, p, k)
+        I, muf = oracle.patch_spectra(c, op.window)
+        Po = np.mean(np.abs(I) ** 2, axis=0)
+        Mo = np.mean(I, axis=0)
+        perr = np.linalg.norm(P[k] - Po) / np.linalg.norm(Po)
+        m10 = abs(complex(M[k, 0, 0], M[k, 0, 1]) - Mo[0, 1]) / abs(Mo[0, 1])
+        m01 = abs(complex(M[k, 1, 0], M[k, 1, 1]) - Mo[1, 0]) / abs(Mo[1, 0])
+        muerr = abs(mu[k] - muf.mean()) / abs(muf.mean())
+        Bo = oracle.bispectrum(I, Sset)
+        A = abs_bispectrum(I, Sset)
+        nerr, aerr = bispec_errors(B[k], Bo, A)
+        say(f"[{label}] patch {k}: P {perr:.2e} M10 {m10:.2e} M01 {m01:.2e} mu {muerr:.2e} "
+            f"B norm {nerr:.2e} B/A max {aerr:.2e}")
+        assert perr <= POWER_TOL
+        assert m10 <= 1e-5 and m01 <= 1e-5 and muerr <= 1e-6
+        assert nerr <= BISPEC_TOL and aerr <= BISPEC_TOL
+
+
+def test_single64_whole_path(torch_cuda):
+    """64x64 subimage, 100 float32 frames, no taper, R = 8."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case single64: accumulate/solve/synthesize, F=100, N=64, R=8")
+    fr = burst("single64")
+    p = nv.default_params(64, v_radius=8, window=0)
+    s = _session(p, 64, 64, 100)
+    d = to_device(fr)
+    s.accumulate(d)
+    torch.cuda.synchronize()
+    Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+    _check_accumulate(s, fr, p, [0], S, "single64")
+    # modulus and phase from the GPU accumulation vs the oracle end to end
+    st = stf("single64")
+    st_d = torch.from_numpy(st).cuda()
+    s.solve(st_d)
+    s.synthesize()
+    torch.cuda.synchronize()
+    ref = oracle.reconstruct(fr, oparams(p), st)
+    t = ref["tiles"][(0, 0)]
+    amp = s.amp.cpu().numpy()[0]
+    ph = as_complex(s.phasor)[0]
+    aerr = np.max(np.abs(amp - t["amp"]) / np.maximum(t["amp"], 1e-30 + np.max(t["amp"]) * 1e-12))
+    rms, mx = phase_rms(ph, t["phasor"])
+    say(f"[single64] amp rel max {aerr:.2e} phase rms {rms:.2e} max {mx:.2e}")
+    assert aerr <= 1e-4
+    assert rms <= PHASE_RMS_TOL
+    img = s.image.cpu().numpy()
+    o = ref["image"]
+    merr = np.linalg.norm(img - o) / np.linalg.norm(o - o.mean())
+    say(f"[single64] mosaic {merr:.2e}")
+    assert merr <= MOSAIC_TOL
+
+
+def test_ragged_crop_accumulate(torch_cuda):
+    """250x300 crop (clamped last row and column), 37 frames (odd, two frame
+    groups with a ragged tail), N = 128, R = 10, Hann taper."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case crop250x300 F=37: accumulate")
+    fr = burst("burst1024", F=37, H=250, W=300)
+    p = nv.default_params(128, v_radius=10)
+    s = _session(p, 250, 300, 37)
+    assert s.info.patches == 12
+    s.accumulate(to_device(fr))
+    torch.cuda.synchronize()
+    Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+    _check_accumulate(s, fr, p, list(range(12)), S, "crop")
+
+
+def test_solve_on_identical_inputs(torch_cuda):
+    """The FP64 solve alone: both sides get the same FP32-rounded power,
+    mean spectrum and bispectrum (computed by the oracle)."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case solve-only: oracle inputs rounded to FP32, N=128, R=10, noise bias on")
+    fr = burst("burst1024", F=37, H=250, W=300)
+    p = nv.default_params(128, v_radius=10, noise_bias=1)
+    op = oparams(p)
+    Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+    ks = [0, 5, 11]
+    Ps, Ms, Bs = [], [], []
+    for k in ks:
+        acc = oracle.accumulate_patch(cube(fr, p, k), op, S)
+        Ps.append(acc["P"].astype(np.float32))
+        Ms.append(np.array([[acc["M10"].real, acc["M10"].imag], [acc["M01"].real, acc["M01"].imag]], np.float32))
+        Bs.append(np.stack([acc["B"].real, acc["B"].imag], -1).astype(np.float32))
+    st = stf("burst1024", screens=100)
+    ctx = nv.nvsm_create(0)
+    try:
+        n = len(ks)
+        amp = torch.empty(n, len(Wset), dtype=torch.float64, device="cuda")
+        ph = torch.empty(n, len(Wset), 2, dtype=torch.float64, device="cuda")
+        nv.nvsm_solve(ctx, p, n, torch.from_numpy(np.stack(Ps)).cuda(), torch.from_numpy(np.stack(Ms)).cuda(),
+                      torch.from_numpy(np.stack(Bs)).cuda(), torch.from_numpy(st).cuda(), amp, ph)
+        torch.cuda.synchronize()
+    finally:
+        nv.nvsm_destroy(ctx)
+    amp = amp.cpu().numpy()
+    ph = as_complex(ph)
+    for i in range(len(ks)):
+        P64 = Ps[i].astype(np.float64)
+        nb = oracle.noise_bias(P64)
+        ao = oracle.amplitude(P64, st, Wset, nb, p.stf_floor)
+        B64 = Bs[i][..., 0].astype(np.float64) + 1j * Bs[i][..., 1].astype(np.float64)
+        eo = oracle.phase_recursion(B64, complex(*Ms[i][0].astype(np.float64)),
+                                    complex(*Ms[i][1].astype(np.float64)), Wset, S, woff, p.patch)
+        aerr = np.max(np.abs(amp[i] - ao)) / np.max(ao)
+        rms, mx = phase_rms(ph[i], eo)
+        say(f"[solve] patch {ks[i]}: amp {aerr:.2e} phase rms {rms:.2e} max {mx:.2e}")
+        assert aerr <= 1e-12
+        assert rms <= 1e-9
+
+
+def test_synthesize_on_identical_inputs(torch_cuda):
+    """Inverse transforms and mosaic from the same FP64 modulus and phase."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case synthesize-only: crop 250x300, N=128, filter on")
+    H, W = 250, 300
+    p = nv.default_params(128, v_radius=10, filter=1)
+    op = oparams(p)
+    ys, xs = oracle.tiling(H, W, 128, 64)
+    Wset = oracle.frequency_half_disk(p.u_cut)
+    rng = np.random.default_rng(7)
+    n = len(ys) * len(xs)
+    amp = rng.random((n, len(Wset))) * 1e4 / (1.0 + np.hypot(Wset[:, 0], Wset[:, 1]))[None]
+    phase = rng.uniform(-np.pi, np.pi, (n, len(Wset)))
+    ph = np.exp(1j * phase)
+    mu = rng.uniform(1500, 2500, n).astype(np.float32)
+    filt = oracle.diffraction_filter(Wset, 128)
+    pats = np.stack([oracle.synthesize_patch(amp[k], ph[k], Wset, 128, float(mu[k]), 1, filt) for k in range(n)])
+    ref = oracle.mosaic(pats.reshape(len(ys), len(xs), 128, 128), ys, xs, H, W, 1)
+    s = _session(p, H, W, 1)
+    s.synthesize(torch.from_numpy(amp).cuda(), torch.from_numpy(np.stack([ph.real, ph.imag], -1)).cuda(),
+                 torch.from_numpy(mu).cuda())
+    torch.cuda.synchronize()
+    pg = s.patches.cpu().numpy()
+    perr = np.linalg.norm(pg - pats) / np.linalg.norm(pats - pats.mean())
+    img = s.image.cpu().numpy()
+    inner = (slice(64, H - 64), slice(64, W - 64))
+    merr = np.linalg.norm(img[inner] - ref[inner]) / np.linalg.norm(ref[inner] - ref[inner].mean())
+    full = np.max(np.abs(img - ref)) / np.max(np.abs(ref))
+    say(f"[synth] patches {perr:.2e} mosaic interior {merr:.2e} full max {full:.2e}")
+    assert perr <= 1e-5 and merr <= 1e-5 and full <= 1e-5
+    assert np.all(img[0, :] == 0) and np.all(img[:, 0] == 0)
+
+
+def test_reconstruct_crop_end_to_end_and_deterministic(torch_cuda):
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case reconstruct crop 250x300 F=37, N=128, R=10, noise bias + filter")
+    fr = burst("burst1024", F=37, H=250, W=300)
+    p = nv.default_params(128, v_radius=10, noise_bias=1, filter=1)
+    st = stf("burst1024", screens=100)
+    s = _session(p, 250, 300, 37)
+    d = to_device(fr)
+    std = torch.from_numpy(st).cuda()
+    a = s.reconstruct(d, std).clone()
+    b = s.reconstruct(d, std).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b), "two runs differ"
+    ref = oracle.reconstruct(fr, oparams(p), st)["image"]
+    img = a.cpu().numpy()
+    inner = (slice(64, 250 - 64), slice(64, 300 - 64))
+    merr = np.linalg.norm(img[inner] - ref[inner]) / np.linalg.norm(ref[inner] - ref[inner].mean())
+    say(f"[reconstruct] mosaic interior {merr:.2e}")
+    assert merr <= MOSAIC_TOL
+
+
+def test_error_paths(torch_cuda):
+    import ctypes
+    import paper_1701_00581_amd as nv
+    from paper_1701_00581_amd import _lib
+    torch = torch_cuda
+    say("case error paths")
+    p = nv.default_params(128)
+    ctx = nv.nvsm_create(0)
+    L = nv.lib()
+    try:
+        fr = torch.zeros(3, 256, 256, dtype=torch.int16, device="cuda")
+        info = nv.nvsm_plan(p, 256, 256, 3)
+        out = torch.zeros(256, 256, device="cuda")
+        st = torch.ones(128, 128, dtype=torch.float64, device="cuda")
+        ws = torch.empty(info.ws_reconstruct - 1, dtype=torch.uint8, device="cuda")
+        args = lambda w, n: (ctx, ctypes.byref(p), fr.data_ptr(), 0, 3, 256, 256, 256, st.data_ptr(),  # noqa: E731
+                             out.data_ptr(), w, n, None)
+        assert L.nvsm_reconstruct(*args(ws.data_ptr(), ws.numel())) == _lib.NVSM_ERR_WORKSPACE
+        assert "workspace" in nv.nvsm_last_error(ctx)
+        assert L.nvsm_reconstruct(*args(None, 0)) == _lib.NVSM_ERR_WORKSPACE
+        a = list(args(ws.data_ptr(), ws.numel()))
+        a[8] = None
+        assert L.nvsm_reconstruct(*a) == _lib.NVSM_ERR_INVALID_ARG
+        a = list(args(ws.data_ptr(), ws.numel()))
+        a[7] = 100   # pitch < W
+        assert L.nvsm_reconstruct(*a) == _lib.NVSM_ERR_SHAPE
+        a = list(args(ws.data_ptr(), ws.numel()))
+        a[3] = 7     # bad dtype
+        assert L.nvsm_reconstruct(*a) == _lib.NVSM_ERR_INVALID_ARG
+        assert torch.count_nonzero(out).item() == 0
+        torch.cuda.synchronize()
+    finally:
+        nv.nvsm_destroy(ctx)

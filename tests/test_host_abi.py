@@ -1,0 +1,107 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every entry point the header declares, and
+its host-only calls (parameters, planning, index sets, validation) must
+agree with the oracle's independent enumeration and the paper's tiling.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1701_00581_amd as nv
+from paper_1701_00581_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "nvsm.h")).read()
+    return sorted(set(re.findall(r"\b(nvsm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = nv.lib()
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(nv.EXPORTS)
+
+
+def test_default_params():
+    p = nv.default_params(128)
+    assert (p.patch, p.stride, p.u_cut, p.v_radius, p.window) == (128, 64, 63, 10, 1)
+    with pytest.raises(nv.NvsmError):
+        nv.default_params(96)
+
+
+@pytest.mark.parametrize("H,W,N,R,ny,nx", [
+    (1024, 1024, 128, 10, 15, 15),
+    (2160, 2560, 128, 12, 33, 39),
+    (64, 64, 64, 8, 1, 1),
+    (250, 300, 128, 10, 3, 4),
+])
+def test_plan_counts_match_oracle(H, W, N, R, ny, nx):
+    p = nv.default_params(N, v_radius=R)
+    info = nv.nvsm_plan(p, H, W, 100)
+    assert (info.patches_y, info.patches_x, info.patches) == (ny, nx, ny * nx)
+    ys, xs = oracle.tiling(H, W, N, N // 2)
+    assert (len(ys), len(xs)) == (ny, nx)
+    Wset, S, woff = oracle.bispectrum_set(N // 2 - 1, R)
+    assert info.w_count == len(Wset) and info.s_count == len(S)
+    assert info.shells == len(set((Wset ** 2).sum(1).tolist()))
+    assert info.ws_reconstruct > info.ws_accumulate > 0
+
+
+@pytest.mark.parametrize("N,R", [(64, 8), (128, 10), (128, 12), (64, 3)])
+def test_index_sets_equal_oracle(N, R):
+    p = nv.default_params(N, v_radius=R)
+    Wset, S, woff = oracle.bispectrum_set(N // 2 - 1, R)
+    np.testing.assert_array_equal(nv.nvsm_w_index(p), Wset)
+    np.testing.assert_array_equal(nv.nvsm_bispectrum_index(p), S)
+
+
+def test_invalid_parameters_are_rejected_before_anything_runs():
+    L = nv.lib()
+    info = nv.PlanInfo()
+    for field, bad in [("patch", 96), ("stride", 0), ("stride", 200), ("u_cut", 64), ("v_radius", 0),
+                       ("v_radius", 63), ("v_radius", 17), ("window", 2), ("noise_bias", 3), ("filter", -1),
+                       ("stf_floor", float("nan"))]:
+        p = nv.default_params(128)
+        setattr(p, field, bad)
+        assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG, field
+    p = nv.default_params(128)
+    p.phase_method = 1
+    assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_NOT_IMPLEMENTED
+    p = nv.default_params(128)
+    assert L.nvsm_plan(ctypes.byref(p), 100, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
+    assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 0, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
+    assert L.nvsm_plan(None, 1024, 1024, 10, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG
+    # wrong buffer length for the index export
+    buf = np.zeros(8, np.int32)
+    assert L.nvsm_bispectrum_index(ctypes.byref(p), buf.ctypes.data, 2) == _lib.NVSM_ERR_SHAPE
+    # compute calls reject a null context
+    assert L.nvsm_reconstruct(None, ctypes.byref(p), None, 0, 1, 128, 128, 128, None, None, None, 0,
+                              None) == _lib.NVSM_ERR_INVALID_ARG
+    assert L.nvsm_accumulate(None, ctypes.byref(p), None, 0, 1, 128, 128, 128, None, None, None, None,
+                             None, 0, None) == _lib.NVSM_ERR_INVALID_ARG
+
+
+def test_status_strings():
+    for s in range(-6, 1):
+        assert nv.status_string(s)
+    assert nv.status_string(-3) == "workspace too small"
+
+
+def test_workspace_sizes_scale_with_the_burst():
+    p = nv.default_params(128, v_radius=12)
+    a = nv.nvsm_plan(p, 2160, 2560, 100)
+    b = nv.nvsm_plan(p, 2160, 2560, 50)
+    assert a.ws_accumulate > b.ws_accumulate
+    # spectra (P F N/2 N complex64) dominate the accumulation workspace
+    assert a.ws_accumulate >= 1287 * 100 * 64 * 128 * 8
+    assert a.ws_reconstruct >= a.ws_accumulate + 1287 * a.s_count * 8
