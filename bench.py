@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of the speckle-masking reconstruction on one MI355X.
+
+One step = one whole burst through the library: ingest (tile cut, taper,
+FFT, power/mean sums), bispectrum accumulation, FP64 modulus and phase
+solve, inverse transforms and mosaic -- nvsm_reconstruct, frames already in
+HBM, image written to HBM.  Default workload: one 2560x2160 burst of 100
+12-bit frames, 128x128 patches at 50 % overlap (39x33 patches), |v| <= 12.
+
+Prints one JSON line (rank 0).  Stage times come from HIP events the
+library records on the launch stream during the timed steps.  The CPU
+baseline is the FP64 oracle on a sample of patches, in a process pool over
+the host cores, extrapolated to the whole burst.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "reconstructed bursts/s (2560×2160×100 frames); bispectrum GB/s; p99 latency"
+FLOP_PER_TERM = 14          # I(w-v) I(v): 6, times conj I(w): 6, accumulate: 2
+BYTES_PER_TERM = 8          # one complex64 bispectrum term per frame
+# Peaks.  The bispectrum kernel is bound by FP32 vector FMA issue; packed
+# FP32 instructions are disabled in this build, so its ceiling is
+# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s (the
+# published 157.3 TFLOP/s counts packed FP32).
+PEAK_FP32_UNPACKED = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_FP32_PACKED = 157.3
+HBM_PEAK_GBPS = 8000.0
+
+WORKLOADS = {
+    "burst2560": dict(v_radius=12, patch=128, noise_bias=1, filter=1),
+    "burst1024": dict(v_radius=10, patch=128, noise_bias=1, filter=1),
+    "single64": dict(v_radius=8, patch=64, window=0, noise_bias=1, filter=1),
+}
+
+_FR = None
+_STF = None
+_OP = None
+
+
+def _oracle_worker(tiles):
+    import oracle
+    t = time.perf_counter()
+    oracle.reconstruct(_FR, _OP, _STF, patch_list=tiles)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(frames, stf, op, n_patches_total, ny, nx, workers):
+    """FP64 oracle on a stratified sample of tiles, one pool worker per core."""
+    global _FR, _STF, _OP
+    _FR, _STF, _OP = frames, stf, op
+    per = 2
+    n = workers * per
+    idx = np.linspace(0, n_patches_total - 1, n).round().astype(int)
+    tiles = [(int(k // nx), int(k % nx)) for k in idx]
+    chunks = [tiles[i::workers] for i in range(workers)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        cpu_s = pool.map(_oracle_worker, chunks)
+    wall = time.perf_counter() - t0
+    per_burst_s = wall * n_patches_total / n
+    return dict(value=1.0 / per_burst_s, unit="bursts/s", cores=workers, kind="oracle",
+                sample=f"{n} of {n_patches_total} patches (stratified, full frame count), FP64 NumPy oracle, "
+                       f"{workers} worker processes, {wall:.1f} s wall / {sum(cpu_s):.1f} s CPU, "
+                       f"extrapolated x{n_patches_total / n:.1f} to the whole burst (mosaic excluded)",
+                wall_s=wall)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="burst2560", choices=sorted(WORKLOADS))
+    ap.add_argument("--frames", type=int, default=None, help="override the frame count")
+    ap.add_argument("--stf-screens", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs the path on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import oracle
+    import synth
+    cfg = synth.CONFIGS[args.workload]
+    t = time.perf_counter()
+    frames = synth.make_burst(cfg, frames=args.frames)
+    stf = synth.stf_table(cfg, screens=args.stf_screens)
+    F, H, W = frames.shape
+    gen_s = time.perf_counter() - t
+    print(f"[bench] generated {args.workload} {F}x{H}x{W} {frames.dtype} in {gen_s:.1f} s", file=sys.stderr,
+          flush=True)
+    wl = WORKLOADS[args.workload]
+
+    # CPU baseline first, before the GPU runtime exists in this process
+    cpu = None
+    ys, xs = oracle.tiling(H, W, wl["patch"], wl["patch"] // 2)
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
+        op = oracle.Params(patch=wl["patch"], v_radius=wl["v_radius"], window=wl.get("window", 1),
+                           noise_bias=wl["noise_bias"], filter=wl["filter"])
+        cpu = cpu_baseline(frames, stf, op, len(ys) * len(xs), len(ys), len(xs), workers)
+        print(f"[bench] cpu baseline {cpu['value']:.3e} bursts/s ({cpu['sample']})", file=sys.stderr, flush=True)
+
+    import torch
+    import paper_1701_00581_amd as nv
+    dev = torch.device("cuda", 0)
+    p = nv.default_params(wl["patch"], v_radius=wl["v_radius"], window=wl.get("window", 1),
+                          noise_bias=wl["noise_bias"], filter=wl["filter"])
+    s = nv.Session(p, H, W, F)
+    # host -> device upload of the burst (pinned), reported beside the value
+    raw = frames.view(np.int16) if frames.dtype == np.uint16 else frames
+    pinned = torch.from_numpy(raw).pin_memory()
+    d_frames = torch.empty(pinned.shape, dtype=pinned.dtype, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h2d = []
+    for _ in range(3):
+        e0.record()
+        d_frames.copy_(pinned, non_blocking=True)
+        e1.record()
+        torch.cuda.synchronize()
+        h2d.append(e0.elapsed_time(e1))
+    h2d_ms = float(np.median(h2d))
+    d_stf = torch.from_numpy(stf).to(dev)
+
+    for _ in range(args.warmup):
+        s.reconstruct(d_frames, d_stf)
+    torch.cuda.synchronize()
+    if not torch.isfinite(s.image).all():
+        raise RuntimeError("non-finite output")
+
+    nv.nvsm_profile_read(s.ctx)          # drop anything recorded so far
+    nv.nvsm_profile_enable(s.ctx, True)
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        s.reconstruct(d_frames, d_stf)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nv.nvsm_profile_enable(s.ctx, False)
+    stages = nv.nvsm_profile_read(s.ctx)
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+
+    info = s.info
+    P, S = info.patches, info.s_count
+    terms = P * S * F
+    bis_ms = stages["bispectrum"][0] / max(1, stages["bispectrum"][1])
+    achieved = terms * FLOP_PER_TERM / (bis_ms * 1e-3) / 1e12
+    stage_ms = {k: v[0] / max(1, v[1]) for k, v in stages.items()}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "bursts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {W}x{H} x {F} {'uint16 12-bit' if frames.dtype == np.uint16 else 'float32'} "
+                        f"frames, {p.patch}x{p.patch} patches at stride {p.stride} ({info.patches_x}x{info.patches_y}), "
+                        f"|v|<={p.v_radius}, u_cut {p.u_cut}, FP32 compensated accumulation, FP64 solve",
+            "frames": F, "height": H, "width": W, "patch": p.patch, "v_radius": p.v_radius,
+            "patches": P, "bispectrum_samples_per_patch": S, "parallelism": "single GPU",
+        },
+        "bispectrum_GBps": terms * BYTES_PER_TERM / (bis_ms * 1e-3) / 1e9,
+        "bispectrum_terms_per_s": terms / (bis_ms * 1e-3),
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "stage_ms": stage_ms,
+        "h2d": {"ms": h2d_ms, "GBps": frames.nbytes / (h2d_ms * 1e-3) / 1e9,
+                "bursts_per_s_with_h2d": 1.0 / (elapsed / args.steps + h2d_ms * 1e-3)},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_bispec",
+            "achieved": achieved,
+            "peak": PEAK_FP32_UNPACKED,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_UNPACKED,
+            "traffic": None,
+            "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
+            "algorithmic_flop_per_launch": terms * FLOP_PER_TERM,
+            "avg_launch_ms": bis_ms,
+        },
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

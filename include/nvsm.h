@@ -171,6 +171,17 @@ nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p,
                              const double *stf, float *out,
                              void *workspace, size_t workspace_bytes, void *stream);
 
+/* Stage timing with HIP events recorded on the call's stream around each
+ * stage's kernels (off by default; recording adds no synchronisation).
+ * Stages: 0 ingest (tile cut, taper, FFT, power and mean sums),
+ * 1 bispectrum accumulation, 2 modulus and phase solve, 3 synthesis and
+ * mosaic.  Enabling creates events on first use; 0 disables. */
+nvsm_status nvsm_profile_enable(nvsm_context *ctx, int32_t enable);
+/* Waits for every recorded stage, adds its elapsed milliseconds to ms[stage]
+ * and its launch count to count[stage] (host arrays of n >= 4 entries), and
+ * forgets the records. */
+nvsm_status nvsm_profile_read(nvsm_context *ctx, double *ms, int64_t *count, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,9 @@ EXPORTS = [
     "nvsm_create", "nvsm_destroy", "nvsm_status_string", "nvsm_last_error",
     "nvsm_default_params", "nvsm_plan", "nvsm_w_index", "nvsm_bispectrum_index",
     "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
+    "nvsm_profile_enable", "nvsm_profile_read",
 ]
+STAGES = ["ingest", "bispectrum", "solve", "synthesize"]
 
 
 class NvsmError(RuntimeError):
@@ -84,6 +86,8 @@ def lib():
         L.nvsm_synthesize.argtypes = [c_p, P, c_i32, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]
         L.nvsm_reconstruct.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64,
                                        c_p, c_p, c_p, c_sz, c_p]
+        L.nvsm_profile_enable.argtypes = [c_p, c_i32]
+        L.nvsm_profile_read.argtypes = [c_p, c_p, c_p, c_i32]
         for name in EXPORTS:
             if name not in ("nvsm_destroy", "nvsm_status_string", "nvsm_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -215,3 +219,16 @@ def nvsm_reconstruct(ctx, params, frames, stf, out, workspace, stream=None, row_
                                 _ptr(stf), _ptr(out), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream))
     _check(st, "nvsm_reconstruct", ctx)
+
+
+def nvsm_profile_enable(ctx, enable=True):
+    _check(lib().nvsm_profile_enable(ctx, 1 if enable else 0), "nvsm_profile_enable", ctx)
+
+
+def nvsm_profile_read(ctx):
+    """{stage: (total ms, launches)} since the last read."""
+    import numpy as np
+    ms = np.zeros(len(STAGES), np.float64)
+    cnt = np.zeros(len(STAGES), np.int64)
+    _check(lib().nvsm_profile_read(ctx, ms.ctypes.data, cnt.ctypes.data, len(STAGES)), "nvsm_profile_read", ctx)
+    return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}

@@ -41,10 +41,22 @@ struct DevicePlan {
 
 }  // namespace
 
+constexpr int NSTAGE = 4;
+enum { ST_INGEST = 0, ST_BISPEC = 1, ST_SOLVE = 2, ST_SYNTH = 3 };
+
 struct nvsm_context {
     int device = 0;
     std::string err;
     std::map<std::tuple<int, int, int>, std::unique_ptr<DevicePlan>> plans;
+    // stage timing
+    bool prof = false;
+    std::vector<hipEvent_t> free_ev;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    ~nvsm_context() {
+        for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : free_ev) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -177,9 +189,36 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
     return NVSM_OK;
 }
 
-hipError_t run_accumulate(DevicePlan *dp, const nvsm_params *p, const Sizes &z, const void *frames,
-                          nvsm_dtype dtype, int F, int H, int W, int64_t pitch, float *power,
-                          float *mean_spec, float *mu, float *bispec, char *ws, hipStream_t st) {
+// Records an event pair around one stage when profiling is on.
+struct StageTimer {
+    nvsm_context *ctx;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(nvsm_context *c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
+        if (!ctx || !ctx->prof) return;
+        a = take();
+        b = take();
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    hipEvent_t take() {
+        if (!ctx->free_ev.empty()) { hipEvent_t e = ctx->free_ev.back(); ctx->free_ev.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~StageTimer() {
+        if (!ctx || !ctx->prof) return;
+        if (a && b && hipEventRecord(b, st) == hipSuccess) { ctx->recs.push_back({stage, a, b}); return; }
+        if (a) ctx->free_ev.push_back(a);
+        if (b) ctx->free_ev.push_back(b);
+    }
+};
+
+hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const Sizes &z,
+                          const void *frames, nvsm_dtype dtype, int F, int H, int W, int64_t pitch,
+                          float *power, float *mean_spec, float *mu, float *bispec, char *ws,
+                          hipStream_t st) {
     IngestArgs a;
     a.N = p->patch;
     a.f32 = dtype == NVSM_F32;
@@ -194,16 +233,21 @@ hipError_t run_accumulate(DevicePlan *dp, const nvsm_params *p, const Sizes &z, 
     a.mpart = (float *)(ws + z.spectra + z.ppart);
     a.mupart = (float *)(ws + z.spectra + z.ppart + z.mpart);
     a.power = power; a.mean_spec = mean_spec; a.mu = mu;
-    hipError_t e = launch_ingest(a, st);
+    hipError_t e;
+    {
+        StageTimer t(ctx, ST_INGEST, st);
+        e = launch_ingest(a, st);
+    }
     if (e != hipSuccess || bispec == nullptr) return e;
     BispecArgs b;
     b.N = p->patch; b.spectra = a.spectra; b.F = F; b.patches = (int)z.P;
     b.n_items = dp->h.n_items; b.items = dp->items; b.slot_v = dp->slot; b.out_idx = dp->out_idx;
     b.bispec = (float2 *)bispec; b.s_count = z.S;
+    StageTimer t(ctx, ST_BISPEC, st);
     return launch_bispec(b, st);
 }
 
-hipError_t run_solve(DevicePlan *dp, const nvsm_params *p, int64_t P, const float *power,
+hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, int64_t P, const float *power,
                      const float *mean_spec, const float *bispec, const double *stf, double *amp,
                      double *phasor, hipStream_t st) {
     SolveArgs a;
@@ -212,10 +256,11 @@ hipError_t run_solve(DevicePlan *dp, const nvsm_params *p, int64_t P, const floa
     a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;
     a.stf = stf; a.floor = p->stf_floor; a.noise_bias = p->noise_bias; a.amp = amp;
     a.phasor = (double2 *)phasor;
+    StageTimer t(ctx, ST_SOLVE, st);
     return launch_solve(a, st);
 }
 
-hipError_t run_synth(DevicePlan *dp, const nvsm_params *p, const Sizes &z, int H, int W,
+hipError_t run_synth(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const Sizes &z, int H, int W,
                      const double *amp, const double *phasor, const float *mu, float *patch_buf,
                      float *out, hipStream_t st) {
     SynthArgs a;
@@ -223,6 +268,7 @@ hipError_t run_synth(DevicePlan *dp, const nvsm_params *p, const Sizes &z, int H
     a.amp = amp; a.phasor = (const double2 *)phasor; a.filt = p->filter ? dp->filt : nullptr;
     a.mu = mu; a.hann = dp->hann; a.twiddle = dp->twiddle; a.patch_buf = patch_buf;
     a.H = H; a.W = W; a.ny = z.t.ny; a.nx = z.t.nx; a.stride = p->stride; a.out = out;
+    StageTimer t(ctx, ST_SYNTH, st);
     return launch_synth(a, st);
 }
 
@@ -364,7 +410,7 @@ nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p, const void 
     nvsm_status s = prepare_call(ctx, p, H, W, F, &dp, &z);
     if (s != NVSM_OK) return s;
     if (!workspace || workspace_bytes < ws_acc(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for accumulate");
-    hipError_t e = run_accumulate(dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean_spec, mu, bispec,
+    hipError_t e = run_accumulate(ctx, dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean_spec, mu, bispec,
                                   (char *)workspace, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
     return NVSM_OK;
@@ -383,7 +429,7 @@ nvsm_status nvsm_solve(nvsm_context *ctx, const nvsm_params *p, int64_t patches,
     if (!power || !mean_spec || !bispec || !stf || !amp || !phasor) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
     DevicePlan *dp;
     if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;
-    hipError_t e = run_solve(dp, p, patches, power, mean_spec, bispec, stf, amp, phasor, (hipStream_t)stream);
+    hipError_t e = run_solve(ctx, dp, p, patches, power, mean_spec, bispec, stf, amp, phasor, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
     return NVSM_OK;
 }
@@ -402,7 +448,7 @@ nvsm_status nvsm_synthesize(nvsm_context *ctx, const nvsm_params *p, int32_t H, 
         if (!workspace || workspace_bytes < z.patches) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for synthesize");
         pb = (float *)workspace;
     }
-    hipError_t e = run_synth(dp, p, z, H, W, amp, phasor, mu, pb, out, (hipStream_t)stream);
+    hipError_t e = run_synth(ctx, dp, p, z, H, W, amp, phasor, mu, pb, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
     return NVSM_OK;
 }
@@ -428,13 +474,37 @@ nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p, const void
     double *ph = (double *)w; w += z.phasor;
     float *pat = (float *)w; w += z.patches;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = run_accumulate(dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean, mu, bis, w, st);
+    hipError_t e = run_accumulate(ctx, dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean, mu, bis, w, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
-    e = run_solve(dp, p, z.P, power, mean, bis, stf, amp, ph, st);
+    e = run_solve(ctx, dp, p, z.P, power, mean, bis, stf, amp, ph, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
-    e = run_synth(dp, p, z, H, W, amp, ph, mu, pat, out, st);
+    e = run_synth(ctx, dp, p, z, H, W, amp, ph, mu, pat, out, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
     return NVSM_OK;
+}
+
+nvsm_status nvsm_profile_enable(nvsm_context *ctx, int32_t enable) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    ctx->prof = enable != 0;
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_profile_read(nvsm_context *ctx, double *ms, int64_t *count, int32_t n) {
+    if (!ctx || !ms || !count || n < NSTAGE) return NVSM_ERR_INVALID_ARG;
+    nvsm_status s = NVSM_OK;
+    for (auto &r : ctx->recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+            s = fail(ctx, NVSM_ERR_HIP, "event timing failed");
+        } else {
+            ms[r.stage] += t;
+            count[r.stage] += 1;
+        }
+        ctx->free_ev.push_back(r.a);
+        ctx->free_ev.push_back(r.b);
+    }
+    ctx->recs.clear();
+    return s;
 }
 
 }  // extern "C"

@@ -24,6 +24,7 @@ independently and in any order.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
 import os
 
@@ -112,9 +113,9 @@ def phase_screen(M: int, r0: float, rng: np.random.Generator,
     f = np.sqrt(fx * fx + fy * fy)
     c = (rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M)))
     c *= np.sqrt(_psd(f, r0)) * df
-    scr = np.real(sfft.fft2(c, workers=_workers()))
+    scr = np.real(sfft.fft2(c, workers=1))
     if subharmonics:
-        y, x = np.mgrid[0:M, 0:M].astype(np.float64)
+        n = np.arange(M, dtype=np.float64)
         sh = np.zeros((M, M))
         for p in range(1, subharmonics + 1):
             dfp = df / 3.0 ** p
@@ -126,7 +127,9 @@ def phase_screen(M: int, r0: float, rng: np.random.Generator,
                     fr = np.hypot(fxp, fyp)
                     cc = (rng.standard_normal() + 1j * rng.standard_normal())
                     cc *= np.sqrt(0.023 * r0 ** (-5.0 / 3.0) * fr ** (-11.0 / 3.0)) * dfp
-                    sh += np.real(cc * np.exp(2j * np.pi * (fxp * x + fyp * y)))
+                    ex = np.exp(2j * np.pi * fxp * n)
+                    ey = np.exp(2j * np.pi * fyp * n)
+                    sh += np.real(cc * np.outer(ey, ex))
         scr = scr + sh - sh.mean()
     return scr
 
@@ -141,7 +144,7 @@ def pupil_psf(screen: np.ndarray) -> np.ndarray:
     """Unit-sum PSF |FFT(pupil exp(i phi))|^2, origin at [0, 0] (wrapped)."""
     M = screen.shape[0]
     field = _pupil(M) * np.exp(1j * screen)
-    psf = np.abs(sfft.fft2(field, workers=_workers())) ** 2
+    psf = np.abs(sfft.fft2(field, workers=1)) ** 2
     return psf / psf.sum()
 
 
@@ -170,11 +173,12 @@ def make_burst(cfg: BurstConfig, frames: int | None = None,
     ospec = sfft.rfft2(obj, workers=_workers())
     out = np.empty((F, cfg.H, cfg.W), np.uint16 if cfg.dtype == "u16" else np.float32)
     gain = cfg.photons / 2048.0
-    for f in range(F):
+
+    def one(f):
         srng = np.random.default_rng([burst_seed(cfg, 1), f])
         psf = pupil_psf(phase_screen(cfg.M, cfg.r0_px, srng))
-        otf = sfft.rfft2(_embed(psf, cfg.H, cfg.W), workers=_workers())
-        img = sfft.irfft2(ospec * otf, s=(cfg.H, cfg.W), workers=_workers())
+        otf = sfft.rfft2(_embed(psf, cfg.H, cfg.W), workers=1)
+        img = sfft.irfft2(ospec * otf, s=(cfg.H, cfg.W), workers=1)
         np.maximum(img, 0.0, out=img)
         nrng = np.random.default_rng([burst_seed(cfg, 2), f])
         photons = nrng.poisson(img * cfg.photons)
@@ -182,6 +186,9 @@ def make_burst(cfg: BurstConfig, frames: int | None = None,
             out[f] = np.clip(np.rint(photons / gain), 0, 4095).astype(np.uint16)
         else:
             out[f] = photons.astype(np.float32)
+
+    with cf.ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(one, range(F)))
     if return_object:
         return out, obj
     return out
@@ -196,12 +203,15 @@ def stf_table(cfg: BurstConfig, screens: int = 1000, patch: int | None = None) -
     """
     N = cfg.patch if patch is None else patch
     M = cfg.M
-    acc = np.zeros((M, M))
-    for j in range(screens):
+    def one(j):
         rng = np.random.default_rng([burst_seed(cfg, 3), j])
         psf = pupil_psf(phase_screen(M, cfg.r0_px, rng))
-        otf = sfft.fft2(psf, workers=_workers())
-        acc += np.abs(otf) ** 2
+        return np.abs(sfft.fft2(psf, workers=1)) ** 2
+
+    acc = np.zeros((M, M))
+    with cf.ThreadPoolExecutor(max_workers=_workers()) as ex:
+        for a in ex.map(one, range(screens)):
+            acc += a
     acc /= screens
     acc /= acc[0, 0]
     step = M // N
