@@ -92,6 +92,16 @@ __host__ __device__ constexpr int fft_pos(int k) {
 
 template <int N> struct LdsPitch { static constexpr int v = N + 1; };
 
+// Stored spectrum of one (patch, frame): rows uy = -SPEC_NEG_ROWS .. N/2-1
+// of I(ux, uy), row-major, ux in DFT order (column ux mod N).  The rows
+// below 0 are the conjugate mirrors I(ux, -uy) = conj I(-ux, uy), kept so
+// that every value the bispectrum needs is a plain load.
+constexpr int SPEC_NEG_ROWS = 16;
+template <int N> struct SpecRows {
+    static constexpr int ROWS = N / 2 + SPEC_NEG_ROWS;
+    static constexpr int FS = ROWS * N;
+};
+
 // In-place forward 2-D DFT (unnormalised, exp(-2 pi i ...)) of the N x N
 // complex tile z[y * PITCH + x] in LDS, by NT threads.  tw[k] =
 // exp(-2 pi i k / N).  Input in natural order; on return frequency
@@ -108,6 +118,7 @@ __device__ void fft2d_lds(float2 *z, const float2 *tw) {
         const int es = axis == 0 ? 1 : P;   // element step along the axis
         const int ls = axis == 0 ? P : 1;   // step between lines
         // pass A: for each line and n1, DFT over n2 of x[n1 + R1 n2]
+#pragma unroll 2
         for (int t = tid; t < N * R1; t += NT) {
             const int line = t % N, n1 = t / N;
             float2 v[R2];
@@ -123,6 +134,7 @@ __device__ void fft2d_lds(float2 *z, const float2 *tw) {
         }
         __syncthreads();
         // pass B: for each line and k2, DFT over n1 of the contiguous group
+#pragma unroll 2
         for (int t = tid; t < N * R2; t += NT) {
             const int line = t % N, k2 = t / N;
             float2 v[R1];

@@ -13,9 +13,29 @@ namespace {
 
 constexpr int NT = 256;
 
-template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
+// Four consecutive pixels of a row, loaded as one vector when the layout
+// allows it (VEC), else one by one.
+template <typename T, bool VEC> struct Quad;
+template <> struct Quad<uint16_t, true> {
+    ushort4 v;
+    __device__ void load(const uint16_t *p) { v = *(const ushort4 *)p; }
+    __device__ float operator[](int i) const { return (float)(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w); }
+};
+template <> struct Quad<float, true> {
+    float4 v;
+    __device__ void load(const float *p) { v = *(const float4 *)p; }
+    __device__ float operator[](int i) const { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+};
+template <typename T> struct Quad<T, false> {
+    float e[4];
+    __device__ void load(const T *p) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = (float)p[i];
+    }
+    __device__ float operator[](int i) const { return e[i]; }
+};
 
-template <int N, typename T>
+template <int N, typename T, bool VEC>
 __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int F, int H, int W,
                                                int64_t pitch, int nx, int stride, int chunk_frames,
                                                int nchunks, int total, int window, float inv_wsum,
@@ -27,7 +47,7 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
     constexpr int HALF = N / 2;
     constexpr int NP = (HALF + 1) * N;           // power rows 0..N/2
     constexpr int NPT = (NP + NT - 1) / NT;
-    constexpr int PPT = N * N / NT;              // pixels per thread
+    constexpr int QPT = N * N / 4 / NT;          // pixel quads per thread and frame
     __shared__ float2 z[N * P];
     __shared__ float2 tw[N];
     __shared__ float hw[N];
@@ -43,31 +63,53 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
         tw[i] = twiddle[i];
         hw[i] = window ? hann[i] : 1.0f;
     }
-    float ps[NPT], pc[NPT];
+    // power sums of this frame group: plain FP32 over the group (at most
+    // CHUNK_FRAMES frames); the groups are combined with Kahan sums later
+    float ps[NPT];
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) { ps[i] = 0.f; pc[i] = 0.f; }
+    for (int i = 0; i < NPT; ++i) ps[i] = 0.f;
     float m10s[2] = {0.f, 0.f}, m10c[2] = {0.f, 0.f}, m01s[2] = {0.f, 0.f}, m01c[2] = {0.f, 0.f};
     float mus = 0.f, muc = 0.f;
-    const size_t spec_patch = (size_t)patch * F * HALF * N;
+    constexpr int FS = SpecRows<N>::FS;          // float2 per stored frame spectrum
+    const size_t spec_patch = (size_t)patch * F * FS;
+
+    // raw pixels of the current frame pair, loaded one pair ahead (not for
+    // 4-byte pixels at N = 128, which would not fit in registers)
+    constexpr bool AHEAD = !(sizeof(T) == 4 && N == 128);
+    Quad<T, VEC> qa[QPT], qb[QPT];
+    auto load_pair = [&](int fa) __attribute__((always_inline)) {
+        const int fb = min(fa + 1, f1 - 1);
+        const T *pa = frames + (size_t)fa * H * pitch + (size_t)y0 * pitch + x0;
+        const T *pb = frames + (size_t)fb * H * pitch + (size_t)y0 * pitch + x0;
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            qa[j].load(pa + (size_t)y * pitch + x);
+            qb[j].load(pb + (size_t)y * pitch + x);
+        }
+    };
+    if (AHEAD) load_pair(f0);
     __syncthreads();
 
     for (int fa = f0; fa < f1; fa += 2) {
         const int fb = fa + 1;
         const bool hasb = fb < f1;
-        const T *pa = frames + (size_t)fa * H * pitch + (size_t)y0 * pitch + x0;
-        const T *pb = frames + (size_t)(hasb ? fb : fa) * H * pitch + (size_t)y0 * pitch + x0;
-        // load, weighted sums (compensated), raw pixels to LDS
+        if (!AHEAD) load_pair(fa);
+        // weighted sums (compensated), raw pixels to LDS
         float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
-#pragma unroll 4
-        for (int j = 0; j < PPT; ++j) {
-            const int i = j * NT + tid, y = i / N, x = i % N;
-            const float va = to_f(pa[(size_t)y * pitch + x]);
-            const float vb = hasb ? to_f(pb[(size_t)y * pitch + x]) : 0.f;
-            const float w = hw[y] * hw[x];
-            kahan_add(sa, ca, w * va);
-            kahan_add(sb, cb, w * vb);
-            z[y * P + x] = make_float2(va, vb);
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float va = qa[j][e], vb = hasb ? qb[j][e] : 0.f;
+                const float w = hw[y] * hw[x + e];
+                kahan_add(sa, ca, w * va);
+                kahan_add(sb, cb, w * vb);
+                z[y * P + x + e] = make_float2(va, vb);
+            }
         }
+        if (AHEAD && fa + 2 < f1) load_pair(fa + 2);      // in flight during the FFT
         float ra = wave_sum(sa - ca), rb = wave_sum(sb - cb);
         if ((tid & 63) == 0) { red[0][tid >> 6] = ra; red[1][tid >> 6] = rb; }
         __syncthreads();
@@ -81,12 +123,15 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
             if (hasb) kahan_add(mus, muc, mub);
         }
         // taper the mean-removed pixels
-#pragma unroll 4
-        for (int j = 0; j < PPT; ++j) {
-            const int i = j * NT + tid, y = i / N, x = i % N;
-            const float w = hw[y] * hw[x];
-            const float2 v = z[y * P + x];
-            z[y * P + x] = make_float2((v.x - mua) * w, hasb ? (v.y - mub) * w : 0.f);
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float w = hw[y] * hw[x + e];
+                const float2 v = z[y * P + x + e];
+                z[y * P + x + e] = make_float2((v.x - mua) * w, hasb ? (v.y - mub) * w : 0.f);
+            }
         }
         __syncthreads();
         fft2d_lds<N, NT>(z, tw);
@@ -100,11 +145,21 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
                 const float2 Zm = z[fft_pos<N>((N - uy) & (N - 1)) * P + fft_pos<N>((N - ux) & (N - 1))];
                 const float2 Ia = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
                 const float2 Ib = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
-                kahan_add(ps[k], pc[k], Ia.x * Ia.x + Ia.y * Ia.y);
-                if (hasb) kahan_add(ps[k], pc[k], Ib.x * Ib.x + Ib.y * Ib.y);
+                ps[k] += Ia.x * Ia.x + Ia.y * Ia.y;
+                if (hasb) ps[k] += Ib.x * Ib.x + Ib.y * Ib.y;
                 if (uy < HALF) {
-                    spectra[spec_patch + (size_t)fa * HALF * N + j] = Ia;
-                    if (hasb) spectra[spec_patch + (size_t)fb * HALF * N + j] = Ib;
+                    // row uy of the stored record, and its conjugate mirror
+                    // I(-u) = conj I(u) in row -uy for the rows below 0
+                    float2 *ra = spectra + spec_patch + (size_t)fa * FS;
+                    float2 *rb = spectra + spec_patch + (size_t)fb * FS;
+                    const int o = (uy + SPEC_NEG_ROWS) * N + ux;
+                    ra[o] = Ia;
+                    if (hasb) rb[o] = Ib;
+                    if (uy >= 1 && uy <= SPEC_NEG_ROWS) {
+                        const int om = (SPEC_NEG_ROWS - uy) * N + ((N - ux) & (N - 1));
+                        ra[om] = conjf2(Ia);
+                        if (hasb) rb[om] = conjf2(Ib);
+                    }
                 }
                 if (j == 1) {          // u = (1, 0)
                     kahan_add(m10s[0], m10c[0], Ia.x); kahan_add(m10s[1], m10c[1], Ia.y);
@@ -123,7 +178,7 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int j = k * NT + tid;
-        if (j < NP) pp[j] = ps[k] - pc[k];
+        if (j < NP) pp[j] = ps[k];
     }
     float *mp = mpart + ((size_t)patch * nchunks + chunk) * 4;
     if (tid == 1 % NT) { mp[0] = m10s[0] - m10c[0]; mp[1] = m10s[1] - m10c[1]; }
@@ -165,9 +220,17 @@ __global__ __launch_bounds__(NT) void k_acc_finalize(int nchunks, float invF,
 template <int N, typename T>
 hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
     const int total = a.patches * a.nchunks;
-    hipLaunchKernelGGL((k_ingest<N, T>), dim3(total), dim3(NT), 0, st, (const T *)a.frames, a.F, a.H,
-                       a.W, a.pitch, a.nx, a.stride, a.chunk_frames, a.nchunks, total, a.window,
-                       a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart, a.mupart);
+    // vector loads need every quad of 4 pixels aligned to its size
+    const bool vec = a.stride % 4 == 0 && (a.W - N) % 4 == 0 && a.pitch % 4 == 0 &&
+                     ((uintptr_t)a.frames % (4 * sizeof(T))) == 0;
+    if (vec)
+        hipLaunchKernelGGL((k_ingest<N, T, true>), dim3(total), dim3(NT), 0, st, (const T *)a.frames, a.F, a.H,
+                           a.W, a.pitch, a.nx, a.stride, a.chunk_frames, a.nchunks, total, a.window,
+                           a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart, a.mupart);
+    else
+        hipLaunchKernelGGL((k_ingest<N, T, false>), dim3(total), dim3(NT), 0, st, (const T *)a.frames, a.F, a.H,
+                           a.W, a.pitch, a.nx, a.stride, a.chunk_frames, a.nchunks, total, a.window,
+                           a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart, a.mupart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_acc_finalize<N>), dim3(a.patches), dim3(NT), 0, st, a.nchunks, 1.0f / a.F,

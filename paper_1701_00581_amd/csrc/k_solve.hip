@@ -18,6 +18,7 @@ namespace {
 constexpr int NT = 512;
 constexpr int NWAVE = NT / 64;
 constexpr int MAXW_PER_SHELL_WAVE = 2;   // up to 16 w per shell
+constexpr int DEPTH = 4;                 // shells of samples in flight
 
 template <int N> struct MaxW;
 template <> struct MaxW<64> { static constexpr int v = 1504; };
@@ -98,29 +99,28 @@ __global__ __launch_bounds__(NT) void k_solve(int nW, int nshell, const int *__r
     }
 
     const float2 *B = bispec + (size_t)patch * s_count;
-    auto load = [&](int s, ShellRegs<TPL> &r) {
+    // Loads are issued unconditionally (clamped to entry 0 where there is no
+    // sample) so that every shell issues the same number of loads.
+    auto load = [&](int s, ShellRegs<TPL> &r) __attribute__((always_inline)) {
         const int wb = shell_wb[s], nw = shell_wb[s + 1] - wb;
 #pragma unroll
         for (int m = 0; m < MAXW_PER_SHELL_WAVE; ++m) {
             const int jj = wave + NWAVE * m;
-            r.w[m] = -1;
-            r.cnt[m] = 0;
-            if (jj < nw) {
-                const int w = wb + jj, o = woff[w], cnt = woff[w + 1] - o;
-                r.w[m] = w;
-                r.cnt[m] = cnt;
+            const bool has = jj < nw;
+            const int w = has ? wb + jj : 0;
+            const int o = woff[w], cnt = has ? woff[w + 1] - o : 0;
+            r.w[m] = has ? w : -1;
+            r.cnt[m] = cnt;
 #pragma unroll
-                for (int i = 0; i < TPL; ++i) {
-                    const int t = lane + 64 * i;
-                    if (t < cnt) {
-                        r.code[m][i] = code[o + t];
-                        r.b[m][i] = B[o + t];
-                    }
-                }
+            for (int i = 0; i < TPL; ++i) {
+                const int t = lane + 64 * i;
+                const int idx = t < cnt ? o + t : 0;
+                r.code[m][i] = code[idx];
+                r.b[m][i] = B[idx];
             }
         }
     };
-    auto solve = [&](const ShellRegs<TPL> &r) {
+    auto solve = [&](const ShellRegs<TPL> &r) __attribute__((always_inline)) {
 #pragma unroll
         for (int m = 0; m < MAXW_PER_SHELL_WAVE; ++m) {
             if (r.w[m] >= 0) {
@@ -151,14 +151,21 @@ __global__ __launch_bounds__(NT) void k_solve(int nW, int nshell, const int *__r
     };
 
     __syncthreads();
-    if (nshell > 1) {
-        ShellRegs<TPL> cur, nxt;
-        load(1, cur);
-        for (int s = 1; s < nshell; ++s) {
-            if (s + 1 < nshell) load(s + 1, nxt);
-            solve(cur);
-            __syncthreads();
-            cur = nxt;
+    // shells 1.. in order; the samples of shell s + DEPTH - 1 are loaded
+    // while shell s is solved (a ring of DEPTH register sets)
+    ShellRegs<TPL> ring[DEPTH];
+#pragma unroll
+    for (int d = 0; d < DEPTH - 1; ++d)
+        if (1 + d < nshell) load(1 + d, ring[d]);
+    for (int s0 = 1; s0 < nshell; s0 += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            const int s = s0 + d;
+            if (s < nshell) {
+                if (s + DEPTH - 1 < nshell) load(s + DEPTH - 1, ring[(d + DEPTH - 1) % DEPTH]);
+                solve(ring[d]);
+                __syncthreads();
+            }
         }
     }
     for (int i = tid; i < nW; i += NT) phasor[(size_t)patch * nW + i] = e[i];

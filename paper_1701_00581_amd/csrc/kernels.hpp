@@ -16,7 +16,7 @@ struct IngestArgs {
     float inv_wsum = 0.f;
     const float2 *twiddle = nullptr;
     const float *hann = nullptr;
-    float2 *spectra = nullptr;            // [P][F][N/2][N]
+    float2 *spectra = nullptr;            // [P][F][N/2 + 16][N], rows -16 .. N/2-1
     float *ppart = nullptr, *mpart = nullptr, *mupart = nullptr;
     float *power = nullptr, *mean_spec = nullptr, *mu = nullptr;
 };
@@ -25,7 +25,7 @@ hipError_t launch_ingest(const IngestArgs &a, hipStream_t st);
 struct BispecArgs {
     int N = 0;
     const float2 *spectra = nullptr;
-    int F = 0, patches = 0, n_items = 0;
+    int F = 0, patches = 0, n_items = 0, slots = 0;
     const int *items = nullptr, *slot_v = nullptr, *out_idx = nullptr;
     float2 *bispec = nullptr;             // [P][|S|]
     int64_t s_count = 0;

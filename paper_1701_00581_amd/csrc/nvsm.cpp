@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -106,7 +107,7 @@ void sizes_of(const nvsm_params *p, int H, int W, int F, int64_t nW, int64_t S, 
     z->S = S;
     z->shells = shells;
     z->chunks = (F + CHUNK_FRAMES - 1) / CHUNK_FRAMES;
-    z->spectra = align_up((size_t)z->P * F * (N / 2) * N * 8);
+    z->spectra = align_up((size_t)z->P * F * (N / 2 + 16) * N * 8);   // rows -16 .. N/2-1
     z->ppart = align_up((size_t)z->P * z->chunks * (N / 2 + 1) * N * 4);
     z->mpart = align_up((size_t)z->P * z->chunks * 4 * 4);
     z->mupart = align_up((size_t)z->P * z->chunks * 4);
@@ -147,6 +148,15 @@ nvsm_status upload(DevicePlan *dp, const std::vector<T> &v, T **out, std::string
     return NVSM_OK;
 }
 
+int bispec_slots() {
+    static const int k = [] {
+        const char *e = getenv("NVSM_BISPEC_SLOTS");
+        int v = e ? atoi(e) : 16;
+        return (v == 16 || v == 24) ? v : 16;
+    }();
+    return k;
+}
+
 nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) {
     auto key = std::make_tuple(p->patch, p->u_cut, p->v_radius);
     auto f = ctx->plans.find(key);
@@ -159,7 +169,7 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
     }
     std::string msg;
     try {
-        if (!build_plan(p->patch, p->u_cut, p->v_radius, &dp->h, &msg)) return fail(ctx, NVSM_ERR_INVALID_ARG, msg);
+        if (!build_plan(p->patch, p->u_cut, p->v_radius, bispec_slots(), &dp->h, &msg)) return fail(ctx, NVSM_ERR_INVALID_ARG, msg);
     } catch (const std::bad_alloc &) {
         return fail(ctx, NVSM_ERR_OOM, "host allocation failed while planning");
     }
@@ -241,7 +251,7 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
     if (e != hipSuccess || bispec == nullptr) return e;
     BispecArgs b;
     b.N = p->patch; b.spectra = a.spectra; b.F = F; b.patches = (int)z.P;
-    b.n_items = dp->h.n_items; b.items = dp->items; b.slot_v = dp->slot; b.out_idx = dp->out_idx;
+    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.slot_v = dp->slot; b.out_idx = dp->out_idx;
     b.bispec = (float2 *)bispec; b.s_count = z.S;
     StageTimer t(ctx, ST_BISPEC, st);
     return launch_bispec(b, st);

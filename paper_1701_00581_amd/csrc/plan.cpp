@@ -83,7 +83,9 @@ int count_shells(const std::vector<int32_t> &W) {
     return n;
 }
 
-bool build_plan(int N, int uc, int R, HostPlan *pl, std::string *err) {
+bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
+    if (K < 8 || K > BS_MAX_SLOTS || K % 8) { *err = "slots per wave must be 8..32, a multiple of 8"; return false; }
+    pl->slots = K;
     if (N != 64 && N != 128) { *err = "patch must be 64 or 128"; return false; }
     if (uc < 2 || uc >= N / 2) { *err = "u_cut must be in [2, N/2)"; return false; }
     if (R < 1 || R > 16 || R >= uc) { *err = "v_radius must be in [1, min(16, u_cut))"; return false; }
@@ -124,7 +126,7 @@ bool build_plan(int N, int uc, int R, HostPlan *pl, std::string *err) {
     if (pl->s_count >= (int64_t)1 << 31) { *err = "bispectrum set too large"; return false; }
 
     // Bispectrum work: 8x8 blocks of w; the union of their v, cut into
-    // balanced chunks of <= BS_SLOTS, BS_WAVES chunks per workgroup.
+    // balanced chunks of <= K, BS_WAVES chunks per workgroup.
     const int half = N / 2;
     const int nbx = N / BS_BLOCK;
     std::map<std::pair<int, int>, std::vector<int>> blocks;  // (cy, cx) -> w ids
@@ -159,7 +161,7 @@ bool build_plan(int N, int uc, int R, HostPlan *pl, std::string *err) {
         for (auto &u : uni) U.push_back({u.first.second, u.first.first});
         if (U.empty()) continue;
         const int nU = (int)U.size();
-        const int nchunk = (nU + BS_SLOTS - 1) / BS_SLOTS;
+        const int nchunk = (nU + K - 1) / K;
         const int ngroup = (nchunk + BS_WAVES - 1) / BS_WAVES;
         // balanced chunk sizes
         std::vector<int> cstart(nchunk + 1, 0);
@@ -174,19 +176,19 @@ bool build_plan(int N, int uc, int R, HostPlan *pl, std::string *err) {
             int rx0 = bx0 - vxmax, ry0 = by0 - vymax;
             int rw = (bx0 + BS_BLOCK - 1 - vxmin) - rx0 + 1;
             int rh = (by0 + BS_BLOCK - 1 - vymin) - ry0 + 1;
-            if (rw * rh > BS_MAX_REGION) { *err = "bispectrum region too large"; return false; }
-            int32_t it[BS_ITEM_INTS] = {bx0, by0, rx0, ry0, rw, rh, rw * rh, 0, 0, 0, 0, 0};
+            const int pitch = bs_region_pitch(rw);
+            if (pitch * rh > bs_region_cap(K)) { *err = "bispectrum region too large"; return false; }
+            int32_t it[BS_ITEM_INTS] = {bx0, by0, rx0, ry0, rw, rh, rw * rh, pitch, 0, 0, 0, 0};
             for (int wv = 0; wv < BS_WAVES; ++wv) {
                 int c = c0 + wv;
                 int ns = c < c1 ? cstart[c + 1] - cstart[c] : 0;
                 it[8 + wv] = ns;
                 pl->computed_terms += (int64_t)ns * BS_LANES;
-                for (int k = 0; k < BS_SLOTS; ++k) {
+                for (int k = 0; k < K; ++k) {
                     int u = k < ns ? cstart[c] + k : cstart[c0];
                     int vx = U[u].first, vy = U[u].second;
-                    pl->slot_v.push_back(vy * rw + vx);
-                    uint32_t so = vy >= 0 ? (uint32_t)(vy * N + (vx & (N - 1)))
-                                          : ((uint32_t)(-vy * N + ((-vx) & (N - 1))) | 0x80000000u);
+                    pl->slot_v.push_back(vy * pitch + vx);
+                    const uint32_t so = (uint32_t)((vy + 16) * N + (vx & (N - 1)));
                     pl->slot_v.push_back((int32_t)so);
                     for (int lane = 0; lane < BS_LANES; ++lane) {
                         int32_t o = -1;

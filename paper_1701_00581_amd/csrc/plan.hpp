@@ -10,12 +10,12 @@
 namespace nvsm {
 
 // Bispectrum kernel geometry: a wave's 64 lanes hold an 8x8 block of w, its
-// BS_SLOTS slots hold v values shared by the whole wave.
+// K slots hold v values shared by the whole wave.
 constexpr int BS_LANES = 64;
 constexpr int BS_BLOCK = 8;
-constexpr int BS_SLOTS = 32;
+constexpr int BS_MAX_SLOTS = 32;     // largest slot count per wave
 constexpr int BS_WAVES = 4;            // waves per workgroup
-constexpr int BS_MAX_REGION = 1024;    // staged points per frame per workgroup
+constexpr int BS_MAX_REGION = 1024;    // staged region extent (pitch x height) per frame
 constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
 
 struct Tiling {
@@ -37,15 +37,18 @@ struct HostPlan {
     std::vector<uint32_t> phase_code;
     int64_t s_count = 0;
     // Bispectrum work items.  items[g*12 + 0..11] = block x0, block y0,
-    // region x0, region y0, region width, region height, region points, 0,
-    // then the slot count of each of the BS_WAVES waves.
+    // region x0, region y0, region width, region height, region points
+    // (width x height), region row pitch in LDS, then the slot count of each
+    // of the BS_WAVES waves.  The pitch is padded to 8 mod 32 complex values
+    // so that the 8 rows of a block fall into different LDS banks.
+    int slots = 0;                      // v slots per wave (K)
     int n_items = 0;
     std::vector<int32_t> items;
-    // slot[((g*BS_WAVES + wave)*BS_SLOTS + k)*2 + 0] = vy * region_width + vx
+    // slot[((g*BS_WAVES + wave)*K + k)*2 + 0] = vy * region_pitch + vx
     // (offset of v in the staged region), [..+1] = offset of I(v) in a
-    // frame's stored half spectrum, bit 31 set when I(v) = conj of it.
+    // frame's stored spectrum record (rows -16 .. N/2-1).
     std::vector<int32_t> slot_v;
-    // out_idx[((g*BS_WAVES + wave)*BS_SLOTS + k)*64 + lane] = S index or -1
+    // out_idx[((g*BS_WAVES + wave)*K + k)*64 + lane] = S index or -1
     std::vector<int32_t> out_idx;
     int64_t computed_terms = 0;         // wave slots x 64 lanes actually run
     // Constant tables.
@@ -56,7 +59,11 @@ struct HostPlan {
 };
 
 // Builds everything above; returns false with *err set on bad sizes.
-bool build_plan(int N, int uc, int R, HostPlan *out, std::string *err);
+bool build_plan(int N, int uc, int R, int slots, HostPlan *out, std::string *err);
+// Largest padded region extent the slot count allows (LDS sizing).
+constexpr int bs_region_cap(int) { return BS_MAX_REGION; }
+// Row pitch >= w with pitch = 8 (mod 32).
+constexpr int bs_region_pitch(int w) { return w + ((8 - w) % 32 + 32) % 32; }
 
 // S in storage order, 4 ints per entry (wx, wy, vx, vy).
 void enumerate_S(int uc, int R, std::vector<int32_t> *wv);
