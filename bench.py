@@ -43,9 +43,34 @@ WORKLOADS = {
     "single64": dict(v_radius=8, patch=64, window=0, noise_bias=1, filter=1),
 }
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_bispec_burst2560_traffic.md")
+
 _FR = None
 _STF = None
 _OP = None
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_bispec launch from the committed counter summary, or
+    None when it does not cover this workload or the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    if workload != "burst2560" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for f in kv["source_files"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != kv["source_sha256_16"]:
+            return None
+        return float(kv["k_bispec_traffic_bytes"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def _oracle_worker(tiles):
@@ -87,6 +112,8 @@ def main():
     ap.add_argument("--stf-screens", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (reference for traffic counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -136,6 +163,13 @@ def main():
     h2d_ms = float(np.median(h2d))
     d_stf = torch.from_numpy(stf).to(dev)
 
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for _ in range(args.warmup):
         s.reconstruct(d_frames, d_stf)
     torch.cuda.synchronize()
@@ -201,7 +235,8 @@ def main():
             "peak": PEAK_FP32_UNPACKED,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_UNPACKED,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
+            "traffic_unit": "bytes per launch (HBM read+write, copy-calibrated FETCH_SIZE/WRITE_SIZE)",
             "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
             "algorithmic_flop_per_launch": terms * FLOP_PER_TERM,
             "avg_launch_ms": bis_ms,

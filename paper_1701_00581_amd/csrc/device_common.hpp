@@ -149,6 +149,21 @@ __device__ void fft2d_lds(float2 *z, const float2 *tw) {
     }
 }
 
+// A wave-uniform pointer held in scalar registers, opaque to the optimizer:
+// loads at (base + 32-bit lane offset) then use scalar-base addressing
+// instead of per-lane 64-bit address arithmetic.
+typedef const __attribute__((address_space(1))) char *gptr_c;
+__device__ __forceinline__ gptr_c uniform_ptr(const void *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (gptr_c)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T load_global(gptr_c base, unsigned byte_off) {
+    return *(const __attribute__((address_space(1))) T *)(base + byte_off);
+}
+
 // Workgroup id remapped so that consecutive logical ids stay on one XCD:
 // hardware dispatches workgroup b to XCD b % 8.
 __device__ __forceinline__ int xcd_remap(int b, int total) {

@@ -22,7 +22,7 @@ namespace nvsm {
 namespace {
 
 constexpr int NT = BS_WAVES * 64;
-constexpr int KB = 10;                     // frames per compensated block
+constexpr int KB = 20;                     // frames per compensated block
 
 // LDS staging record of one frame: the item's region of I (w - v values),
 // then the slot values I(v) of the 4 waves, then the 64 I(w) of the block.
@@ -63,7 +63,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
     // stored spectrum record (always inside it; region points beyond the
     // stored rows are never used by a sample and read a clamped row) and
     // byte offsets in the LDS record (the last slot of the record is a sink
-    // for threads with nothing to stage).
+    // for threads with nothing to stage).  32-bit byte offsets on a uniform
+    // frame base let the loads use scalar-base addressing.
     constexpr int FS = SpecRows<N>::FS;
     const int nstage = npts + St::NV + 64;
     int src[St::PER], dst[St::PER];
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
             so = (by0 + (l >> 3) + SPEC_NEG_ROWS) * N + ((bx0 + (l & 7)) & (N - 1));
             d = rext + St::NV + l;
         }
-        src[j] = so;
+        src[j] = so * (int)sizeof(float2);
         dst[j] = d * (int)sizeof(float2);
     }
 
@@ -92,9 +93,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
     auto fetch = [&](int f0, float2 (&v)[GF][St::PER]) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < GF; ++q) {
-            const float2 *sf = sp + (size_t)min(f0 + q, F - 1) * FS;
+            const gptr_c sf = uniform_ptr(sp + (size_t)min(f0 + q, F - 1) * FS);
 #pragma unroll
-            for (int j = 0; j < St::PER; ++j) v[q][j] = sf[(unsigned)src[j]];
+            for (int j = 0; j < St::PER; ++j) v[q][j] = load_global<float2>(sf, (unsigned)src[j]);
         }
     };
     auto store = [&](int buf, const float2 (&v)[GF][St::PER]) __attribute__((always_inline)) {

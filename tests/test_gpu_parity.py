@@ -233,3 +233,68 @@ def test_error_paths(torch_cuda):
         torch.cuda.synchronize()
     finally:
         nv.nvsm_destroy(ctx)
+
+
+def test_full_burst2560_sampled(torch_cuda):
+    """The benchmark workload at full size (2560x2160 x 100 frames, 39x33
+    patches, R = 12, noise bias and filter on) through nvsm_reconstruct and
+    the stage calls: sampled patches against the oracle (power, mean
+    spectrum, 20000 bispectrum samples, modulus, all phases of two patches)
+    and a mosaic window covered by four patches."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case burst2560 full size: reconstruct + sampled stages")
+    fr = burst("burst2560")
+    F, H, W = fr.shape
+    p = nv.default_params(128, v_radius=12, noise_bias=1, filter=1)
+    st = stf("burst2560", screens=100)
+    s = _session(p, H, W, F)
+    assert s.info.patches == 1287
+    d = to_device(fr)
+    std = torch.from_numpy(st).cuda()
+    img = s.reconstruct(d, std).clone()
+    s.accumulate(d)
+    s.solve(std)
+    torch.cuda.synchronize()
+    assert torch.isfinite(img).all()
+    op = oparams(p)
+    Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+    rng = np.random.default_rng(2560)
+    pick = rng.choice(len(S), 20000, replace=False)
+    P = s.power.cpu().numpy()
+    B = as_complex(s.bispec)
+    amp = s.amp.cpu().numpy()
+    ph = as_complex(s.phasor)
+    for k in [0, 643, 1286, int(rng.integers(0, 1287))]:
+        c = cube(fr, p, k)
+        I, muf = oracle.patch_spectra(c, op.window)
+        Po = np.mean(np.abs(I) ** 2, axis=0)
+        perr = np.linalg.norm(P[k] - Po) / np.linalg.norm(Po)
+        Bo = oracle.bispectrum(I, S[pick])
+        A = abs_bispectrum(I, S[pick])
+        nerr, aerr = bispec_errors(B[k][pick], Bo, A)
+        nb = oracle.noise_bias(Po)
+        ao = oracle.amplitude(Po, st, Wset, nb, p.stf_floor)
+        aerr2 = np.max(np.abs(amp[k] - ao)) / np.max(ao)
+        say(f"[burst2560] patch {k}: P {perr:.2e} B norm {nerr:.2e} B/A max {aerr:.2e} amp {aerr2:.2e}")
+        assert perr <= POWER_TOL and nerr <= BISPEC_TOL and aerr <= BISPEC_TOL and aerr2 <= 1e-4
+    for k in [0, 1286]:
+        acc = oracle.accumulate_patch(cube(fr, p, k), op, S)
+        eo = oracle.phase_recursion(acc["B"], acc["M10"], acc["M01"], Wset, S, woff, p.patch)
+        rms, mx = phase_rms(ph[k], eo)
+        say(f"[burst2560] patch {k}: phase rms {rms:.2e} max {mx:.2e}")
+        assert rms <= PHASE_RMS_TOL
+    # mosaic window [64, 128) x [64, 128): covered by tiles (0..1, 0..1) only
+    ref = oracle.reconstruct(fr, op, st, patch_list=[(0, 0), (0, 1), (1, 0), (1, 1)])
+    win = np.zeros((64, 64))
+    den = np.zeros((64, 64))
+    w2 = oracle.window2d(128, 1)
+    for (i, j), t in ref["tiles"].items():
+        oy, ox = ref["ys"][i], ref["xs"][j]
+        win += t["patch"][64 - oy:128 - oy, 64 - ox:128 - ox]
+        den += w2[64 - oy:128 - oy, 64 - ox:128 - ox]
+    win /= den
+    g = img.cpu().numpy()[64:128, 64:128]
+    merr = np.linalg.norm(g - win) / np.linalg.norm(win - win.mean())
+    say(f"[burst2560] mosaic window {merr:.2e}")
+    assert merr <= MOSAIC_TOL
