@@ -159,9 +159,9 @@ __device__ __forceinline__ gptr_c uniform_ptr(const void *p) {
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return (gptr_c)(((uint64_t)hi << 32) | lo);
 }
-template <typename T>
-__device__ __forceinline__ T load_global(gptr_c base, unsigned byte_off) {
-    return *(const __attribute__((address_space(1))) T *)(base + byte_off);
+__device__ __forceinline__ float2 load_global_f2(gptr_c base, unsigned byte_off) {
+    const unsigned long long v = *(const __attribute__((address_space(1))) unsigned long long *)(base + byte_off);
+    return make_float2(__uint_as_float((unsigned)v), __uint_as_float((unsigned)(v >> 32)));
 }
 
 // Workgroup id remapped so that consecutive logical ids stay on one XCD:

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
         for (int q = 0; q < GF; ++q) {
             const gptr_c sf = uniform_ptr(sp + (size_t)min(f0 + q, F - 1) * FS);
 #pragma unroll
-            for (int j = 0; j < St::PER; ++j) v[q][j] = load_global<float2>(sf, (unsigned)src[j]);
+            for (int j = 0; j < St::PER; ++j) v[q][j] = load_global_f2(sf, (unsigned)src[j]);
         }
     };
     auto store = [&](int buf, const float2 (&v)[GF][St::PER]) __attribute__((always_inline)) {

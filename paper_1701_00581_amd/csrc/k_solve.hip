@@ -1,13 +1,19 @@
 // Fourier modulus (Eq. 1) and phase (speckle-masking recursion), FP64.
 //
-// One workgroup per patch.  The phasors e(w) of the whole half disk live in
-// LDS.  Frequencies are visited shell by shell (|w|^2 ascending); every w
-// of a shell reads only strictly shorter frequencies, so a shell's w are
-// independent: wave j takes the shell's w number j and j + 8, its lanes
-// split that w's bispectrum samples, and a wave reduction gives
+// One workgroup per patch.  Frequencies are visited shell by shell (|w|^2
+// ascending); every w of a shell reads only strictly shorter frequencies,
+// so a shell's w are independent: wave j takes the shell's w number j and
+// j + 8 (at most 16 w per shell), its lanes split that w's bispectrum
+// samples, and a wave reduction (DPP) gives
 //   z(w) = sum_v e(w - v) e(v) conj B(w, v),  e(w) = z / |z|.
-// The samples of the next shell are loaded into registers while the current
-// shell is computed, so only LDS latency sits on the dependency chain.
+// Since |v| <= R, a shell only reads phasors with |x| <= R or
+// |x| >= |w| - R: those stay in LDS (the inner disk, plus a ring for the
+// annulus), which keeps the workgroup small enough for three per CU.  The
+// sample codes hold the LDS slot of each phasor for the sample's shell
+// (computed on the host), so a lookup is a plain LDS read.  Each phasor is
+// written to the output as soon as it is known.  The samples of
+// the next shells are loaded into registers while the current shell is
+// computed, so only LDS latency sits on the dependency chain.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -17,12 +23,8 @@ namespace {
 
 constexpr int NT = 512;
 constexpr int NWAVE = NT / 64;
-constexpr int MAXW_PER_SHELL_WAVE = 2;   // up to 16 w per shell
-constexpr int DEPTH = 4;                 // shells of samples in flight
-
-template <int N> struct MaxW;
-template <> struct MaxW<64> { static constexpr int v = 1504; };
-template <> struct MaxW<128> { static constexpr int v = 6232; };
+constexpr int WPW = 2;                   // w per wave and shell: 16 per shell
+constexpr int DEPTH = 2;                 // shells of samples in flight
 
 __device__ __forceinline__ double2 unit_or_one(double2 z) {
     const double m = sqrt(z.x * z.x + z.y * z.y);
@@ -30,29 +32,55 @@ __device__ __forceinline__ double2 unit_or_one(double2 z) {
     return make_double2(z.x / m, z.y / m);
 }
 
+// LDS phasor window: inner entries + ring entries (two sizes)
+template <int BIG> struct Win;
+template <> struct Win<0> { static constexpr int INNER = 416, RING = 2560; };
+template <> struct Win<1> { static constexpr int INNER = 512, RING = 3072; };
+
+// Sum over the 64 lanes with DPP row operations; the total lands in lane 63.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_total_lane63(double v) {
+    v += dpp_d<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_d<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_d<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp_d<0x140, 0xf>(v);   // row_mirror: every lane holds its row sum
+    v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// Samples of one shell for this lane: lane l takes samples l, l + 64, ...
+// of the wave's w number m (m < WPW).
 template <int TPL>
 struct ShellRegs {
-    int w[MAXW_PER_SHELL_WAVE];
-    int cnt[MAXW_PER_SHELL_WAVE];
-    unsigned code[MAXW_PER_SHELL_WAVE][TPL];
-    float2 b[MAXW_PER_SHELL_WAVE][TPL];
+    int w[WPW];
+    int cnt[WPW];
+    unsigned code[WPW][TPL];
+    float2 b[WPW][TPL];
 };
 
-template <int N, int TPL>
-__global__ __launch_bounds__(NT) void k_solve(int nW, int nshell, const int *__restrict__ shell_wb,
+template <int N, int TPL, int BIG>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6 : 2))) void k_solve(int nW, int nshell, const int *__restrict__ shell_wb,
+                                              const int *__restrict__ w_slot,
                                               const int *__restrict__ woff, const unsigned *__restrict__ code,
                                               const int *__restrict__ Wxy, const float *__restrict__ power,
                                               const float *__restrict__ mean_spec,
                                               const float2 *__restrict__ bispec, int64_t s_count,
                                               const double *__restrict__ stf, double floor_, int noise_bias,
                                               double *__restrict__ amp, double2 *__restrict__ phasor) {
-    __shared__ double2 e[MaxW<N>::v];
+    __shared__ double2 e[Win<BIG>::INNER + Win<BIG>::RING];
     __shared__ double red[NWAVE];
     const int patch = blockIdx.x;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const float *P = power + (size_t)patch * N * N;
+    double2 *ph_out = phasor + (size_t)patch * nW;
 
     // noise level: mean power where |u| > N/2 + 2 (signed u in [-N/2, N/2))
     double nb = 0.0;
@@ -91,11 +119,15 @@ __global__ __launch_bounds__(NT) void k_solve(int nW, int nshell, const int *__r
         }
         amp[(size_t)patch * nW + i] = a;
     }
-    // seeds (1,0) and (0,1) are W[0] and W[1]
+    // seeds (1,0) and (0,1) are W[0] and W[1], inner entries
     if (tid == 0) {
         const float *m = mean_spec + (size_t)patch * 4;
-        e[0] = unit_or_one(make_double2((double)m[0], (double)m[1]));
-        e[1] = unit_or_one(make_double2((double)m[2], (double)m[3]));
+        const double2 e0 = unit_or_one(make_double2((double)m[0], (double)m[1]));
+        const double2 e1 = unit_or_one(make_double2((double)m[2], (double)m[3]));
+        e[0] = e0;
+        e[1] = e1;
+        ph_out[0] = e0;
+        ph_out[1] = e1;
     }
 
     const float2 *B = bispec + (size_t)patch * s_count;
@@ -104,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_solve(int nW, int nshell, const int *__r
     auto load = [&](int s, ShellRegs<TPL> &r) __attribute__((always_inline)) {
         const int wb = shell_wb[s], nw = shell_wb[s + 1] - wb;
 #pragma unroll
-        for (int m = 0; m < MAXW_PER_SHELL_WAVE; ++m) {
+        for (int m = 0; m < WPW; ++m) {
             const int jj = wave + NWAVE * m;
             const bool has = jj < nw;
             const int w = has ? wb + jj : 0;
@@ -121,31 +153,50 @@ __global__ __launch_bounds__(NT) void k_solve(int nW, int nshell, const int *__r
         }
     };
     auto solve = [&](const ShellRegs<TPL> &r) __attribute__((always_inline)) {
+        if (r.w[0] < 0) return;                   // no w of this shell in this wave
+        double zx[WPW], zy[WPW];
 #pragma unroll
-        for (int m = 0; m < MAXW_PER_SHELL_WAVE; ++m) {
-            if (r.w[m] >= 0) {
-                double zx = 0.0, zy = 0.0;
+        for (int m = 0; m < WPW; ++m) {
+            zx[m] = 0.0;
+            zy[m] = 0.0;
 #pragma unroll
-                for (int i = 0; i < TPL; ++i) {
-                    const int t = lane + 64 * i;
-                    if (t < r.cnt[m]) {
-                        const unsigned cd = r.code[m][i];
-                        const unsigned ia = cd >> 16, ib = cd & 0xffffu;
-                        double2 ea = e[ia & 0x7fffu];
-                        double2 eb = e[ib & 0x7fffu];
-                        if (ia & 0x8000u) ea.y = -ea.y;
-                        if (ib & 0x8000u) eb.y = -eb.y;
-                        const double px = ea.x * eb.x - ea.y * eb.y;
-                        const double py = ea.x * eb.y + ea.y * eb.x;
-                        const double bx = (double)r.b[m][i].x, by = (double)r.b[m][i].y;
-                        // (px + i py) * conj(bx + i by)
-                        zx += px * bx + py * by;
-                        zy += py * bx - px * by;
-                    }
+            for (int i = 0; i < TPL; ++i) {
+                const int t = lane + 64 * i;
+                if (t < r.cnt[m]) {
+                    const unsigned cd = r.code[m][i];
+                    const unsigned ia = cd >> 16, ib = cd & 0xffffu;
+                    double2 ea = e[ia & 0x7fffu];
+                    double2 eb = e[ib & 0x7fffu];
+                    if (ia & 0x8000u) ea.y = -ea.y;
+                    if (ib & 0x8000u) eb.y = -eb.y;
+                    const double px = ea.x * eb.x - ea.y * eb.y;
+                    const double py = ea.x * eb.y + ea.y * eb.x;
+                    const double bx = (double)r.b[m][i].x, by = (double)r.b[m][i].y;
+                    // (px + i py) * conj(bx + i by)
+                    zx[m] += px * bx + py * by;
+                    zy[m] += py * bx - px * by;
                 }
-                zx = wave_sum_d(zx);
-                zy = wave_sum_d(zy);
-                if (lane == 0) e[r.w[m]] = unit_or_one(make_double2(zx, zy));
+            }
+        }
+        double tx[WPW], ty[WPW];
+#pragma unroll
+        for (int m = 0; m < WPW; ++m) {
+            tx[m] = wave_total_lane63(zx[m]);
+            ty[m] = wave_total_lane63(zy[m]);
+        }
+        if (lane == 63) {
+#pragma unroll
+            for (int m = 0; m < WPW; ++m) {
+                if (r.w[m] >= 0) {
+                    const double n = tx[m] * tx[m] + ty[m] * ty[m];
+                    double2 v = make_double2(1.0, 0.0);
+                    if (n > 0.0) {
+                        const double rn = rsqrt(n);
+                        v = make_double2(tx[m] * rn, ty[m] * rn);
+                    }
+                    e[w_slot[r.w[m]]] = v;
+                    ph_out[r.w[m]] = v;
+                }
             }
         }
     };
@@ -153,45 +204,47 @@ __global__ __launch_bounds__(NT) void k_solve(int nW, int nshell, const int *__r
     __syncthreads();
     // shells 1.. in order; the samples of shell s + DEPTH - 1 are loaded
     // while shell s is solved (a ring of DEPTH register sets)
-    ShellRegs<TPL> ring[DEPTH];
+    ShellRegs<TPL> buf[DEPTH];
 #pragma unroll
     for (int d = 0; d < DEPTH - 1; ++d)
-        if (1 + d < nshell) load(1 + d, ring[d]);
+        if (1 + d < nshell) load(1 + d, buf[d]);
     for (int s0 = 1; s0 < nshell; s0 += DEPTH) {
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d) {
             const int s = s0 + d;
             if (s < nshell) {
-                if (s + DEPTH - 1 < nshell) load(s + DEPTH - 1, ring[(d + DEPTH - 1) % DEPTH]);
-                solve(ring[d]);
+                if (s + DEPTH - 1 < nshell) load(s + DEPTH - 1, buf[(d + DEPTH - 1) % DEPTH]);
+                solve(buf[d]);
                 __syncthreads();
             }
         }
     }
-    for (int i = tid; i < nW; i += NT) phasor[(size_t)patch * nW + i] = e[i];
 }
 
-template <int N, int TPL>
+template <int N, int TPL, int BIG>
 hipError_t launch_solve_t(const SolveArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_solve<N, TPL>), dim3(a.patches), dim3(NT), 0, st, a.nW, a.nshell, a.shell_wb,
-                       a.woff, a.code, a.Wxy, a.power, a.mean_spec, a.bispec, a.s_count, a.stf, a.floor,
-                       a.noise_bias, a.amp, a.phasor);
+    hipLaunchKernelGGL((k_solve<N, TPL, BIG>), dim3(a.patches), dim3(NT), 0, st, a.nW, a.nshell, a.shell_wb,
+                       a.w_slot, a.woff, a.code, a.Wxy, a.power, a.mean_spec, a.bispec,
+                       a.s_count, a.stf, a.floor, a.noise_bias, a.amp, a.phasor);
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, int BIG>
 hipError_t launch_solve_n(const SolveArgs &a, hipStream_t st) {
-    if (a.max_sw <= 128) return launch_solve_t<N, 2>(a, st);
-    if (a.max_sw <= 256) return launch_solve_t<N, 4>(a, st);
-    return launch_solve_t<N, 8>(a, st);
+    if (a.max_sw <= 128) return launch_solve_t<N, 2, BIG>(a, st);
+    if (a.max_sw <= 256) return launch_solve_t<N, 4, BIG>(a, st);
+    return launch_solve_t<N, 8, BIG>(a, st);
 }
 
 }  // namespace
 
 hipError_t launch_solve(const SolveArgs &a, hipStream_t st) {
     if (a.patches == 0) return hipSuccess;
-    if (a.max_sw > 512 || a.nW > (a.N == 128 ? MaxW<128>::v : MaxW<64>::v)) return hipErrorInvalidValue;
-    return a.N == 128 ? launch_solve_n<128>(a, st) : launch_solve_n<64>(a, st);
+    if (a.max_sw > 512) return hipErrorInvalidValue;
+    const bool small = a.n_inner <= Win<0>::INNER && a.ring <= Win<0>::RING;
+    if (!small && (a.n_inner > Win<1>::INNER || a.ring > Win<1>::RING)) return hipErrorInvalidValue;
+    if (a.N == 128) return small ? launch_solve_n<128, 0>(a, st) : launch_solve_n<128, 1>(a, st);
+    return small ? launch_solve_n<64, 0>(a, st) : launch_solve_n<64, 1>(a, st);
 }
 
 }  // namespace nvsm

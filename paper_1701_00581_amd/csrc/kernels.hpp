@@ -35,7 +35,9 @@ hipError_t launch_bispec(const BispecArgs &a, hipStream_t st);
 struct SolveArgs {
     int N = 0, patches = 0, nW = 0, nshell = 0, max_sw = 0;
     const int *shell_wb = nullptr, *woff = nullptr, *Wxy = nullptr;
-    const unsigned *code = nullptr;
+    const int *w_slot = nullptr;          // LDS slot of each w's phasor
+    int n_inner = 0, ring = 0;            // phasor window (see plan.hpp)
+    const unsigned *code = nullptr;       // sample codes with LDS slots
     const float *power = nullptr, *mean_spec = nullptr;
     const float2 *bispec = nullptr;
     int64_t s_count = 0;

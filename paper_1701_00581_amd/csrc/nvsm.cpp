@@ -30,8 +30,8 @@ struct DevicePlan {
     HostPlan h;
     int nshell = 0, max_sw = 0;
     std::vector<void *> bufs;
-    int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *items = nullptr, *slot = nullptr,
-        *out_idx = nullptr;
+    int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr,
+        *slot = nullptr, *out_idx = nullptr;
     unsigned *code = nullptr;
     float2 *twiddle = nullptr;
     float *hann = nullptr, *filt = nullptr;
@@ -178,7 +178,8 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
     int max_per_shell = 0;
     for (int s = 0; s < dp->nshell; ++s) max_per_shell = std::max(max_per_shell, h.shell_wb[s + 1] - h.shell_wb[s]);
     for (size_t i = 0; i + 1 < h.woff.size(); ++i) dp->max_sw = std::max(dp->max_sw, h.woff[i + 1] - h.woff[i]);
-    if (max_per_shell > 16 || dp->max_sw > 512) return fail(ctx, NVSM_ERR_INVALID_ARG, "shell too large for the phase kernel");
+    if (max_per_shell > 16 || dp->max_sw > 512 || h.n_inner > 512 || h.ring_size > 3072)
+        return fail(ctx, NVSM_ERR_INVALID_ARG, "shell or phasor window too large for the phase kernel");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NVSM_ERR_HIP, "hipSetDevice failed");
     nvsm_status s;
     std::vector<float2> tw(h.N);
@@ -186,7 +187,8 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
     if ((s = upload(dp.get(), h.W, &dp->W, &msg)) ||
         (s = upload(dp.get(), h.woff, &dp->woff, &msg)) ||
         (s = upload(dp.get(), h.shell_wb, &dp->shell_wb, &msg)) ||
-        (s = upload(dp.get(), h.phase_code, &dp->code, &msg)) ||
+        (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
+        (s = upload(dp.get(), h.phase_slot_code, &dp->code, &msg)) ||
         (s = upload(dp.get(), h.items, &dp->items, &msg)) ||
         (s = upload(dp.get(), h.slot_v, &dp->slot, &msg)) ||
         (s = upload(dp.get(), h.out_idx, &dp->out_idx, &msg)) ||
@@ -263,6 +265,7 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, in
     SolveArgs a;
     a.N = p->patch; a.patches = (int)P; a.nW = (int)(dp->h.W.size() / 2); a.nshell = dp->nshell;
     a.max_sw = dp->max_sw; a.shell_wb = dp->shell_wb; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
+    a.w_slot = dp->w_slot; a.n_inner = dp->h.n_inner; a.ring = dp->h.ring_size;
     a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;
     a.stf = stf; a.floor = p->stf_floor; a.noise_bias = p->noise_bias; a.amp = amp;
     a.phasor = (double2 *)phasor;

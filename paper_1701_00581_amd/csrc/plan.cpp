@@ -123,6 +123,53 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     }
     pl->shell_wb.push_back(nW);
     pl->s_count = pl->woff[nW];
+
+    // phasor window: inner entries |w| <= R, the rest in a ring; each
+    // shell's lowest ring entry read comes from its sample codes
+    pl->n_inner = 0;
+    while (pl->n_inner < nW) {
+        const int x = pl->W[2 * pl->n_inner], y = pl->W[2 * pl->n_inner + 1];
+        if (x * x + y * y > R * R) break;
+        ++pl->n_inner;
+    }
+    const int nshell = (int)pl->shell_wb.size() - 1;
+    std::vector<int32_t> lo(nshell);
+    int span = 1;
+    for (int sh = 0; sh < nshell; ++sh) {
+        int l = pl->shell_wb[sh];
+        for (int32_t t = pl->woff[pl->shell_wb[sh]]; t < pl->woff[pl->shell_wb[sh + 1]]; ++t) {
+            const int ia = (int)((pl->phase_code[t] >> 16) & 0x7fffu), ib = (int)(pl->phase_code[t] & 0x7fffu);
+            if (ia >= pl->n_inner) l = std::min(l, ia);
+            if (ib >= pl->n_inner) l = std::min(l, ib);
+        }
+        lo[sh] = std::max(l, pl->n_inner);
+        span = std::max(span, pl->shell_wb[sh + 1] - lo[sh]);
+    }
+    pl->ring_size = span;
+    pl->shell_ring_off.resize(nshell);
+    for (int sh = 0; sh < nshell; ++sh)
+        pl->shell_ring_off[sh] = (lo[sh] - pl->n_inner) / span * span;
+    auto slot_of = [&](int i, int ro) {
+        if (i < pl->n_inner) return i;
+        int q = i - pl->n_inner - ro;
+        if (q >= span) q -= span;
+        return pl->n_inner + q;
+    };
+    pl->phase_slot_code.resize(pl->phase_code.size());
+    pl->w_slot.resize(nW);
+    for (int sh = 0; sh < nshell; ++sh) {
+        const int ro = pl->shell_ring_off[sh];
+        for (int w = pl->shell_wb[sh]; w < pl->shell_wb[sh + 1]; ++w) {
+            pl->w_slot[w] = slot_of(w, ro);
+            for (int32_t t = pl->woff[w]; t < pl->woff[w + 1]; ++t) {
+                const uint32_t c = pl->phase_code[t];
+                const uint32_t ca = c >> 16, cb = c & 0xffffu;
+                const uint32_t sa = (uint32_t)slot_of((int)(ca & 0x7fffu), ro) | (ca & 0x8000u);
+                const uint32_t sb = (uint32_t)slot_of((int)(cb & 0x7fffu), ro) | (cb & 0x8000u);
+                pl->phase_slot_code[t] = (sa << 16) | sb;
+            }
+        }
+    }
     if (pl->s_count >= (int64_t)1 << 31) { *err = "bispectrum set too large"; return false; }
 
     // Bispectrum work: 8x8 blocks of w; the union of their v, cut into

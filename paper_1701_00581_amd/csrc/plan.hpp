@@ -32,6 +32,16 @@ struct HostPlan {
     std::vector<int32_t> W;
     std::vector<int32_t> woff;          // |W|+1
     std::vector<int32_t> shell_wb;      // shells+1: W range of each shell
+    // Phasor window of the phase solve: W entries [0, n_inner) (|w| <= R)
+    // stay resident; the others live in a ring of ring_size entries.  A
+    // shell reads ring entries >= its lowest index, so entry i sits at ring
+    // slot (i - n_inner - shell_ring_off[s]) reduced once by ring_size.
+    int n_inner = 0, ring_size = 0;
+    std::vector<int32_t> shell_ring_off;  // shells: multiple of ring_size
+    // phase_code with W indices replaced by the LDS slot each phasor has
+    // while the sample's shell is solved, and the slot of every w.
+    std::vector<uint32_t> phase_slot_code;
+    std::vector<int32_t> w_slot;
     // Per S entry: lookup codes of (w - v) and v in the phasor table
     // (bits 0..14 index into W, bit 15 set = use the conjugate).
     std::vector<uint32_t> phase_code;
