@@ -2,20 +2,23 @@
 // frames of the burst (speckle masking; the hot loop of the path).
 //
 // Work decomposition (see plan.cpp): a workgroup owns one patch and one
-// work item = an 8x8 block of w (one w per lane) times up to 4 x 32 values
-// of v (one v per wave slot, the same for all 64 lanes).  Per frame:
-//   * the region of I holding every w - v of the item, the slot values
-//     I(v) and the block's I(w) are staged in LDS, GF frames at a time,
-//     double buffered (the next group is fetched while this one is used);
-//   * each slot costs one LDS gather, half a broadcast read and 8 FP32
-//     FMA/MUL per lane.
+// work item = a group of up to 64 w close in angle and radius (one w per
+// lane) times 4 x NS values of v (one v per wave slot, the same for all 64
+// lanes).  Per frame, and for the next frame while this one is computed:
+//   * the region of I holding every w - v of the item goes to LDS by direct
+//     16-byte global-to-LDS loads (no registers involved), double buffered;
+//   * each lane loads its own I(w), and lane l the slot value I(v) of slot
+//     l mod 16, into registers; a slot's value reaches every lane through a
+//     DPP row broadcast folded into the multiplies that use it.
+// Each slot then costs one 64-bit LDS gather and 8 FP32 FMA/MUL per lane.
+// LDS bandwidth is the other limit of this loop (a 64-bit read returns 16
+// lanes per clock), so I(v) and I(w) stay out of LDS and the lanes of a
+// group are laid out for conflict-free gathers (see plan.cpp).
 // Accumulators stay in registers for the whole burst: a plain FP32 sum over
 // KB frames, folded into a Kahan (sum, compensation) pair every KB frames.
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
-
-#include <cstdlib>
 
 namespace nvsm {
 
@@ -24,154 +27,223 @@ namespace {
 constexpr int NT = BS_WAVES * 64;
 constexpr int KB = 20;                     // frames per compensated block
 
-// LDS staging record of one frame: the item's region of I (w - v values),
-// then the slot values I(v) of the 4 waves, then the 64 I(w) of the block.
-template <int K> struct Stage {
-    static constexpr int RMAX = bs_region_cap(K);               // padded region extent
-    static constexpr int NV = BS_WAVES * K;
-    static constexpr int SZ = RMAX + NV + 64 + 1;               // float2 per frame (+1 sink)
-    static constexpr int PER = (RMAX + NV + 64 + NT - 1) / NT;  // loads per thread per frame
-};
+// LDS record of one frame: the item's region of I (w - v values, row pitch =
+// region width), moved in chunks of 128 complex values (one wave-wide
+// 16-byte load each).
+constexpr int SZ = BS_MAX_REGION;                              // float2 per frame
+constexpr int CH = SZ / 128;                                   // chunks per frame
+constexpr int PERW = (CH + BS_WAVES - 1) / BS_WAVES;           // chunks per wave
+static_assert(SZ % 128 == 0, "region capacity must be whole chunks");
 
-template <int N, int K, int GF>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec(
-    const float2 *__restrict__ spec, int F, int n_items, int total, const int *__restrict__ items,
-    const int *__restrict__ slot, const int *__restrict__ out_idx, float2 *__restrict__ bispec,
-    int64_t s_count, float invF) {
+typedef __attribute__((address_space(3))) void *lds_ptr;
+typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+
+__device__ __forceinline__ float2 as_f2(u32x2 v) { return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1])); }
+
+// b taken from lane K of this lane's row of 16 (DPP row_newbcast), times a;
+// and acc + that product.  Arithmetic only; EXEC must be full.
+template <int K>
+__device__ __forceinline__ float mul_bc(float b, float a) {
+    float r;
+    asm("v_mul_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(r) : "v"(b), "v"(a), "i"(K));
+    return r;
+}
+template <int K>
+__device__ __forceinline__ float fmac_bc(float acc, float b, float a) {
+    asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(acc) : "v"(b), "v"(a), "i"(K));
+    return acc;
+}
+
+// Waits until at most n vector-memory loads of this wave are in flight
+// (they complete in order).
+template <int n>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    // s_waitcnt: vmcnt[3:0] | expcnt[6:4] = 7 | lgkmcnt[11:8] = 15 | vmcnt[5:4] at [15:14]
+    __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+// fn(integral_constant<k>) for k = 0 .. n - 1, unrolled at compile time.
+template <int n, int k = 0, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&fn) {
+    if constexpr (k < n) {
+        fn(std::integral_constant<int, k>{});
+        static_for<n, k + 1>(fn);
+    }
+}
+
+// Waits until this wave's LDS reads are done: lgkmcnt(0), other counters free.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (3 << 14)); }
+
+// One work item with NS slots per wave (NS a multiple of 4, <= K).  Slots
+// past a chunk's real v hold a valid v of the item; their results are
+// dropped.  The frame's slot loop is one branch-free block, so its LDS reads
+// can be issued ahead.
+template <int N, int K, int NS>
+__device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const float2 *__restrict__ spec, int F,
+                                            int patch, int g, const int *__restrict__ it,
+                                            const int *__restrict__ group_xy, const int *__restrict__ slot,
+                                            const int *__restrict__ out_idx, float2 *__restrict__ bispec,
+                                            int64_t s_count, float invF) {
     constexpr int HALF = N / 2;
-    using St = Stage<K>;
-    __shared__ float2 lds[2 * GF * St::SZ];
-
-    const int L = xcd_remap(blockIdx.x, total);
-    const int patch = L / n_items, g = L % n_items;
-    const int *it = items + g * BS_ITEM_INTS;
-    const int bx0 = it[0], by0 = it[1], rx0 = it[2], ry0 = it[3], rw = it[4], npts = it[6];
-    const int pitch = it[7], rext = pitch * it[5];   // LDS row pitch and extent of the region
+    constexpr int FS = SpecRows<N>::FS;
+    constexpr int FB = FS * (int)sizeof(float2);               // bytes per stored frame
+    const int *gxy = group_xy + it[0] * (2 * BS_LANES);
+    const int rx0 = it[1], ry0 = it[2], npts = it[5], pitch = it[6];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
-    const int ns = it[8 + wave];                      // slots of this wave
-    const int wx = bx0 + (lane & 7), wy = by0 + (lane >> 3);
+    const int wx = gxy[2 * lane], wy = gxy[2 * lane + 1];
     const int lane_base = (wy - ry0) * pitch + (wx - rx0);
     const int *sl = slot + (size_t)(g * BS_WAVES + wave) * K * 2;
 
-    int addr[K];
+    constexpr int NQ = (NS + 15) / 16;           // rows of 16 slot values
+    int addr[NS];     // LDS byte offset of I(w - v) in the region, per slot
 #pragma unroll
-    for (int k = 0; k < K; ++k) addr[k] = lane_base - sl[2 * k];
+    for (int k = 0; k < NS; ++k) addr[k] = (lane_base - sl[2 * k]) * (int)sizeof(float2);
+    int sol[NQ];      // byte offset of I(v) of slot 16 q + lane mod 16 in a frame's record
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sol[q] = sl[2 * min(16 * q + (lane & 15), K - 1) + 1] * (int)sizeof(float2);
+    const int wo = ((wy + SPEC_NEG_ROWS) * N + (wx & (N - 1))) * (int)sizeof(float2);   // I(w)
 
-    // The values this thread stages every frame: offsets in the frame's
-    // stored spectrum record (always inside it; region points beyond the
-    // stored rows are never used by a sample and read a clamped row) and
-    // byte offsets in the LDS record (the last slot of the record is a sink
-    // for threads with nothing to stage).  32-bit byte offsets on a uniform
-    // frame base let the loads use scalar-base addressing.
-    constexpr int FS = SpecRows<N>::FS;
-    const int nstage = npts + St::NV + 64;
-    int src[St::PER], dst[St::PER];
+    // Region staging: wave j moves chunks j, j + 4, ... of the region; lane
+    // l of chunk c moves the complex values 128 c + 2 l and + 1.  The pitch
+    // and the region's x0 are even (see plan.cpp), so each pair is one row,
+    // two adjacent stored columns, 16-byte aligned.  src[] holds each lane's
+    // byte offset in the frame's record: region points beyond the stored
+    // rows are never used by a sample and read a clamped row; pairs past
+    // the region read offset 0 into the unused tail of the LDS record.
+    // Every wave issues all PERW loads, so that their number is known when
+    // the compiler places the waits for the loads issued before them.
+    unsigned src[PERW];
 #pragma unroll
-    for (int j = 0; j < St::PER; ++j) {
-        const int i = tid + NT * j;
-        int so = 0, d = St::SZ - 1;
-        if (i < npts) {
-            const int ix = i % rw, iy = i / rw, x = rx0 + ix;
+    for (int j = 0; j < PERW; ++j) {
+        const int e = 128 * (wave + BS_WAVES * j) + 2 * lane;
+        int o = 0;
+        if (e < npts) {
+            const int ix = e % pitch, iy = e / pitch, x = rx0 + ix;
             const int y = min(ry0 + iy, HALF - 1);
-            so = (y + SPEC_NEG_ROWS) * N + (x & (N - 1));
-            d = iy * pitch + ix;
-        } else if (i < npts + St::NV) {
-            so = slot[((size_t)(g * BS_WAVES) * K + (i - npts)) * 2 + 1];
-            d = rext + (i - npts);
-        } else if (i < nstage) {
-            const int l = i - npts - St::NV;
-            so = (by0 + (l >> 3) + SPEC_NEG_ROWS) * N + ((bx0 + (l & 7)) & (N - 1));
-            d = rext + St::NV + l;
+            o = (y + SPEC_NEG_ROWS) * N + (x & (N - 1));
         }
-        src[j] = so * (int)sizeof(float2);
-        dst[j] = d * (int)sizeof(float2);
+        src[j] = (unsigned)(o * (int)sizeof(float2));
     }
 
-    const float2 *sp = spec + (size_t)patch * F * FS;
-    auto fetch = [&](int f0, float2 (&v)[GF][St::PER]) __attribute__((always_inline)) {
+    // the patch's spectra as one buffer resource; frame f at byte f * FB
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(spec + (size_t)patch * F * FS), (short)0, F * FB, 0x00020000);
+    // the region loads of frame f into buf
+    auto fetch = [&](int f, float2 *buf) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < GF; ++q) {
-            const gptr_c sf = uniform_ptr(sp + (size_t)min(f0 + q, F - 1) * FS);
-#pragma unroll
-            for (int j = 0; j < St::PER; ++j) v[q][j] = load_global_f2(sf, (unsigned)src[j]);
-        }
+        for (int j = 0; j < PERW; ++j)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_ptr)(buf + 128 * (wave + BS_WAVES * j)), 16,
+                                                     (int)src[j], f * FB, 0, 0);
     };
-    auto store = [&](int buf, const float2 (&v)[GF][St::PER]) __attribute__((always_inline)) {
+    auto load_vals = [&](int f, float2 &cw, float2 (&bv)[NQ]) __attribute__((always_inline)) {
+        cw = as_f2(__builtin_amdgcn_raw_buffer_load_b64(rsrc, wo, f * FB, 0));
 #pragma unroll
-        for (int q = 0; q < GF; ++q)
-#pragma unroll
-            for (int j = 0; j < St::PER; ++j)
-                *(float2 *)((char *)(lds + (buf * GF + q) * St::SZ) + dst[j]) = v[q][j];
+        for (int q = 0; q < NQ; ++q) bv[q] = as_f2(__builtin_amdgcn_raw_buffer_load_b64(rsrc, sol[q], f * FB, 0));
     };
 
-    float2 t[K], s[K], c[K];
+    float2 t[NS], s[NS], c[NS];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < NS; ++k) {
         t[k] = make_float2(0.f, 0.f);
         s[k] = make_float2(0.f, 0.f);
         c[k] = make_float2(0.f, 0.f);
     }
 
-    {
-        float2 v[GF][St::PER];
-        fetch(0, v);
-        store(0, v);
-    }
-    __syncthreads();
+    float2 cw, bv[NQ];
+    fetch(0, lds0);
+    load_vals(0, cw, bv);
+    wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
 
-    // Every slot is computed (slots past this wave's count hold a valid v
-    // of the item and their results are dropped), so the frame is one
-    // branch-free block and its LDS reads can be issued ahead.
-    auto one_frame = [&](const float2 *rg, int f) __attribute__((always_inline)) {
-        const float2 cw = rg[rext + St::NV + lane];
-        const float2 *vrow = rg + rext + wave * K;
+    // Frame f from LDS buffer rg with its values in cw, bv.  The next
+    // frame's region goes to the other buffer meanwhile; its values replace
+    // cw and bv once this frame's slot loop has used them.  Before the
+    // barrier only the region loads are awaited (loads complete in order,
+    // the 1 + NQ value loads were issued last).  Loads are issued without
+    // branches, so the compiler knows how many are in flight at each use.
+    auto frame = [&](int f, const float2 *rg, float2 *nxt) __attribute__((always_inline)) {
+        // the last frame fetches itself again (unused) rather than branch
+        const int fn = min(f + 1, F - 1);
+        fetch(fn, nxt);
+        const char *rb = (const char *)rg;
+        float nby[NQ];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float2 bv = vrow[k];
-            const float2 a = rg[addr[k]];
-            // p = I(w - v) I(v);  t += p conj I(w), as one FMA chain
-            const float pr = fmaf(a.x, bv.x, -(a.y * bv.y));
-            const float pi = fmaf(a.x, bv.y, a.y * bv.x);
+        for (int q = 0; q < NQ; ++q) nby[q] = -bv[q].y;
+        const float ncy = -cw.y;
+        // p = I(w - v) I(v);  t += p conj I(w)
+        auto slot_k = [&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value, q = k / 16, r = k % 16;
+            const float2 a = *(const float2 *)(rb + addr[k]);
+            const float pr = fmac_bc<r>(mul_bc<r>(nby[q], a.y), bv[q].x, a.x);
+            const float pi = fmac_bc<r>(mul_bc<r>(bv[q].x, a.y), bv[q].y, a.x);
             t[k].x = fmaf(pr, cw.x, fmaf(pi, cw.y, t[k].x));
-            t[k].y = fmaf(pi, cw.x, fmaf(-pr, cw.y, t[k].y));
-        }
+            t[k].y = fmaf(pi, cw.x, fmaf(pr, ncy, t[k].y));
+        };
+        static_for<NS>(slot_k);
         if ((f + 1) % KB == 0 || f + 1 == F) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < NS; ++k) {
                 kahan_add(s[k].x, c[k].x, t[k].x);
                 kahan_add(s[k].y, c[k].y, t[k].y);
                 t[k] = make_float2(0.f, 0.f);
             }
         }
-    };
-    auto group = [&](int f0, auto bufc) __attribute__((always_inline)) {
-        constexpr int BUF = decltype(bufc)::value;
-        float2 nxt[GF][St::PER];
-        const bool more = f0 + GF < F;
-        if (more) fetch(f0 + GF, nxt);
-#pragma unroll
-        for (int q = 0; q < GF; ++q)
-            if (f0 + q < F) one_frame(lds + (BUF * GF + q) * St::SZ, f0 + q);
-        if (more) store(1 - BUF, nxt);
-        __syncthreads();
+        load_vals(fn, cw, bv);
+        wait_vm<1 + NQ>();
+        wait_lds();
+        __builtin_amdgcn_s_barrier();
     };
 
-    for (int f = 0; f < F; f += 2 * GF) {
-        group(f, std::integral_constant<int, 0>{});
-        if (f + GF < F) group(f + GF, std::integral_constant<int, 1>{});
+    for (int f = 0; f < F; f += 2) {
+        frame(f, lds0, lds1);
+        if (f + 1 < F) frame(f + 1, lds1, lds0);
     }
+    wait_vm<0>();
 
     const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
     float2 *bo = bispec + (size_t)patch * s_count;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (k < ns) {
-            const int o = oi[k * 64];
-            if (o >= 0) bo[o] = make_float2((s[k].x - c[k].x) * invF, (s[k].y - c[k].y) * invF);
-        }
+    for (int k = 0; k < NS; ++k) {
+        const int o = oi[k * 64];
+        if (o >= 0) bo[o] = make_float2((s[k].x - c[k].x) * invF, (s[k].y - c[k].y) * invF);
     }
+}
+
+// Runs the item with its slot count (one of 4, 8, ..., Q * 4).
+template <int N, int K, int Q>
+__device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *lds1, const float2 *spec, int F,
+                                                int patch, int g, const int *it, const int *group_xy,
+                                                const int *slot, const int *out_idx, float2 *bispec,
+                                                int64_t s_count, float invF) {
+    if constexpr (Q > 0) {
+        if (nq == Q)
+            bispec_item<N, K, 4 * Q>(lds0, lds1, spec, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
+                                     invF);
+        else
+            bispec_dispatch<N, K, Q - 1>(nq, lds0, lds1, spec, F, patch, g, it, group_xy, slot, out_idx, bispec,
+                                         s_count, invF);
+    }
+}
+
+template <int N, int K>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec(
+    const float2 *__restrict__ spec, int F, int n_items, int total, const int *__restrict__ items,
+    const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
+    float2 *__restrict__ bispec, int64_t s_count, float invF) {
+    // two separate arrays, so that loads into one are known not to touch
+    // the other
+    __shared__ float2 lds0[SZ];
+    __shared__ float2 lds1[SZ];
+    const int L = xcd_remap(blockIdx.x, total);
+    const int patch = L / n_items, g = L % n_items;
+    const int *it = items + g * BS_ITEM_INTS;
+    const int nq = __builtin_amdgcn_readfirstlane(it[8]) >> 2;   // the item's slots per wave / 4
+    bispec_dispatch<N, K, K / 4>(nq, lds0, lds1, spec, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
+                                 invF);
 }
 
 }  // namespace
@@ -179,24 +251,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
 hipError_t launch_bispec(const BispecArgs &a, hipStream_t st) {
     const int total = a.patches * a.n_items;
     if (total == 0) return hipSuccess;
-    static const int gf = [] {
-        const char *e = getenv("NVSM_BISPEC_GF");
-        int v = e ? atoi(e) : 1;
-        return (v == 1 || v == 2 || v == 4) ? v : 1;
-    }();
-#define NVSM_LAUNCH_BS(NN, KK, GG)                                                                          \
-    hipLaunchKernelGGL((k_bispec<NN, KK, GG>), dim3(total), dim3(NT), 0, st, a.spectra, a.F, a.n_items, total, \
-                       a.items, a.slot_v, a.out_idx, a.bispec, a.s_count, 1.0f / a.F)
-#define NVSM_LAUNCH_G(NN, KK)                                                                   \
-    if (gf == 1) NVSM_LAUNCH_BS(NN, KK, 1); else if (gf == 2) NVSM_LAUNCH_BS(NN, KK, 2); else NVSM_LAUNCH_BS(NN, KK, 4);
+#define NVSM_LAUNCH_BS(NN, KK)                                                                             \
+    hipLaunchKernelGGL((k_bispec<NN, KK>), dim3(total), dim3(NT), 0, st, a.spectra, a.F, a.n_items, total, \
+                       a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, 1.0f / a.F)
     if (a.slots == 16) {
-        if (a.N == 128) { NVSM_LAUNCH_G(128, 16) } else { NVSM_LAUNCH_G(64, 16) }
+        if (a.N == 128) NVSM_LAUNCH_BS(128, 16); else NVSM_LAUNCH_BS(64, 16);
     } else if (a.slots == 24) {
-        if (a.N == 128) { NVSM_LAUNCH_G(128, 24) } else { NVSM_LAUNCH_G(64, 24) }
+        if (a.N == 128) NVSM_LAUNCH_BS(128, 24); else NVSM_LAUNCH_BS(64, 24);
     } else {
         return hipErrorInvalidValue;
     }
-#undef NVSM_LAUNCH_G
 #undef NVSM_LAUNCH_BS
     return hipGetLastError();
 }

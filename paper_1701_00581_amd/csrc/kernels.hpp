@@ -26,7 +26,7 @@ struct BispecArgs {
     int N = 0;
     const float2 *spectra = nullptr;
     int F = 0, patches = 0, n_items = 0, slots = 0;
-    const int *items = nullptr, *slot_v = nullptr, *out_idx = nullptr;
+    const int *items = nullptr, *group_xy = nullptr, *slot_v = nullptr, *out_idx = nullptr;
     float2 *bispec = nullptr;             // [P][|S|]
     int64_t s_count = 0;
 };

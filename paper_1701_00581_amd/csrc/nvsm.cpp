@@ -31,7 +31,7 @@ struct DevicePlan {
     int nshell = 0, max_sw = 0;
     std::vector<void *> bufs;
     int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr,
-        *slot = nullptr, *out_idx = nullptr;
+        *group_xy = nullptr, *slot = nullptr, *out_idx = nullptr;
     unsigned *code = nullptr;
     float2 *twiddle = nullptr;
     float *hann = nullptr, *filt = nullptr;
@@ -190,6 +190,7 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
         (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
         (s = upload(dp.get(), h.phase_slot_code, &dp->code, &msg)) ||
         (s = upload(dp.get(), h.items, &dp->items, &msg)) ||
+        (s = upload(dp.get(), h.group_xy, &dp->group_xy, &msg)) ||
         (s = upload(dp.get(), h.slot_v, &dp->slot, &msg)) ||
         (s = upload(dp.get(), h.out_idx, &dp->out_idx, &msg)) ||
         (s = upload(dp.get(), tw, &dp->twiddle, &msg)) ||
@@ -253,7 +254,7 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
     if (e != hipSuccess || bispec == nullptr) return e;
     BispecArgs b;
     b.N = p->patch; b.spectra = a.spectra; b.F = F; b.patches = (int)z.P;
-    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.slot_v = dp->slot; b.out_idx = dp->out_idx;
+    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy; b.slot_v = dp->slot; b.out_idx = dp->out_idx;
     b.bispec = (float2 *)bispec; b.s_count = z.S;
     StageTimer t(ctx, ST_BISPEC, st);
     return launch_bispec(b, st);

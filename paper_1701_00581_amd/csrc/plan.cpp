@@ -172,74 +172,171 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     }
     if (pl->s_count >= (int64_t)1 << 31) { *err = "bispectrum set too large"; return false; }
 
-    // Bispectrum work: 8x8 blocks of w; the union of their v, cut into
-    // balanced chunks of <= K, BS_WAVES chunks per workgroup.
-    const int half = N / 2;
-    const int nbx = N / BS_BLOCK;
-    std::map<std::pair<int, int>, std::vector<int>> blocks;  // (cy, cx) -> w ids
-    for (int i = 0; i < nW; ++i) {
-        int cx = (pl->W[2 * i] + half) / BS_BLOCK, cy = pl->W[2 * i + 1] / BS_BLOCK;
-        blocks[{cy, cx}].push_back(i);
+    // Bispectrum work.  Lanes of a wave hold a group of up to 64 w that lie
+    // close together in angle and radius: for |w| well above R, S(w) is the
+    // part of the |v| <= R disk on w's side of a line through the origin
+    // normal to w, so w of similar direction share most of their v and the
+    // union of their sets (the v slots the wave runs) is little larger
+    // than each set.  Groups: radial bands (8 wide up to 24, then about 20
+    // wide), each sorted by angle and cut into equal groups of <= 64.
+    std::vector<int> edges = {0};
+    for (int e = 8; e <= 24; e += 8)
+        if (e < uc + 1) edges.push_back(e);
+    {
+        const int lo = edges.back(), parts = std::max(1, (int)std::lround((uc + 1 - lo) / 20.0));
+        for (int q = 1; q <= parts; ++q) edges.push_back(lo + (uc + 1 - lo) * q / parts);
     }
-    (void)nbx;
+    std::vector<std::vector<int>> groups;
+    for (size_t bnd = 0; bnd + 1 < edges.size(); ++bnd) {
+        const double r0 = edges[bnd], r1 = edges[bnd + 1];
+        std::vector<std::pair<double, int>> ws;
+        for (int i = 0; i < nW; ++i) {
+            const double r = std::sqrt((double)(pl->W[2 * i] * pl->W[2 * i] + pl->W[2 * i + 1] * pl->W[2 * i + 1]));
+            if (r >= r0 && r < r1) ws.push_back({std::atan2((double)pl->W[2 * i + 1], (double)pl->W[2 * i]), i});
+        }
+        if (ws.empty()) continue;
+        std::sort(ws.begin(), ws.end());
+        const int n = (int)ws.size(), ng = (n + BS_LANES - 1) / BS_LANES;
+        for (int q = 0; q < ng; ++q) {
+            std::vector<int> gw;
+            for (int j = (int)((int64_t)n * q / ng); j < (int)((int64_t)n * (q + 1) / ng); ++j) gw.push_back(ws[j].second);
+            groups.push_back(gw);
+        }
+    }
+    pl->n_groups = (int)groups.size();
+    pl->group_xy.assign((size_t)pl->n_groups * BS_LANES * 2, 0);
     pl->items.clear();
     pl->slot_v.clear();
     pl->out_idx.clear();
     pl->computed_terms = 0;
     int64_t covered = 0;
-    for (auto &kv : blocks) {
-        const int by0 = kv.first.first * BS_BLOCK;
-        const int bx0 = kv.first.second * BS_BLOCK - half;
-        // lane -> w id, and the rank of each v inside S(w)
-        int lane_w[BS_LANES];
-        std::fill(lane_w, lane_w + BS_LANES, -1);
-        std::vector<std::unordered_map<int, int>> rank(BS_LANES);
+    pl->max_region = 0;
+    for (int gi = 0; gi < pl->n_groups; ++gi) {
+        const std::vector<int> &gset = groups[gi];
+        int gx0 = 1 << 20, gx1 = -(1 << 20), gy0 = 1 << 20, gy1 = -(1 << 20);
         std::map<std::pair<int, int>, int> uni;  // (vy, vx) sorted union
-        for (int i : kv.second) {
-            int lane = (pl->W[2 * i + 1] - by0) * BS_BLOCK + (pl->W[2 * i] - bx0);
-            lane_w[lane] = i;
-            for (size_t j = 0; j < Sw[i].size() / 2; ++j) {
-                int vx = Sw[i][2 * j], vy = Sw[i][2 * j + 1];
-                rank[lane][(vy + 64) * 256 + (vx + 64)] = (int)j;
-                uni[{vy, vx}] = 1;
-            }
+        for (int i : gset) {
+            const int wx = pl->W[2 * i], wy = pl->W[2 * i + 1];
+            gx0 = std::min(gx0, wx); gx1 = std::max(gx1, wx);
+            gy0 = std::min(gy0, wy); gy1 = std::max(gy1, wy);
+            for (size_t j = 0; j < Sw[i].size() / 2; ++j) uni[{Sw[i][2 * j + 1], Sw[i][2 * j]}] = 1;
         }
         std::vector<std::pair<int, int>> U;  // (vx, vy)
         for (auto &u : uni) U.push_back({u.first.second, u.first.first});
         if (U.empty()) continue;
+        // Items: full ones (BS_WAVES chunks of K slots), then one for the
+        // rest, whose waves all run ns slots (ns the smallest multiple of 4
+        // that holds a quarter of the rest); chunks balanced within an item.
         const int nU = (int)U.size();
-        const int nchunk = (nU + K - 1) / K;
-        const int ngroup = (nchunk + BS_WAVES - 1) / BS_WAVES;
-        // balanced chunk sizes
-        std::vector<int> cstart(nchunk + 1, 0);
-        for (int c = 0; c < nchunk; ++c) cstart[c + 1] = cstart[c] + nU / nchunk + (c < nU % nchunk ? 1 : 0);
-        for (int g = 0; g < ngroup; ++g) {
-            int c0 = g * BS_WAVES, c1 = std::min(nchunk, c0 + BS_WAVES);
+        struct Item { int u0, m, ns, rx0, ry0, rw, rh; };
+        std::vector<Item> gitems;
+        int maxw = 0;
+        for (int u0 = 0; u0 < nU; u0 += BS_WAVES * K) {
+            const int m = std::min(nU - u0, BS_WAVES * K);
+            const int ns = std::min(K, 4 * (((m + BS_WAVES - 1) / BS_WAVES + 3) / 4));
             int vxmin = 1 << 20, vxmax = -(1 << 20), vymin = 1 << 20, vymax = -(1 << 20);
-            for (int u = cstart[c0]; u < cstart[c1]; ++u) {
+            for (int u = u0; u < u0 + m; ++u) {
                 vxmin = std::min(vxmin, U[u].first); vxmax = std::max(vxmax, U[u].first);
                 vymin = std::min(vymin, U[u].second); vymax = std::max(vymax, U[u].second);
             }
-            int rx0 = bx0 - vxmax, ry0 = by0 - vymax;
-            int rw = (bx0 + BS_BLOCK - 1 - vxmin) - rx0 + 1;
-            int rh = (by0 + BS_BLOCK - 1 - vymin) - ry0 + 1;
-            const int pitch = bs_region_pitch(rw);
-            if (pitch * rh > bs_region_cap(K)) { *err = "bispectrum region too large"; return false; }
-            int32_t it[BS_ITEM_INTS] = {bx0, by0, rx0, ry0, rw, rh, rw * rh, pitch, 0, 0, 0, 0};
+            // x0 even: region pairs (x, x + 1) never straddle column 0
+            const int rx0 = (gx0 - vxmax) & ~1, ry0 = gy0 - vymax;
+            const int rw = gx1 - vxmin - rx0 + 1, rh = gy1 - vymin - ry0 + 1;
+            gitems.push_back({u0, m, ns, rx0, ry0, rw, rh});
+            maxw = std::max(maxw, rw);
+        }
+        // One row pitch for all items of the group, even (the kernel moves
+        // the region in pairs of columns).  A lane reads LDS at
+        // (wy - ry0) pitch + (wx - rx0) - (slot offset), so the bank of
+        // every gather follows key = (wx + pitch wy) mod 32 up to a shift
+        // common to the wave.  A 64-bit LDS read serves 16 lanes per pass (32
+        // on a 64-bank LDS): the pitch (one of the even values from the
+        // widest region up to 32 more, within the LDS capacity) is the one
+        // whose keys spread most evenly over the group
+        // (at most 4 w per key mod 16, then 2 per key), and lanes are then
+        // assigned so that each run of 16 lanes has distinct key mod 16 and,
+        // where the keys allow, each run of 32 distinct key.
+        int maxh = 0;
+        for (const Item &gt : gitems) maxh = std::max(maxh, gt.rh);
+        int pitch = maxw + (maxw & 1), best = 1 << 30;
+        for (int cand = maxw + (maxw & 1); cand < maxw + 33; cand += 2) {
+            if (cand * maxh > BS_MAX_REGION) break;
+            int c16[16] = {}, c32[32] = {};
+            for (int i : gset) {
+                const int key = ((pl->W[2 * i] + cand * pl->W[2 * i + 1]) % 32 + 32) % 32;
+                ++c32[key];
+                ++c16[key & 15];
+            }
+            int score = 0;
+            for (int k = 0; k < 16; ++k) score += 4 * std::max(0, c16[k] - 4);
+            for (int k = 0; k < 32; ++k) score += std::max(0, c32[k] - 2);
+            if (score < best) { best = score; pitch = cand; }
+        }
+        int lane_w[BS_LANES];
+        std::fill(lane_w, lane_w + BS_LANES, -1);
+        {
+            // bucket by key mod 16, each bucket alternating its two key
+            // classes, dealt to the 4 runs of 16 lanes in order
+            std::vector<std::vector<int>> bucket(16);
+            for (int k16 = 0; k16 < 16; ++k16) {
+                std::vector<int> a, b;
+                for (int i : gset) {
+                    const int key = ((pl->W[2 * i] + pitch * pl->W[2 * i + 1]) % 32 + 32) % 32;
+                    if ((key & 15) == k16) (key < 16 ? a : b).push_back(i);
+                }
+                if (a.size() < b.size()) std::swap(a, b);
+                for (size_t j = 0; j < a.size(); ++j) {
+                    bucket[k16].push_back(a[j]);
+                    if (j < b.size()) bucket[k16].push_back(b[j]);
+                }
+            }
+            std::vector<int> rest;
+            for (int k16 = 0; k16 < 16; ++k16) {
+                for (size_t j = 0; j < bucket[k16].size(); ++j) {
+                    if (j < 4) lane_w[16 * j + k16] = bucket[k16][j];
+                    else rest.push_back(bucket[k16][j]);
+                }
+            }
+            for (int lane = 0; lane < BS_LANES && !rest.empty(); ++lane)
+                if (lane_w[lane] < 0) { lane_w[lane] = rest.back(); rest.pop_back(); }
+        }
+        std::vector<std::unordered_map<int, int>> rank(BS_LANES);
+        for (int lane = 0; lane < BS_LANES; ++lane) {
+            int i = lane_w[lane];
+            if (i < 0) {
+                // idle lane: repeat a w of its own 16-lane run (same address,
+                // no extra bank conflict); its results are dropped
+                for (int l = lane & ~15; l < (lane & ~15) + 16 && i < 0; ++l) i = lane_w[l];
+                for (int l = 0; l < BS_LANES && i < 0; ++l) i = lane_w[l];
+            } else {
+                for (size_t j = 0; j < Sw[i].size() / 2; ++j)
+                    rank[lane][(Sw[i][2 * j + 1] + 64) * 256 + (Sw[i][2 * j] + 64)] = (int)j;
+            }
+            pl->group_xy[((size_t)gi * BS_LANES + lane) * 2 + 0] = pl->W[2 * i];
+            pl->group_xy[((size_t)gi * BS_LANES + lane) * 2 + 1] = pl->W[2 * i + 1];
+        }
+        for (const Item &gt : gitems) {
+            const int u0 = gt.u0, m = gt.m, ns = gt.ns, rx0 = gt.rx0, ry0 = gt.ry0, rw = pitch, rh = gt.rh;
+            int cstart[BS_WAVES + 1];
+            cstart[0] = u0;
+            for (int c = 0; c < BS_WAVES; ++c) cstart[c + 1] = cstart[c] + m / BS_WAVES + (c < m % BS_WAVES ? 1 : 0);
+            if (pitch * rh > BS_MAX_REGION) { *err = "bispectrum region too large"; return false; }
+            pl->max_region = std::max(pl->max_region, pitch * rh);
+            int32_t it[BS_ITEM_INTS] = {gi, rx0, ry0, rw, rh, rw * rh, pitch, 0, ns, ns, ns, ns};
             for (int wv = 0; wv < BS_WAVES; ++wv) {
-                int c = c0 + wv;
-                int ns = c < c1 ? cstart[c + 1] - cstart[c] : 0;
-                it[8 + wv] = ns;
+                const int nreal = cstart[wv + 1] - cstart[wv];
                 pl->computed_terms += (int64_t)ns * BS_LANES;
                 for (int k = 0; k < K; ++k) {
-                    int u = k < ns ? cstart[c] + k : cstart[c0];
-                    int vx = U[u].first, vy = U[u].second;
+                    // slots past the real v of the chunk repeat the item's first v
+                    const bool real = k < nreal;
+                    const int u = real ? cstart[wv] + k : u0;
+                    const int vx = U[u].first, vy = U[u].second;
                     pl->slot_v.push_back(vy * pitch + vx);
                     const uint32_t so = (uint32_t)((vy + 16) * N + (vx & (N - 1)));
                     pl->slot_v.push_back((int32_t)so);
                     for (int lane = 0; lane < BS_LANES; ++lane) {
                         int32_t o = -1;
-                        if (k < ns && lane_w[lane] >= 0) {
+                        if (real && lane_w[lane] >= 0) {
                             auto f = rank[lane].find((vy + 64) * 256 + (vx + 64));
                             if (f != rank[lane].end()) o = pl->woff[lane_w[lane]] + f->second;
                         }

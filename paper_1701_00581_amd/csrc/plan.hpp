@@ -9,13 +9,12 @@
 
 namespace nvsm {
 
-// Bispectrum kernel geometry: a wave's 64 lanes hold an 8x8 block of w, its
-// K slots hold v values shared by the whole wave.
+// Bispectrum kernel geometry: a wave's 64 lanes hold a group of w close in
+// angle and radius, its K slots hold v values shared by the whole wave.
 constexpr int BS_LANES = 64;
-constexpr int BS_BLOCK = 8;
 constexpr int BS_MAX_SLOTS = 32;     // largest slot count per wave
 constexpr int BS_WAVES = 4;            // waves per workgroup
-constexpr int BS_MAX_REGION = 1024;    // staged region extent (pitch x height) per frame
+constexpr int BS_MAX_REGION = 1536;    // staged region extent (pitch x height) per frame, whole 128s
 constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
 
 struct Tiling {
@@ -46,14 +45,20 @@ struct HostPlan {
     // (bits 0..14 index into W, bit 15 set = use the conjugate).
     std::vector<uint32_t> phase_code;
     int64_t s_count = 0;
-    // Bispectrum work items.  items[g*12 + 0..11] = block x0, block y0,
-    // region x0, region y0, region width, region height, region points
-    // (width x height), region row pitch in LDS, then the slot count of each
-    // of the BS_WAVES waves.  The pitch is padded to 8 mod 32 complex values
-    // so that the 8 rows of a block fall into different LDS banks.
+    // Bispectrum work items.  items[g*12 + 0..11] = w group, region x0,
+    // region y0, region width, region height, region points (width x
+    // height), region row pitch in LDS, 0, then the slot count ns of each of
+    // the BS_WAVES waves (the same for all, a multiple of 4, <= K).  The
+    // region holds I(w - v) for every lane's w and every slot's v of the
+    // item.
     int slots = 0;                      // v slots per wave (K)
     int n_items = 0;
     std::vector<int32_t> items;
+    // group_xy[(group*64 + lane)*2 + 0/1] = (wx, wy) of the lane's w (idle
+    // lanes repeat lane 0's w and never write a result).
+    int n_groups = 0;
+    std::vector<int32_t> group_xy;
+    int max_region = 0;                 // largest region points of any item
     // slot[((g*BS_WAVES + wave)*K + k)*2 + 0] = vy * region_pitch + vx
     // (offset of v in the staged region), [..+1] = offset of I(v) in a
     // frame's stored spectrum record (rows -16 .. N/2-1).
@@ -70,10 +75,6 @@ struct HostPlan {
 
 // Builds everything above; returns false with *err set on bad sizes.
 bool build_plan(int N, int uc, int R, int slots, HostPlan *out, std::string *err);
-// Largest padded region extent the slot count allows (LDS sizing).
-constexpr int bs_region_cap(int) { return BS_MAX_REGION; }
-// Row pitch >= w with pitch = 8 (mod 32).
-constexpr int bs_region_pitch(int w) { return w + ((8 - w) % 32 + 32) % 32; }
 
 // S in storage order, 4 ints per entry (wx, wy, vx, vy).
 void enumerate_S(int uc, int R, std::vector<int32_t> *wv);
