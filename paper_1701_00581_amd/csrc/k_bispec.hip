@@ -25,7 +25,7 @@ namespace nvsm {
 namespace {
 
 constexpr int NT = BS_WAVES * 64;
-constexpr int KB = 20;                     // frames per compensated block
+constexpr int KB = 25;                     // frames per compensated block
 
 // LDS record of one frame: the item's region of I (w - v values, row pitch =
 // region width), moved in chunks of 128 complex values (one wave-wide
@@ -40,12 +40,20 @@ typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
 
 __device__ __forceinline__ float2 as_f2(u32x2 v) { return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1])); }
 
-// b taken from lane K of this lane's row of 16 (DPP row_newbcast), times a;
-// and acc + that product.  Arithmetic only; EXEC must be full.
+// b taken from lane K of this lane's row of 16 (DPP row_newbcast), times a
+// (negated, for mul_bc_neg); and acc + that product.  Arithmetic only; EXEC
+// must be full.
 template <int K>
 __device__ __forceinline__ float mul_bc(float b, float a) {
     float r;
     asm("v_mul_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(r) : "v"(b), "v"(a), "i"(K));
+    return r;
+}
+template <int K>
+__device__ __forceinline__ float mul_bc_neg(float b, float a) {
+    float r;
+    asm("v_mul_f32_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
         : "=v"(r) : "v"(b), "v"(a), "i"(K));
     return r;
 }
@@ -170,18 +178,14 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         const int fn = min(f + 1, F - 1);
         fetch(fn, nxt);
         const char *rb = (const char *)rg;
-        float nby[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) nby[q] = -bv[q].y;
-        const float ncy = -cw.y;
         // p = I(w - v) I(v);  t += p conj I(w)
         auto slot_k = [&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value, q = k / 16, r = k % 16;
             const float2 a = *(const float2 *)(rb + addr[k]);
-            const float pr = fmac_bc<r>(mul_bc<r>(nby[q], a.y), bv[q].x, a.x);
+            const float pr = fmac_bc<r>(mul_bc_neg<r>(bv[q].y, a.y), bv[q].x, a.x);
             const float pi = fmac_bc<r>(mul_bc<r>(bv[q].x, a.y), bv[q].y, a.x);
             t[k].x = fmaf(pr, cw.x, fmaf(pi, cw.y, t[k].x));
-            t[k].y = fmaf(pi, cw.x, fmaf(pr, ncy, t[k].y));
+            t[k].y = fmaf(pi, cw.x, fmaf(pr, -cw.y, t[k].y));
         };
         static_for<NS>(slot_k);
         if ((f + 1) % KB == 0 || f + 1 == F) {
