@@ -171,6 +171,57 @@ nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p,
                              const double *stf, float *out,
                              void *workspace, size_t workspace_bytes, void *stream);
 
+/* One burst of a batch.  frames: device [F][H][row_pitch] pixels of the
+ * batch's dtype; stf: device double [N][N] (DFT order) for this burst's
+ * seeing; out: device float [H][W].  All caller-owned. */
+typedef struct nvsm_burst {
+    const void *frames;
+    int32_t F, H, W;
+    int64_t row_pitch;
+    const double *stf;
+    float *out;
+} nvsm_burst;
+
+/* Workspace for nvsm_reconstruct_batch on these bursts (host call, no
+ * device access; pointers may be NULL): *ws_min is enough to run them one
+ * burst per launch group, *ws_all to run up to 16 per group.  Any size in
+ * between works; larger groups share launches. */
+nvsm_status nvsm_batch_plan(const nvsm_params *p, const nvsm_burst *bursts, int32_t n,
+                            size_t *ws_min, size_t *ws_all);
+
+/* The whole path (as nvsm_reconstruct) for n bursts of uneven shape and
+ * frame count that share the parameters p and the dtype.  The bursts are
+ * taken in order in groups of at most 16 whose intermediates fit in the
+ * workspace; each group runs as one launch per stage over all patches of
+ * its bursts (workgroups find their burst from the patch and workgroup
+ * numbering), so small bursts fill the GPU together.  Each image equals
+ * the one nvsm_reconstruct gives for that burst alone, bit for bit: every
+ * value is computed by the same arithmetic in the same order.  Launches go
+ * to `stream` and allocate nothing, so the call can be captured in a HIP
+ * graph once the plan exists (nvsm_prepare). */
+nvsm_status nvsm_reconstruct_batch(nvsm_context *ctx, const nvsm_params *p, nvsm_dtype dtype,
+                                   const nvsm_burst *bursts, int32_t n,
+                                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* Launch tuning for the bispectrum stage of p's plan.  The candidates are
+ * implementations of the same arithmetic in the same order, so every
+ * output is identical whichever is chosen; only the time differs:
+ *   slots per wave: 16 or 24 v values per wave of a work item;
+ *   form: 0 one workgroup per work item, 1 a persistent grid of resident
+ *         workgroups taking items from per-XCD work queues.
+ * nvsm_autotune runs the ingest once on the given burst (device frames,
+ * as for nvsm_reconstruct, with a workspace of ws_reconstruct bytes), then
+ * times the bispectrum launch of each candidate with HIP events and keeps
+ * the fastest for p (it waits for the stream).  *slots_out and *form_out
+ * (may be NULL) receive the choice.  nvsm_set_launch sets a choice
+ * directly.  Without either, calls use 16 slots and form 0. */
+nvsm_status nvsm_autotune(nvsm_context *ctx, const nvsm_params *p,
+                          const void *frames, nvsm_dtype dtype, int32_t F,
+                          int32_t H, int32_t W, int64_t row_pitch,
+                          void *workspace, size_t workspace_bytes, void *stream,
+                          int32_t *slots_out, int32_t *form_out);
+nvsm_status nvsm_set_launch(nvsm_context *ctx, const nvsm_params *p, int32_t slots, int32_t form);
+
 /* Stage timing with HIP events recorded on the call's stream around each
  * stage's kernels (off by default; recording adds no synchronisation).
  * Stages: 0 ingest (tile cut, taper, FFT, power and mean sums),

@@ -27,7 +27,8 @@ EXPORTS = [
     "nvsm_create", "nvsm_destroy", "nvsm_status_string", "nvsm_last_error",
     "nvsm_default_params", "nvsm_plan", "nvsm_w_index", "nvsm_bispectrum_index",
     "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
-    "nvsm_profile_enable", "nvsm_profile_read",
+    "nvsm_profile_enable", "nvsm_profile_read", "nvsm_batch_plan", "nvsm_reconstruct_batch",
+    "nvsm_autotune", "nvsm_set_launch",
 ]
 STAGES = ["ingest", "bispectrum", "solve", "synthesize"]
 
@@ -53,6 +54,13 @@ class PlanInfo(ctypes.Structure):
         ("frame_chunks", ctypes.c_int32), ("ws_accumulate", ctypes.c_size_t),
         ("ws_solve", ctypes.c_size_t), ("ws_synthesize", ctypes.c_size_t),
         ("ws_reconstruct", ctypes.c_size_t),
+    ]
+
+
+class Burst(ctypes.Structure):
+    _fields_ = [
+        ("frames", ctypes.c_void_p), ("F", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+        ("row_pitch", ctypes.c_int64), ("stf", ctypes.c_void_p), ("out", ctypes.c_void_p),
     ]
 
 
@@ -86,6 +94,12 @@ def lib():
         L.nvsm_synthesize.argtypes = [c_p, P, c_i32, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]
         L.nvsm_reconstruct.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64,
                                        c_p, c_p, c_p, c_sz, c_p]
+        L.nvsm_batch_plan.argtypes = [P, ctypes.POINTER(Burst), c_i32, ctypes.POINTER(c_sz),
+                                      ctypes.POINTER(c_sz)]
+        L.nvsm_reconstruct_batch.argtypes = [c_p, P, ctypes.c_int, ctypes.POINTER(Burst), c_i32, c_p, c_sz, c_p]
+        L.nvsm_autotune.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_p, c_sz, c_p,
+                                    ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
+        L.nvsm_set_launch.argtypes = [c_p, P, c_i32, c_i32]
         L.nvsm_profile_enable.argtypes = [c_p, c_i32]
         L.nvsm_profile_read.argtypes = [c_p, c_p, c_p, c_i32]
         for name in EXPORTS:
@@ -219,6 +233,52 @@ def nvsm_reconstruct(ctx, params, frames, stf, out, workspace, stream=None, row_
                                 _ptr(stf), _ptr(out), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream))
     _check(st, "nvsm_reconstruct", ctx)
+
+
+def _bursts(bursts):
+    """ctypes array of Burst from (frames, stf, out) triples of tensors
+    (frames [F][H][W] with any row pitch)."""
+    arr = (Burst * len(bursts))()
+    for i, (frames, stf, out) in enumerate(bursts):
+        F, H, W = frames.shape
+        arr[i] = Burst(_ptr(frames), F, H, W, frames.stride(1), _ptr(stf), _ptr(out))
+    return arr
+
+
+def nvsm_batch_plan(params, shapes):
+    """(ws_min, ws_all) bytes for bursts of the given (F, H, W) shapes."""
+    arr = (Burst * len(shapes))()
+    for i, (F, H, W) in enumerate(shapes):
+        arr[i] = Burst(None, F, H, W, W, None, None)
+    lo, hi = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().nvsm_batch_plan(ctypes.byref(params), arr, len(shapes), ctypes.byref(lo), ctypes.byref(hi)),
+           "nvsm_batch_plan")
+    return lo.value, hi.value
+
+
+def nvsm_reconstruct_batch(ctx, params, bursts, workspace, stream=None):
+    """bursts: list of (frames, stf, out) tensors; frames share one dtype."""
+    arr = _bursts(bursts)
+    st = lib().nvsm_reconstruct_batch(ctx, ctypes.byref(params), frames_dtype(bursts[0][0]), arr, len(bursts),
+                                      _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                      _stream(stream))
+    _check(st, "nvsm_reconstruct_batch", ctx)
+
+
+def nvsm_autotune(ctx, params, frames, workspace, stream=None, row_pitch=None):
+    """(slots per wave, form) chosen for params after timing the candidates."""
+    F, H, W = frames.shape
+    pitch = frames.stride(1) if row_pitch is None else row_pitch
+    k, f = ctypes.c_int32(), ctypes.c_int32()
+    st = lib().nvsm_autotune(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W, pitch,
+                             _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream),
+                             ctypes.byref(k), ctypes.byref(f))
+    _check(st, "nvsm_autotune", ctx)
+    return k.value, f.value
+
+
+def nvsm_set_launch(ctx, params, slots, form):
+    _check(lib().nvsm_set_launch(ctx, ctypes.byref(params), int(slots), int(form)), "nvsm_set_launch", ctx)
 
 
 def nvsm_profile_enable(ctx, enable=True):

@@ -20,6 +20,8 @@
 #include "kernels.hpp"
 #include "plan.hpp"
 
+#include <algorithm>
+
 namespace nvsm {
 
 namespace {
@@ -30,10 +32,12 @@ constexpr int KB = 25;                     // frames per compensated block
 // LDS record of one frame: the item's region of I (w - v values, row pitch =
 // region width), moved in chunks of 128 complex values (one wave-wide
 // 16-byte load each).
-constexpr int SZ = BS_MAX_REGION;                              // float2 per frame
-constexpr int CH = SZ / 128;                                   // chunks per frame
-constexpr int PERW = (CH + BS_WAVES - 1) / BS_WAVES;           // chunks per wave
-static_assert(SZ % 128 == 0, "region capacity must be whole chunks");
+template <int K> struct Region {
+    static constexpr int SZ = bs_max_region(K);                // float2 per frame
+    static constexpr int CH = SZ / 128;                        // chunks per frame
+    static constexpr int PERW = (CH + BS_WAVES - 1) / BS_WAVES;    // chunks per wave
+    static_assert(SZ % 128 == 0, "region capacity must be whole chunks");
+};
 
 typedef __attribute__((address_space(3))) void *lds_ptr;
 typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
@@ -89,14 +93,15 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(15 | (7 
 // dropped.  The frame's slot loop is one branch-free block, so its LDS reads
 // can be issued ahead.
 template <int N, int K, int NS>
-__device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const float2 *__restrict__ spec, int F,
-                                            int patch, int g, const int *__restrict__ it,
+__device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const float2 *__restrict__ spec,
+                                            int64_t rec0, int F, int patch, int g, const int *__restrict__ it,
                                             const int *__restrict__ group_xy, const int *__restrict__ slot,
                                             const int *__restrict__ out_idx, float2 *__restrict__ bispec,
                                             int64_t s_count, float invF) {
     constexpr int HALF = N / 2;
     constexpr int FS = SpecRows<N>::FS;
     constexpr int FB = FS * (int)sizeof(float2);               // bytes per stored frame
+    constexpr int PERW = Region<K>::PERW;
     const int *gxy = group_xy + it[0] * (2 * BS_LANES);
     const int rx0 = it[1], ry0 = it[2], npts = it[5], pitch = it[6];
     const int tid = threadIdx.x;
@@ -138,8 +143,8 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     }
 
     // the patch's spectra as one buffer resource; frame f at byte f * FB
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(spec + (size_t)patch * F * FS), (short)0, F * FB, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(spec + (size_t)rec0 * FS), (short)0, F * FB, 0x00020000);
     // the region loads of frame f into buf
     auto fetch = [&](int f, float2 *buf) __attribute__((always_inline)) {
 #pragma unroll
@@ -219,54 +224,125 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
 
 // Runs the item with its slot count (one of 4, 8, ..., Q * 4).
 template <int N, int K, int Q>
-__device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *lds1, const float2 *spec, int F,
-                                                int patch, int g, const int *it, const int *group_xy,
+__device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *lds1, const float2 *spec,
+                                                int64_t rec0, int F, int patch, int g, const int *it, const int *group_xy,
                                                 const int *slot, const int *out_idx, float2 *bispec,
                                                 int64_t s_count, float invF) {
     if constexpr (Q > 0) {
         if (nq == Q)
-            bispec_item<N, K, 4 * Q>(lds0, lds1, spec, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
+            bispec_item<N, K, 4 * Q>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
                                      invF);
         else
-            bispec_dispatch<N, K, Q - 1>(nq, lds0, lds1, spec, F, patch, g, it, group_xy, slot, out_idx, bispec,
+            bispec_dispatch<N, K, Q - 1>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
                                          s_count, invF);
     }
 }
 
+// Item L of the launch: (patch, work item) = (L / n_items, L % n_items).
 template <int N, int K>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec(
-    const float2 *__restrict__ spec, int F, int n_items, int total, const int *__restrict__ items,
-    const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
-    float2 *__restrict__ bispec, int64_t s_count, float invF) {
-    // two separate arrays, so that loads into one are known not to touch
-    // the other
-    __shared__ float2 lds0[SZ];
-    __shared__ float2 lds1[SZ];
-    const int L = xcd_remap(blockIdx.x, total);
+__device__ __forceinline__ void bispec_one(int L, float2 *lds0, float2 *lds1, const BurstTable &bt,
+                                           const float2 *spec, int n_items, const int *items, const int *group_xy,
+                                           const int *slot, const int *out_idx, float2 *bispec, int64_t s_count) {
     const int patch = L / n_items, g = L % n_items;
+    const int b = burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; });
+    const int F = bt.b[b].F;
+    const int64_t rec0 = bt.b[b].spec0 + (int64_t)(patch - bt.b[b].patch0) * F;
+    const float invF = 1.0f / (float)F;
     const int *it = items + g * BS_ITEM_INTS;
     const int nq = __builtin_amdgcn_readfirstlane(it[8]) >> 2;   // the item's slots per wave / 4
-    bispec_dispatch<N, K, K / 4>(nq, lds0, lds1, spec, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
-                                 invF);
+    bispec_dispatch<N, K, K / 4>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
+                                 s_count, invF);
+}
+
+// One workgroup per item.
+template <int N, int K>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec(
+    const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
+    const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
+    float2 *__restrict__ bispec, int64_t s_count) {
+    // two separate arrays, so that loads into one are known not to touch
+    // the other
+    __shared__ float2 lds0[Region<K>::SZ];
+    __shared__ float2 lds1[Region<K>::SZ];
+    bispec_one<N, K>(xcd_remap(blockIdx.x, total), lds0, lds1, bt, spec, n_items, items, group_xy, slot, out_idx,
+                     bispec, s_count);
+}
+
+// Persistent form: as many workgroups as fit on the GPU at once, each
+// taking items from a work queue until none is left.  The items are split
+// into 8 contiguous ranges, one per XCD (workgroups are dispatched to the
+// XCDs in turn, blockIdx mod 8), so that each XCD works on its own patches
+// and keeps their spectra in its L2; a workgroup drains its own XCD's range
+// first, then helps the others.  queue[8] counts the items taken from each
+// range and must be zero at launch.  Every workgroup ends after finding all
+// 8 ranges exhausted.
+template <int N, int K>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec_queue(
+    const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
+    const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
+    float2 *__restrict__ bispec, int64_t s_count, int *__restrict__ queue) {
+    __shared__ float2 lds0[Region<K>::SZ];
+    __shared__ float2 lds1[Region<K>::SZ];
+    __shared__ int next;
+    const int x = blockIdx.x & 7;
+    for (int k = 0; k < 8; ++k) {
+        const int q = (x + k) & 7;
+        const int beg = (int)((int64_t)total * q / 8);
+        const int cnt = (int)((int64_t)total * (q + 1) / 8) - beg;
+        for (;;) {
+            __syncthreads();                     // the last item is done with LDS and `next`
+            if (threadIdx.x == 0) next = atomicAdd(&queue[q], 1);
+            __syncthreads();
+            const int i = __builtin_amdgcn_readfirstlane(next);
+            if (i >= cnt) break;
+            bispec_one<N, K>(beg + i, lds0, lds1, bt, spec, n_items, items, group_xy, slot, out_idx, bispec,
+                             s_count);
+        }
+    }
+}
+
+__global__ void k_queue_reset(int *queue) {
+    if (threadIdx.x < 8) queue[threadIdx.x] = 0;
+}
+
+template <int N, int K>
+hipError_t launch_bispec_t(const BispecArgs &a, int total, hipStream_t st) {
+    if (a.form == 0) {
+        hipLaunchKernelGGL((k_bispec<N, K>), dim3(total), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
+                           a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count);
+        return hipGetLastError();
+    }
+    if (!a.queue) return hipErrorInvalidValue;
+    static int resident[2] = {0, 0};           // workgroups per CU, per slot count
+    int &per_cu = resident[K == 16 ? 0 : 1];
+    if (per_cu == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_bispec_queue<N, K>, NT, 0) != hipSuccess || n < 1)
+            n = 1;
+        per_cu = n;
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return hipErrorInvalidValue;
+    const int grid = std::max(8, std::min(total, per_cu * cus) / 8 * 8);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, a.queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bispec_queue<N, K>), dim3(grid), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
+                       a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, a.queue);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_bispec(const BispecArgs &a, hipStream_t st) {
-    const int total = a.patches * a.n_items;
-    if (total == 0) return hipSuccess;
-#define NVSM_LAUNCH_BS(NN, KK)                                                                             \
-    hipLaunchKernelGGL((k_bispec<NN, KK>), dim3(total), dim3(NT), 0, st, a.spectra, a.F, a.n_items, total, \
-                       a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, 1.0f / a.F)
-    if (a.slots == 16) {
-        if (a.N == 128) NVSM_LAUNCH_BS(128, 16); else NVSM_LAUNCH_BS(64, 16);
-    } else if (a.slots == 24) {
-        if (a.N == 128) NVSM_LAUNCH_BS(128, 24); else NVSM_LAUNCH_BS(64, 24);
-    } else {
-        return hipErrorInvalidValue;
-    }
-#undef NVSM_LAUNCH_BS
-    return hipGetLastError();
+    const int64_t total64 = (int64_t)a.bt.patches * a.n_items;
+    if (total64 == 0) return hipSuccess;
+    if (total64 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    const int total = (int)total64;
+    if (a.slots == 16) return a.N == 128 ? launch_bispec_t<128, 16>(a, total, st) : launch_bispec_t<64, 16>(a, total, st);
+    if (a.slots == 24) return a.N == 128 ? launch_bispec_t<128, 24>(a, total, st) : launch_bispec_t<64, 24>(a, total, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace nvsm

@@ -1,5 +1,6 @@
 // Ingest: subimage cut, taper, 2-D FFT and the power/mean accumulation of
-// the Eq. 1 numerator.  One workgroup per (patch, group of frames).
+// the Eq. 1 numerator.  One workgroup per (patch, group of frames), over
+// all patches of the bursts of the launch.
 //
 // Two real frames a, b are transformed together as z = qa + i qb; with
 // Z = FFT2(z), Ia(u) = (Z(u) + conj Z(-u)) / 2 and
@@ -36,10 +37,8 @@ template <typename T> struct Quad<T, false> {
 };
 
 template <int N, typename T, bool VEC>
-__global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int F, int H, int W,
-                                               int64_t pitch, int nx, int stride, int chunk_frames,
-                                               int nchunks, int total, int window, float inv_wsum,
-                                               const float2 *__restrict__ twiddle,
+__global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, int chunk_frames, int window,
+                                               float inv_wsum, const float2 *__restrict__ twiddle,
                                                const float *__restrict__ hann,
                                                float2 *__restrict__ spectra, float *__restrict__ ppart,
                                                float *__restrict__ mpart, float *__restrict__ mupart) {
@@ -53,9 +52,16 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
     __shared__ float hw[N];
     __shared__ float red[2][NT / 64];
 
-    const int L = xcd_remap(blockIdx.x, total);
-    const int patch = L / nchunks, chunk = L % nchunks;
-    const int py = patch / nx, px = patch % nx;
+    const int L = xcd_remap(blockIdx.x, bt.ingest_wgs);
+    const int b = burst_of(bt, L, [](const BurstDesc &d) { return (int64_t)d.ingest0; });
+    const BurstDesc &bd = bt.b[b];
+    const int F = bd.F, H = bd.H, W = bd.W, nx = bd.nx;
+    const int64_t pitch = bd.pitch;
+    const T *frames = (const T *)bd.frames;
+    const int nchunks = (F + chunk_frames - 1) / chunk_frames;
+    const int local = L - bd.ingest0;
+    const int lpatch = local / nchunks, chunk = local % nchunks;
+    const int py = lpatch / nx, px = lpatch % nx;
     const int y0 = min(py * stride, H - N), x0 = min(px * stride, W - N);
     const int f0 = chunk * chunk_frames, f1 = min(F, f0 + chunk_frames);
     const int tid = threadIdx.x;
@@ -71,7 +77,7 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
     float m10s[2] = {0.f, 0.f}, m10c[2] = {0.f, 0.f}, m01s[2] = {0.f, 0.f}, m01c[2] = {0.f, 0.f};
     float mus = 0.f, muc = 0.f;
     constexpr int FS = SpecRows<N>::FS;          // float2 per stored frame spectrum
-    const size_t spec_patch = (size_t)patch * F * FS;
+    const size_t spec_patch = (size_t)(bd.spec0 + (int64_t)lpatch * F) * FS;
 
     // raw pixels of the current frame pair, loaded one pair ahead (not for
     // 4-byte pixels at N = 128, which would not fit in registers)
@@ -173,23 +179,23 @@ __global__ __launch_bounds__(NT) void k_ingest(const T *__restrict__ frames, int
         }
         __syncthreads();
     }
-    // partial sums of this frame group
-    float *pp = ppart + ((size_t)patch * nchunks + chunk) * NP;
+    // partial sums of this frame group, at the workgroup's index
+    float *pp = ppart + (size_t)L * NP;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int j = k * NT + tid;
         if (j < NP) pp[j] = ps[k];
     }
-    float *mp = mpart + ((size_t)patch * nchunks + chunk) * 4;
+    float *mp = mpart + (size_t)L * 4;
     if (tid == 1 % NT) { mp[0] = m10s[0] - m10c[0]; mp[1] = m10s[1] - m10c[1]; }
     if (tid == N % NT) { mp[2] = m01s[0] - m01c[0]; mp[3] = m01s[1] - m01c[1]; }
-    if (tid == 0) mupart[(size_t)patch * nchunks + chunk] = mus - muc;
+    if (tid == 0) mupart[L] = mus - muc;
 }
 
 // Sums the frame groups (compensated) and divides by F; mirrors the power
 // spectrum rows N/2+1..N-1 from P(-u) = P(u).
 template <int N>
-__global__ __launch_bounds__(NT) void k_acc_finalize(int nchunks, float invF,
+__global__ __launch_bounds__(NT) void k_acc_finalize(const BurstTable bt, int chunk_frames,
                                                      const float *__restrict__ ppart,
                                                      const float *__restrict__ mpart,
                                                      const float *__restrict__ mupart,
@@ -197,7 +203,12 @@ __global__ __launch_bounds__(NT) void k_acc_finalize(int nchunks, float invF,
                                                      float *__restrict__ mu) {
     constexpr int HALF = N / 2, NP = (HALF + 1) * N;
     const int patch = blockIdx.x;
-    const float *pp = ppart + (size_t)patch * nchunks * NP;
+    const int b = burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; });
+    const BurstDesc &bd = bt.b[b];
+    const int nchunks = (bd.F + chunk_frames - 1) / chunk_frames;
+    const float invF = 1.0f / (float)bd.F;
+    const size_t wg0 = (size_t)bd.ingest0 + (size_t)(patch - bd.patch0) * nchunks;   // its first ingest workgroup
+    const float *pp = ppart + wg0 * NP;
     for (int j = threadIdx.x; j < N * N; j += NT) {
         const int uy = j / N, ux = j % N;
         const int src = uy <= HALF ? j : ((N - uy) * N + ((N - ux) & (N - 1)));
@@ -207,40 +218,37 @@ __global__ __launch_bounds__(NT) void k_acc_finalize(int nchunks, float invF,
     }
     if (threadIdx.x < 4) {
         float s = 0.f, c = 0.f;
-        for (int k = 0; k < nchunks; ++k) kahan_add(s, c, mpart[((size_t)patch * nchunks + k) * 4 + threadIdx.x]);
+        for (int k = 0; k < nchunks; ++k) kahan_add(s, c, mpart[(wg0 + k) * 4 + threadIdx.x]);
         mean_spec[(size_t)patch * 4 + threadIdx.x] = (s - c) * invF;
     }
     if (threadIdx.x == 4) {
         float s = 0.f, c = 0.f;
-        for (int k = 0; k < nchunks; ++k) kahan_add(s, c, mupart[(size_t)patch * nchunks + k]);
+        for (int k = 0; k < nchunks; ++k) kahan_add(s, c, mupart[wg0 + k]);
         mu[patch] = (s - c) * invF;
     }
 }
 
 template <int N, typename T>
 hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
-    const int total = a.patches * a.nchunks;
-    // vector loads need every quad of 4 pixels aligned to its size
-    const bool vec = a.stride % 4 == 0 && (a.W - N) % 4 == 0 && a.pitch % 4 == 0 &&
-                     ((uintptr_t)a.frames % (4 * sizeof(T))) == 0;
-    if (vec)
-        hipLaunchKernelGGL((k_ingest<N, T, true>), dim3(total), dim3(NT), 0, st, (const T *)a.frames, a.F, a.H,
-                           a.W, a.pitch, a.nx, a.stride, a.chunk_frames, a.nchunks, total, a.window,
-                           a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart, a.mupart);
+    if (a.vec)
+        hipLaunchKernelGGL((k_ingest<N, T, true>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+                           a.chunk_frames, a.window, a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart,
+                           a.mupart);
     else
-        hipLaunchKernelGGL((k_ingest<N, T, false>), dim3(total), dim3(NT), 0, st, (const T *)a.frames, a.F, a.H,
-                           a.W, a.pitch, a.nx, a.stride, a.chunk_frames, a.nchunks, total, a.window,
-                           a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart, a.mupart);
+        hipLaunchKernelGGL((k_ingest<N, T, false>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+                           a.chunk_frames, a.window, a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart,
+                           a.mupart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_acc_finalize<N>), dim3(a.patches), dim3(NT), 0, st, a.nchunks, 1.0f / a.F,
-                       a.ppart, a.mpart, a.mupart, a.power, a.mean_spec, a.mu);
+    hipLaunchKernelGGL((k_acc_finalize<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames, a.ppart,
+                       a.mpart, a.mupart, a.power, a.mean_spec, a.mu);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_ingest(const IngestArgs &a, hipStream_t st) {
+    if (a.bt.patches == 0) return hipSuccess;
     if (a.N == 128) return a.f32 ? launch_ingest_t<128, float>(a, st) : launch_ingest_t<128, uint16_t>(a, st);
     return a.f32 ? launch_ingest_t<64, float>(a, st) : launch_ingest_t<64, uint16_t>(a, st);
 }

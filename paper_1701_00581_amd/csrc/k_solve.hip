@@ -71,11 +71,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
                                               const int *__restrict__ Wxy, const float *__restrict__ power,
                                               const float *__restrict__ mean_spec,
                                               const float2 *__restrict__ bispec, int64_t s_count,
-                                              const double *__restrict__ stf, double floor_, int noise_bias,
+                                              const BurstTable bt, double floor_, int noise_bias,
                                               double *__restrict__ amp, double2 *__restrict__ phasor) {
     __shared__ double2 e[Win<BIG>::INNER + Win<BIG>::RING];
     __shared__ double red[NWAVE];
     const int patch = blockIdx.x;
+    const double *stf = bt.b[burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; })].stf;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -223,9 +224,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
 
 template <int N, int TPL, int BIG>
 hipError_t launch_solve_t(const SolveArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_solve<N, TPL, BIG>), dim3(a.patches), dim3(NT), 0, st, a.nW, a.nshell, a.shell_wb,
+    hipLaunchKernelGGL((k_solve<N, TPL, BIG>), dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.nshell, a.shell_wb,
                        a.w_slot, a.woff, a.code, a.Wxy, a.power, a.mean_spec, a.bispec,
-                       a.s_count, a.stf, a.floor, a.noise_bias, a.amp, a.phasor);
+                       a.s_count, a.bt, a.floor, a.noise_bias, a.amp, a.phasor);
     return hipGetLastError();
 }
 
@@ -239,7 +240,7 @@ hipError_t launch_solve_n(const SolveArgs &a, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_solve(const SolveArgs &a, hipStream_t st) {
-    if (a.patches == 0) return hipSuccess;
+    if (a.bt.patches == 0) return hipSuccess;
     if (a.max_sw > 512) return hipErrorInvalidValue;
     const bool small = a.n_inner <= Win<0>::INNER && a.ring <= Win<0>::RING;
     if (!small && (a.n_inner > Win<1>::INNER || a.ring > Win<1>::RING)) return hipErrorInvalidValue;

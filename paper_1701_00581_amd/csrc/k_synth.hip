@@ -4,8 +4,9 @@
 // filter(w) |O(w)| e(w) on W in LDS and inverts it with the forward FFT:
 // Re IFFT(X) = Re FFT(conj X) / N^2.  The mean level removed at ingest is
 // put back under the taper.
-// k_mosaic: one thread per output pixel gathers the (at most 3 x 3)
-// subimages covering it, out = sum r_k / sum taper_k (0 where < 1e-3).
+// k_mosaic: one thread per output pixel of the bursts of the launch gathers
+// the (at most 3 x 3) subimages covering it, out = sum r_k / sum taper_k
+// (0 where < 1e-3).
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -53,11 +54,15 @@ __global__ __launch_bounds__(NT) void k_synth(int nW, const int *__restrict__ Wx
     }
 }
 
-__global__ __launch_bounds__(NT) void k_mosaic(const float *__restrict__ patches, int N, int ny, int nx,
-                                               int stride, int H, int W, int window,
-                                               const float *__restrict__ hann, float *__restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (idx >= (int64_t)H * W) return;
+__global__ __launch_bounds__(NT) void k_mosaic(const BurstTable bt, const float *__restrict__ all_patches, int N,
+                                               int stride, int window, const float *__restrict__ hann) {
+    const int64_t gidx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (gidx >= bt.pixels) return;
+    const BurstDesc &bd = bt.b[burst_of(bt, gidx, [](const BurstDesc &d) { return d.pix0; })];
+    const int H = bd.H, W = bd.W, ny = bd.ny, nx = bd.nx;
+    const float *patches = all_patches + (size_t)bd.patch0 * N * N;
+    float *out = bd.out;
+    const int64_t idx = gidx - bd.pix0;
     const int y = (int)(idx / W), x = (int)(idx % W);
     float num = 0.f, dy = 0.f, dx = 0.f;
     const int ky0 = y >= N ? (y - N) / stride : 0;
@@ -85,20 +90,19 @@ __global__ __launch_bounds__(NT) void k_mosaic(const float *__restrict__ patches
 
 template <int N>
 hipError_t launch_synth_t(const SynthArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_synth<N>, dim3(a.patches), dim3(NT), 0, st, a.nW, a.Wxy, a.amp, a.phasor, a.filt,
+    hipLaunchKernelGGL(k_synth<N>, dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.Wxy, a.amp, a.phasor, a.filt,
                        a.mu, a.window, a.hann, a.twiddle, a.patch_buf);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.out == nullptr) return e;
-    const int64_t npx = (int64_t)a.H * a.W;
-    hipLaunchKernelGGL(k_mosaic, dim3((unsigned)((npx + NT - 1) / NT)), dim3(NT), 0, st, a.patch_buf, N,
-                       a.ny, a.nx, a.stride, a.H, a.W, a.window, a.hann, a.out);
+    if (e != hipSuccess || !a.mosaic || a.bt.pixels == 0) return e;
+    hipLaunchKernelGGL(k_mosaic, dim3((unsigned)((a.bt.pixels + NT - 1) / NT)), dim3(NT), 0, st, a.bt, a.patch_buf,
+                       N, a.stride, a.window, a.hann);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_synth(const SynthArgs &a, hipStream_t st) {
-    if (a.patches == 0) return hipSuccess;
+    if (a.bt.patches == 0) return hipSuccess;
     return a.N == 128 ? launch_synth_t<128>(a, st) : launch_synth_t<64>(a, st);
 }
 

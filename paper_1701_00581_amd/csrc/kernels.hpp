@@ -6,34 +6,62 @@
 
 namespace nvsm {
 
+// One burst of a launch.  A launch covers up to MAX_BURSTS bursts that
+// share the patch size and index sets; their patches are numbered
+// consecutively (patch0), as are their ingest workgroups (ingest0), stored
+// spectrum records (spec0, in records of one patch and frame) and output
+// pixels (pix0).  The table travels by value in the kernel arguments.
+constexpr int MAX_BURSTS = 16;
+struct BurstDesc {
+    const void *frames = nullptr;         // [F][H][pitch] pixels
+    int64_t pitch = 0;                    // pixels per row
+    int64_t spec0 = 0;                    // first stored spectrum record
+    int64_t pix0 = 0;                     // first output pixel (mosaic)
+    const double *stf = nullptr;          // [N][N]
+    float *out = nullptr;                 // [H][W]
+    int F = 0, H = 0, W = 0, ny = 0, nx = 0;
+    int patch0 = 0, ingest0 = 0, pad = 0;
+};
+struct BurstTable {
+    int nb = 0;
+    int patches = 0;                      // total over the bursts
+    int ingest_wgs = 0;                   // total ingest workgroups
+    int pad = 0;
+    int64_t pixels = 0;                   // total output pixels
+    BurstDesc b[MAX_BURSTS];
+};
+
 struct IngestArgs {
     int N = 0;
     bool f32 = false;
-    const void *frames = nullptr;
-    int F = 0, H = 0, W = 0;
-    int64_t pitch = 0;
-    int patches = 0, nx = 0, stride = 0, chunk_frames = 0, nchunks = 0, window = 0;
+    BurstTable bt;
+    int stride = 0, chunk_frames = 0, window = 0;
+    bool vec = false;                     // every burst allows 4-pixel vector loads
     float inv_wsum = 0.f;
     const float2 *twiddle = nullptr;
     const float *hann = nullptr;
-    float2 *spectra = nullptr;            // [P][F][N/2 + 16][N], rows -16 .. N/2-1
-    float *ppart = nullptr, *mpart = nullptr, *mupart = nullptr;
-    float *power = nullptr, *mean_spec = nullptr, *mu = nullptr;
+    float2 *spectra = nullptr;            // [records][N/2 + 16][N], rows -16 .. N/2-1
+    float *ppart = nullptr, *mpart = nullptr, *mupart = nullptr;   // per ingest workgroup
+    float *power = nullptr, *mean_spec = nullptr, *mu = nullptr;   // per patch
 };
 hipError_t launch_ingest(const IngestArgs &a, hipStream_t st);
 
 struct BispecArgs {
     int N = 0;
+    BurstTable bt;
     const float2 *spectra = nullptr;
-    int F = 0, patches = 0, n_items = 0, slots = 0;
+    int n_items = 0, slots = 0;
     const int *items = nullptr, *group_xy = nullptr, *slot_v = nullptr, *out_idx = nullptr;
     float2 *bispec = nullptr;             // [P][|S|]
     int64_t s_count = 0;
+    int form = 0;                         // 0: one workgroup per item, 1: persistent work queue
+    int *queue = nullptr;                 // [8] counters for the work queue
 };
 hipError_t launch_bispec(const BispecArgs &a, hipStream_t st);
 
 struct SolveArgs {
-    int N = 0, patches = 0, nW = 0, nshell = 0, max_sw = 0;
+    int N = 0, nW = 0, nshell = 0, max_sw = 0;
+    BurstTable bt;                        // patches and the STF of each burst
     const int *shell_wb = nullptr, *woff = nullptr, *Wxy = nullptr;
     const int *w_slot = nullptr;          // LDS slot of each w's phasor
     int n_inner = 0, ring = 0;            // phasor window (see plan.hpp)
@@ -41,7 +69,6 @@ struct SolveArgs {
     const float *power = nullptr, *mean_spec = nullptr;
     const float2 *bispec = nullptr;
     int64_t s_count = 0;
-    const double *stf = nullptr;
     double floor = 0;
     int noise_bias = 0;
     double *amp = nullptr;
@@ -50,7 +77,8 @@ struct SolveArgs {
 hipError_t launch_solve(const SolveArgs &a, hipStream_t st);
 
 struct SynthArgs {
-    int N = 0, patches = 0, nW = 0, window = 0;
+    int N = 0, nW = 0, window = 0;
+    BurstTable bt;                        // patches, tilings and output images
     const int *Wxy = nullptr;
     const double *amp = nullptr;
     const double2 *phasor = nullptr;
@@ -58,9 +86,17 @@ struct SynthArgs {
     const float *mu = nullptr, *hann = nullptr;
     const float2 *twiddle = nullptr;
     float *patch_buf = nullptr;           // [P][N][N]
-    int H = 0, W = 0, ny = 0, nx = 0, stride = 0;
-    float *out = nullptr;                 // [H][W]
+    int stride = 0;
+    bool mosaic = true;
 };
+
+// The burst of workgroup or item index L, given each burst's first index.
+template <typename Get>
+__device__ __forceinline__ int burst_of(const BurstTable &bt, int64_t L, Get first) {
+    int b = 0;
+    while (b + 1 < bt.nb && L >= first(bt.b[b + 1])) ++b;
+    return b;
+}
 hipError_t launch_synth(const SynthArgs &a, hipStream_t st);
 
 }  // namespace nvsm

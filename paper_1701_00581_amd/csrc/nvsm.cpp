@@ -48,13 +48,18 @@ enum { ST_INGEST = 0, ST_BISPEC = 1, ST_SOLVE = 2, ST_SYNTH = 3 };
 struct nvsm_context {
     int device = 0;
     std::string err;
-    std::map<std::tuple<int, int, int>, std::unique_ptr<DevicePlan>> plans;
+    // plans by (N, u_cut, v_radius, slots per wave)
+    std::map<std::tuple<int, int, int, int>, std::unique_ptr<DevicePlan>> plans;
+    // launch choices by (N, u_cut, v_radius): slots per wave, bispectrum form
+    std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+    int *queue = nullptr;                // [8] work-queue counters of the persistent bispectrum
     // stage timing
     bool prof = false;
     std::vector<hipEvent_t> free_ev;
     struct Rec { int stage; hipEvent_t a, b; };
     std::vector<Rec> recs;
     ~nvsm_context() {
+        if (queue) (void)hipFree(queue);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : free_ev) (void)hipEventDestroy(e);
     }
@@ -92,25 +97,55 @@ nvsm_status check_shape(const nvsm_params *p, int H, int W, int F, std::string *
 }
 
 struct Sizes {
-    Tiling t;
-    int64_t P = 0, nW = 0, S = 0;
-    int shells = 0, chunks = 0;
+    int64_t P = 0, nW = 0, S = 0, records = 0, wgs = 0;
     size_t spectra = 0, ppart = 0, mpart = 0, mupart = 0;      // accumulate scratch
     size_t power = 0, mean = 0, mu = 0, bispec = 0, amp = 0, phasor = 0, patches = 0;
 };
 
-void sizes_of(const nvsm_params *p, int H, int W, int F, int64_t nW, int64_t S, int shells, Sizes *z) {
-    make_tiling(H, W, p->patch, p->stride, &z->t);
-    const int64_t N = p->patch;
-    z->P = (int64_t)z->t.ny * z->t.nx;
+// One burst as the entry points receive it.
+struct BurstIn {
+    const void *frames = nullptr;
+    int F = 0, H = 0, W = 0;
+    int64_t pitch = 0;
+    const double *stf = nullptr;
+    float *out = nullptr;
+};
+
+// Numbers the patches, ingest workgroups, spectrum records and output
+// pixels of up to MAX_BURSTS bursts consecutively.
+void make_table(const nvsm_params *p, const BurstIn *in, int n, BurstTable *bt, int64_t *records) {
+    *bt = BurstTable();
+    bt->nb = n;
+    int64_t P = 0, wgs = 0, rec = 0, pix = 0;
+    for (int i = 0; i < n; ++i) {
+        Tiling t;
+        make_tiling(in[i].H, in[i].W, p->patch, p->stride, &t);
+        BurstDesc &d = bt->b[i];
+        d.frames = in[i].frames; d.pitch = in[i].pitch; d.stf = in[i].stf; d.out = in[i].out;
+        d.F = in[i].F; d.H = in[i].H; d.W = in[i].W; d.ny = t.ny; d.nx = t.nx;
+        d.patch0 = (int)P; d.ingest0 = (int)wgs; d.spec0 = rec; d.pix0 = pix;
+        const int64_t Pb = (int64_t)t.ny * t.nx;
+        P += Pb;
+        wgs += Pb * ((in[i].F + CHUNK_FRAMES - 1) / CHUNK_FRAMES);
+        rec += Pb * in[i].F;
+        pix += (int64_t)in[i].H * in[i].W;
+    }
+    bt->patches = (int)P;
+    bt->ingest_wgs = (int)wgs;
+    bt->pixels = pix;
+    *records = rec;
+}
+
+void sizes_for(int N, const BurstTable &bt, int64_t records, int64_t nW, int64_t S, Sizes *z) {
+    z->P = bt.patches;
     z->nW = nW;
     z->S = S;
-    z->shells = shells;
-    z->chunks = (F + CHUNK_FRAMES - 1) / CHUNK_FRAMES;
-    z->spectra = align_up((size_t)z->P * F * (N / 2 + 16) * N * 8);   // rows -16 .. N/2-1
-    z->ppart = align_up((size_t)z->P * z->chunks * (N / 2 + 1) * N * 4);
-    z->mpart = align_up((size_t)z->P * z->chunks * 4 * 4);
-    z->mupart = align_up((size_t)z->P * z->chunks * 4);
+    z->records = records;
+    z->wgs = bt.ingest_wgs;
+    z->spectra = align_up((size_t)records * (N / 2 + 16) * N * 8);   // rows -16 .. N/2-1
+    z->ppart = align_up((size_t)z->wgs * (N / 2 + 1) * N * 4);
+    z->mpart = align_up((size_t)z->wgs * 4 * 4);
+    z->mupart = align_up((size_t)z->wgs * 4);
     z->power = align_up((size_t)z->P * N * N * 4);
     z->mean = align_up((size_t)z->P * 4 * 4);
     z->mu = align_up((size_t)z->P * 4);
@@ -148,17 +183,22 @@ nvsm_status upload(DevicePlan *dp, const std::vector<T> &v, T **out, std::string
     return NVSM_OK;
 }
 
-int bispec_slots() {
-    static const int k = [] {
-        const char *e = getenv("NVSM_BISPEC_SLOTS");
-        int v = e ? atoi(e) : 16;
-        return (v == 16 || v == 24) ? v : 16;
-    }();
-    return k;
+// Launch choices for p: the tuned ones if nvsm_autotune ran, else 16
+// slots per wave and one workgroup per item.
+std::pair<int, int> choice_of(const nvsm_context *ctx, const nvsm_params *p) {
+    auto f = ctx->tuned.find(std::make_tuple(p->patch, p->u_cut, p->v_radius));
+    return f == ctx->tuned.end() ? std::make_pair(16, 0) : f->second;
 }
 
-nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) {
-    auto key = std::make_tuple(p->patch, p->u_cut, p->v_radius);
+nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DevicePlan **out) {
+    if (!ctx->queue) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NVSM_ERR_HIP, "hipSetDevice failed");
+        if (hipMalloc((void **)&ctx->queue, 8 * sizeof(int)) != hipSuccess) {
+            ctx->queue = nullptr;
+            return fail(ctx, NVSM_ERR_OOM, "hipMalloc failed for the work queue");
+        }
+    }
+    auto key = std::make_tuple(p->patch, p->u_cut, p->v_radius, slots);
     auto f = ctx->plans.find(key);
     if (f != ctx->plans.end()) { *out = f->second.get(); return NVSM_OK; }
     std::unique_ptr<DevicePlan> dp;
@@ -169,7 +209,7 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
     }
     std::string msg;
     try {
-        if (!build_plan(p->patch, p->u_cut, p->v_radius, bispec_slots(), &dp->h, &msg)) return fail(ctx, NVSM_ERR_INVALID_ARG, msg);
+        if (!build_plan(p->patch, p->u_cut, p->v_radius, slots, &dp->h, &msg)) return fail(ctx, NVSM_ERR_INVALID_ARG, msg);
     } catch (const std::bad_alloc &) {
         return fail(ctx, NVSM_ERR_OOM, "host allocation failed while planning");
     }
@@ -202,6 +242,10 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
     return NVSM_OK;
 }
 
+nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) {
+    return get_plan(ctx, p, choice_of(ctx, p).first, out);
+}
+
 // Records an event pair around one stage when profiling is on.
 struct StageTimer {
     nvsm_context *ctx;
@@ -228,17 +272,26 @@ struct StageTimer {
     }
 };
 
-hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const Sizes &z,
-                          const void *frames, nvsm_dtype dtype, int F, int H, int W, int64_t pitch,
-                          float *power, float *mean_spec, float *mu, float *bispec, char *ws,
-                          hipStream_t st) {
+// 4-pixel vector loads need every quad of a patch row aligned to its size.
+bool vec_ok(const nvsm_params *p, const BurstTable &bt, size_t px_bytes) {
+    for (int i = 0; i < bt.nb; ++i) {
+        const BurstDesc &d = bt.b[i];
+        if (p->stride % 4 || (d.W - p->patch) % 4 || d.pitch % 4 || ((uintptr_t)d.frames % (4 * px_bytes)))
+            return false;
+    }
+    return true;
+}
+
+hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
+                          const Sizes &z, nvsm_dtype dtype, float *power, float *mean_spec, float *mu,
+                          float *bispec, char *ws, hipStream_t st) {
     IngestArgs a;
     a.N = p->patch;
     a.f32 = dtype == NVSM_F32;
-    a.frames = frames;
-    a.F = F; a.H = H; a.W = W; a.pitch = pitch;
-    a.patches = (int)z.P; a.nx = z.t.nx; a.stride = p->stride;
-    a.chunk_frames = CHUNK_FRAMES; a.nchunks = z.chunks; a.window = p->window;
+    a.bt = bt;
+    a.stride = p->stride;
+    a.chunk_frames = CHUNK_FRAMES; a.window = p->window;
+    a.vec = vec_ok(p, bt, a.f32 ? 4 : 2);
     a.inv_wsum = (float)(1.0 / (p->window ? dp->h.hann_sum2 : (double)p->patch * p->patch));
     a.twiddle = dp->twiddle; a.hann = dp->hann;
     a.spectra = (float2 *)ws;
@@ -253,51 +306,82 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
     }
     if (e != hipSuccess || bispec == nullptr) return e;
     BispecArgs b;
-    b.N = p->patch; b.spectra = a.spectra; b.F = F; b.patches = (int)z.P;
-    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy; b.slot_v = dp->slot; b.out_idx = dp->out_idx;
+    b.N = p->patch; b.bt = bt; b.spectra = a.spectra;
+    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy;
+    b.slot_v = dp->slot; b.out_idx = dp->out_idx;
     b.bispec = (float2 *)bispec; b.s_count = z.S;
+    b.form = choice_of(ctx, p).second; b.queue = ctx->queue;
     StageTimer t(ctx, ST_BISPEC, st);
     return launch_bispec(b, st);
 }
 
-hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, int64_t P, const float *power,
-                     const float *mean_spec, const float *bispec, const double *stf, double *amp,
+hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
+                     const float *power, const float *mean_spec, const float *bispec, double *amp,
                      double *phasor, hipStream_t st) {
     SolveArgs a;
-    a.N = p->patch; a.patches = (int)P; a.nW = (int)(dp->h.W.size() / 2); a.nshell = dp->nshell;
+    a.N = p->patch; a.bt = bt; a.nW = (int)(dp->h.W.size() / 2); a.nshell = dp->nshell;
     a.max_sw = dp->max_sw; a.shell_wb = dp->shell_wb; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
     a.w_slot = dp->w_slot; a.n_inner = dp->h.n_inner; a.ring = dp->h.ring_size;
     a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;
-    a.stf = stf; a.floor = p->stf_floor; a.noise_bias = p->noise_bias; a.amp = amp;
+    a.floor = p->stf_floor; a.noise_bias = p->noise_bias; a.amp = amp;
     a.phasor = (double2 *)phasor;
     StageTimer t(ctx, ST_SOLVE, st);
     return launch_solve(a, st);
 }
 
-hipError_t run_synth(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const Sizes &z, int H, int W,
-                     const double *amp, const double *phasor, const float *mu, float *patch_buf,
-                     float *out, hipStream_t st) {
+hipError_t run_synth(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
+                     const double *amp, const double *phasor, const float *mu, float *patch_buf, bool mosaic,
+                     hipStream_t st) {
     SynthArgs a;
-    a.N = p->patch; a.patches = (int)z.P; a.nW = (int)z.nW; a.window = p->window; a.Wxy = dp->W;
+    a.N = p->patch; a.bt = bt; a.nW = (int)(dp->h.W.size() / 2); a.window = p->window; a.Wxy = dp->W;
     a.amp = amp; a.phasor = (const double2 *)phasor; a.filt = p->filter ? dp->filt : nullptr;
     a.mu = mu; a.hann = dp->hann; a.twiddle = dp->twiddle; a.patch_buf = patch_buf;
-    a.H = H; a.W = W; a.ny = z.t.ny; a.nx = z.t.nx; a.stride = p->stride; a.out = out;
+    a.stride = p->stride; a.mosaic = mosaic;
     StageTimer t(ctx, ST_SYNTH, st);
     return launch_synth(a, st);
+}
+
+// The whole path for the bursts of one table, in a workspace laid out as
+// power, mean spectrum, mean level, bispectrum, modulus, phasors,
+// subimages, then the accumulate scratch.
+hipError_t run_reconstruct(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
+                           const Sizes &z, nvsm_dtype dtype, char *w, hipStream_t st) {
+    float *power = (float *)w; w += z.power;
+    float *mean = (float *)w; w += z.mean;
+    float *mu = (float *)w; w += z.mu;
+    float *bis = (float *)w; w += z.bispec;
+    double *amp = (double *)w; w += z.amp;
+    double *ph = (double *)w; w += z.phasor;
+    float *pat = (float *)w; w += z.patches;
+    hipError_t e = run_accumulate(ctx, dp, p, bt, z, dtype, power, mean, mu, bis, w, st);
+    if (e != hipSuccess) return e;
+    e = run_solve(ctx, dp, p, bt, power, mean, bis, amp, ph, st);
+    if (e != hipSuccess) return e;
+    return run_synth(ctx, dp, p, bt, amp, ph, mu, pat, true, st);
 }
 
 nvsm_status hip_fail(nvsm_context *ctx, hipError_t e, const char *where) {
     return fail(ctx, NVSM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-nvsm_status prepare_call(nvsm_context *ctx, const nvsm_params *p, int H, int W, int F,
-                         DevicePlan **dp, Sizes *z) {
+nvsm_status check_burst(const nvsm_params *p, const BurstIn &bi, std::string *msg) {
+    nvsm_status s = check_shape(p, bi.H, bi.W, bi.F, msg);
+    if (s != NVSM_OK) return s;
+    if (bi.pitch < bi.W) { *msg = "row_pitch < W"; return NVSM_ERR_SHAPE; }
+    return NVSM_OK;
+}
+
+// Validates one burst and builds its table and sizes.
+nvsm_status prepare_call(nvsm_context *ctx, const nvsm_params *p, const BurstIn &bi, DevicePlan **dp,
+                         BurstTable *bt, Sizes *z) {
     std::string msg;
     nvsm_status s = check_params(p, &msg);
     if (s != NVSM_OK) return fail(ctx, s, msg);
-    if ((s = check_shape(p, H, W, F, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    if ((s = check_burst(p, bi, &msg)) != NVSM_OK) return fail(ctx, s, msg);
     if ((s = get_plan(ctx, p, dp)) != NVSM_OK) return s;
-    sizes_of(p, H, W, F, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, (*dp)->nshell, z);
+    int64_t rec;
+    make_table(p, &bi, 1, bt, &rec);
+    sizes_for(p->patch, *bt, rec, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, z);
     return NVSM_OK;
 }
 
@@ -362,15 +446,20 @@ nvsm_status nvsm_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t F, nvs
     } catch (const std::bad_alloc &) {
         return NVSM_ERR_OOM;
     }
+    BurstIn bi;
+    bi.F = F; bi.H = H; bi.W = W; bi.pitch = W;
+    BurstTable bt;
+    int64_t rec;
+    make_table(p, &bi, 1, &bt, &rec);
     Sizes z;
-    sizes_of(p, H, W, F, nW, S, shells, &z);
-    out->patches_y = z.t.ny;
-    out->patches_x = z.t.nx;
+    sizes_for(p->patch, bt, rec, nW, S, &z);
+    out->patches_y = bt.b[0].ny;
+    out->patches_x = bt.b[0].nx;
     out->patches = z.P;
     out->w_count = nW;
     out->s_count = S;
     out->shells = shells;
-    out->frame_chunks = z.chunks;
+    out->frame_chunks = (F + CHUNK_FRAMES - 1) / CHUNK_FRAMES;
     out->ws_accumulate = ws_acc(z);
     out->ws_solve = 0;
     out->ws_synthesize = z.patches;
@@ -418,14 +507,16 @@ nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p, const void 
     if (!ctx) return NVSM_ERR_INVALID_ARG;
     if (!frames || !power || !mean_spec || !mu) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
     if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
-    if (row_pitch < W) return fail(ctx, NVSM_ERR_SHAPE, "row_pitch < W");
+    BurstIn bi;
+    bi.frames = frames; bi.F = F; bi.H = H; bi.W = W; bi.pitch = row_pitch;
     DevicePlan *dp;
+    BurstTable bt;
     Sizes z;
-    nvsm_status s = prepare_call(ctx, p, H, W, F, &dp, &z);
+    nvsm_status s = prepare_call(ctx, p, bi, &dp, &bt, &z);
     if (s != NVSM_OK) return s;
     if (!workspace || workspace_bytes < ws_acc(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for accumulate");
-    hipError_t e = run_accumulate(ctx, dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean_spec, mu, bispec,
-                                  (char *)workspace, (hipStream_t)stream);
+    hipError_t e = run_accumulate(ctx, dp, p, bt, z, dtype, power, mean_spec, mu, bispec, (char *)workspace,
+                                  (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
     return NVSM_OK;
 }
@@ -443,7 +534,11 @@ nvsm_status nvsm_solve(nvsm_context *ctx, const nvsm_params *p, int64_t patches,
     if (!power || !mean_spec || !bispec || !stf || !amp || !phasor) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
     DevicePlan *dp;
     if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;
-    hipError_t e = run_solve(ctx, dp, p, patches, power, mean_spec, bispec, stf, amp, phasor, (hipStream_t)stream);
+    BurstTable bt;
+    bt.nb = 1;
+    bt.patches = (int)patches;
+    bt.b[0].stf = stf;
+    hipError_t e = run_solve(ctx, dp, p, bt, power, mean_spec, bispec, amp, phasor, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
     return NVSM_OK;
 }
@@ -453,16 +548,19 @@ nvsm_status nvsm_synthesize(nvsm_context *ctx, const nvsm_params *p, int32_t H, 
                             void *workspace, size_t workspace_bytes, void *stream) {
     if (!ctx) return NVSM_ERR_INVALID_ARG;
     if (!amp || !phasor || !mu || !out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    BurstIn bi;
+    bi.F = 1; bi.H = H; bi.W = W; bi.pitch = W; bi.out = out;
     DevicePlan *dp;
+    BurstTable bt;
     Sizes z;
-    nvsm_status s = prepare_call(ctx, p, H, W, 1, &dp, &z);
+    nvsm_status s = prepare_call(ctx, p, bi, &dp, &bt, &z);
     if (s != NVSM_OK) return s;
     float *pb = patches_out;
     if (!pb) {
         if (!workspace || workspace_bytes < z.patches) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for synthesize");
         pb = (float *)workspace;
     }
-    hipError_t e = run_synth(ctx, dp, p, z, H, W, amp, phasor, mu, pb, out, (hipStream_t)stream);
+    hipError_t e = run_synth(ctx, dp, p, bt, amp, phasor, mu, pb, true, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
     return NVSM_OK;
 }
@@ -473,28 +571,187 @@ nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p, const void
     if (!ctx) return NVSM_ERR_INVALID_ARG;
     if (!frames || !stf || !out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
     if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
-    if (row_pitch < W) return fail(ctx, NVSM_ERR_SHAPE, "row_pitch < W");
+    BurstIn bi;
+    bi.frames = frames; bi.F = F; bi.H = H; bi.W = W; bi.pitch = row_pitch; bi.stf = stf; bi.out = out;
     DevicePlan *dp;
+    BurstTable bt;
     Sizes z;
-    nvsm_status s = prepare_call(ctx, p, H, W, F, &dp, &z);
+    nvsm_status s = prepare_call(ctx, p, bi, &dp, &bt, &z);
     if (s != NVSM_OK) return s;
     if (!workspace || workspace_bytes < ws_rec(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for reconstruct");
+    hipError_t e = run_reconstruct(ctx, dp, p, bt, z, dtype, (char *)workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reconstruct launch");
+    return NVSM_OK;
+}
+
+// Splits the bursts, in order, into launch groups of at most MAX_BURSTS
+// whose workspace fits in cap bytes (a group of one burst always forms).
+static void batch_groups(const nvsm_params *p, const BurstIn *bi, int n, int64_t nW, int64_t S, size_t cap,
+                         std::vector<std::pair<int, int>> *groups, size_t *largest) {
+    groups->clear();
+    *largest = 0;
+    int i = 0;
+    while (i < n) {
+        int j = i + 1;
+        BurstTable bt;
+        int64_t rec;
+        Sizes z;
+        make_table(p, bi + i, 1, &bt, &rec);
+        sizes_for(p->patch, bt, rec, nW, S, &z);
+        size_t need = ws_rec(z);
+        while (j < n && j - i < MAX_BURSTS) {
+            make_table(p, bi + i, j + 1 - i, &bt, &rec);
+            sizes_for(p->patch, bt, rec, nW, S, &z);
+            if (ws_rec(z) > cap) break;
+            need = ws_rec(z);
+            ++j;
+        }
+        *largest = std::max(*largest, need);
+        groups->push_back({i, j});
+        i = j;
+    }
+}
+
+static nvsm_status read_bursts(const nvsm_params *p, const nvsm_burst *bursts, int32_t n, bool need_ptrs,
+                               std::vector<BurstIn> *bi, std::string *msg) {
+    if (!bursts || n < 1) { *msg = "no bursts"; return NVSM_ERR_INVALID_ARG; }
+    bi->resize(n);
+    for (int i = 0; i < n; ++i) {
+        BurstIn &b = (*bi)[i];
+        b.frames = bursts[i].frames; b.F = bursts[i].F; b.H = bursts[i].H; b.W = bursts[i].W;
+        b.pitch = bursts[i].row_pitch; b.stf = bursts[i].stf; b.out = bursts[i].out;
+        if (need_ptrs && (!b.frames || !b.stf || !b.out)) { *msg = "null buffer in burst " + std::to_string(i); return NVSM_ERR_INVALID_ARG; }
+        nvsm_status s = check_burst(p, b, msg);
+        if (s != NVSM_OK) { *msg += " (burst " + std::to_string(i) + ")"; return s; }
+    }
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_batch_plan(const nvsm_params *p, const nvsm_burst *bursts, int32_t n, size_t *ws_min,
+                            size_t *ws_all) {
+    std::string msg;
+    if (!ws_min || !ws_all) return NVSM_ERR_INVALID_ARG;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return s;
+    std::vector<BurstIn> bi;
+    if ((s = read_bursts(p, bursts, n, false, &bi, &msg)) != NVSM_OK) return s;
+    int64_t nW, S;
+    int shells;
+    try {
+        count_sets(p, &nW, &S, &shells);
+    } catch (const std::bad_alloc &) {
+        return NVSM_ERR_OOM;
+    }
+    std::vector<std::pair<int, int>> g;
+    size_t largest;
+    batch_groups(p, bi.data(), n, nW, S, 0, &g, &largest);          // one burst per group
+    *ws_min = largest;
+    batch_groups(p, bi.data(), n, nW, S, SIZE_MAX, &g, &largest);   // groups of MAX_BURSTS
+    *ws_all = largest;
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_reconstruct_batch(nvsm_context *ctx, const nvsm_params *p, nvsm_dtype dtype,
+                                   const nvsm_burst *bursts, int32_t n, void *workspace, size_t workspace_bytes,
+                                   void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    std::string msg;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    std::vector<BurstIn> bi;
+    if ((s = read_bursts(p, bursts, n, true, &bi, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    DevicePlan *dp;
+    if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;
+    const int64_t nW = (int64_t)(dp->h.W.size() / 2), S = dp->h.s_count;
+    std::vector<std::pair<int, int>> groups;
+    size_t largest;
+    batch_groups(p, bi.data(), n, nW, S, workspace_bytes, &groups, &largest);
+    if (!workspace || workspace_bytes < largest) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for the largest burst");
+    for (auto &g : groups) {
+        BurstTable bt;
+        int64_t rec;
+        Sizes z;
+        make_table(p, bi.data() + g.first, g.second - g.first, &bt, &rec);
+        sizes_for(p->patch, bt, rec, nW, S, &z);
+        hipError_t e = run_reconstruct(ctx, dp, p, bt, z, dtype, (char *)workspace, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "batch launch");
+    }
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_autotune(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
+                          int32_t F, int32_t H, int32_t W, int64_t row_pitch, void *workspace,
+                          size_t workspace_bytes, void *stream, int32_t *slots_out, int32_t *form_out) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!frames) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    BurstIn bi;
+    bi.frames = frames; bi.F = F; bi.H = H; bi.W = W; bi.pitch = row_pitch;
+    DevicePlan *dp;
+    BurstTable bt;
+    Sizes z;
+    nvsm_status s = prepare_call(ctx, p, bi, &dp, &bt, &z);
+    if (s != NVSM_OK) return s;
+    if (!workspace || workspace_bytes < ws_rec(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for autotune");
+    hipStream_t st = (hipStream_t)stream;
     char *w = (char *)workspace;
     float *power = (float *)w; w += z.power;
     float *mean = (float *)w; w += z.mean;
     float *mu = (float *)w; w += z.mu;
     float *bis = (float *)w; w += z.bispec;
-    double *amp = (double *)w; w += z.amp;
-    double *ph = (double *)w; w += z.phasor;
-    float *pat = (float *)w; w += z.patches;
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = run_accumulate(ctx, dp, p, z, frames, dtype, F, H, W, row_pitch, power, mean, mu, bis, w, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
-    e = run_solve(ctx, dp, p, z.P, power, mean, bis, stf, amp, ph, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
-    e = run_synth(ctx, dp, p, z, H, W, amp, ph, mu, pat, out, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
+    w += z.amp + z.phasor + z.patches;
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    // spectra once; the candidates only differ in the bispectrum launch
+    hipError_t e = run_accumulate(ctx, dp, p, bt, z, dtype, power, mean, mu, nullptr, w, st);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    std::pair<int, int> pick(16, 0);
+    const int cand[4][2] = {{16, 0}, {16, 1}, {24, 0}, {24, 1}};
+    for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+        DevicePlan *dc;
+        if ((s = get_plan(ctx, p, cand[c][0], &dc)) != NVSM_OK) break;
+        BispecArgs b;
+        b.N = p->patch; b.bt = bt; b.spectra = (const float2 *)w;
+        b.n_items = dc->h.n_items; b.slots = dc->h.slots; b.items = dc->items; b.group_xy = dc->group_xy;
+        b.slot_v = dc->slot; b.out_idx = dc->out_idx; b.bispec = (float2 *)bis; b.s_count = z.S;
+        b.form = cand[c][1]; b.queue = ctx->queue;
+        float t = 1e30f;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {       // the first run warms up
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = launch_bispec(b, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) t = std::min(t, ms);
+        }
+        if (e == hipSuccess && t < best) { best = t; pick = std::make_pair(cand[c][0], cand[c][1]); }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ctx->prof = prof;
+    if (s != NVSM_OK) return s;
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
+    ctx->tuned[std::make_tuple(p->patch, p->u_cut, p->v_radius)] = pick;
+    if (slots_out) *slots_out = pick.first;
+    if (form_out) *form_out = pick.second;
     return NVSM_OK;
+}
+
+nvsm_status nvsm_set_launch(nvsm_context *ctx, const nvsm_params *p, int32_t slots, int32_t form) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    std::string msg;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    if ((slots != 16 && slots != 24) || (form != 0 && form != 1))
+        return fail(ctx, NVSM_ERR_INVALID_ARG, "slots must be 16 or 24 and form 0 or 1");
+    ctx->tuned[std::make_tuple(p->patch, p->u_cut, p->v_radius)] = std::make_pair((int)slots, (int)form);
+    DevicePlan *dp;
+    return get_plan(ctx, p, &dp);
 }
 
 nvsm_status nvsm_profile_enable(nvsm_context *ctx, int32_t enable) {

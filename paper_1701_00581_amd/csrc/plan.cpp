@@ -260,7 +260,7 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
         for (const Item &gt : gitems) maxh = std::max(maxh, gt.rh);
         int pitch = maxw + (maxw & 1), best = 1 << 30;
         for (int cand = maxw + (maxw & 1); cand < maxw + 33; cand += 2) {
-            if (cand * maxh > BS_MAX_REGION) break;
+            if (cand * maxh > bs_max_region(K)) break;
             int c16[16] = {}, c32[32] = {};
             for (int i : gset) {
                 const int key = ((pl->W[2 * i] + cand * pl->W[2 * i + 1]) % 32 + 32) % 32;
@@ -320,7 +320,7 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
             int cstart[BS_WAVES + 1];
             cstart[0] = u0;
             for (int c = 0; c < BS_WAVES; ++c) cstart[c + 1] = cstart[c] + m / BS_WAVES + (c < m % BS_WAVES ? 1 : 0);
-            if (pitch * rh > BS_MAX_REGION) { *err = "bispectrum region too large"; return false; }
+            if (pitch * rh > bs_max_region(K)) { *err = "bispectrum region too large"; return false; }
             pl->max_region = std::max(pl->max_region, pitch * rh);
             int32_t it[BS_ITEM_INTS] = {gi, rx0, ry0, rw, rh, rw * rh, pitch, 0, ns, ns, ns, ns};
             for (int wv = 0; wv < BS_WAVES; ++wv) {

@@ -14,7 +14,9 @@ namespace nvsm {
 constexpr int BS_LANES = 64;
 constexpr int BS_MAX_SLOTS = 32;     // largest slot count per wave
 constexpr int BS_WAVES = 4;            // waves per workgroup
-constexpr int BS_MAX_REGION = 1536;    // staged region extent (pitch x height) per frame, whole 128s
+// Staged region extent (pitch x height) per frame, in whole 128s: larger
+// for more slots per wave, whose items span more v.
+constexpr int bs_max_region(int slots) { return slots <= 16 ? 1536 : 2048; }
 constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
 
 struct Tiling {
