@@ -41,6 +41,7 @@ WORKLOADS = {
     "burst2560": dict(v_radius=12, patch=128, noise_bias=1, filter=1),
     "burst1024": dict(v_radius=10, patch=128, noise_bias=1, filter=1),
     "single64": dict(v_radius=8, patch=64, window=0, noise_bias=1, filter=1),
+    "batch16": None,
 }
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_bispec_burst2560_traffic.md")
@@ -102,6 +103,123 @@ def cpu_baseline(frames, stf, op, n_patches_total, ny, nx, workers):
                 wall_s=wall)
 
 
+def batch16(args):
+    """16 bursts of uneven shape: 8 x 2560x2160 (|v| <= 12) and 8 x 1024x1024
+    (|v| <= 10), uint16, frame counts uniform in [80, 150], 128^2 patches.
+    Three ways, same images: one nvsm_reconstruct per burst (plain
+    launches); nvsm_reconstruct_batch per parameter class (eager); the two
+    batch calls captured once in a HIP graph and replayed."""
+    import dataclasses
+    import synth
+    import torch
+    import paper_1701_00581_amd as nv
+    rng = np.random.default_rng(170100581)
+    Fs = rng.integers(80, 151, size=16)
+    classes = []
+    t = time.perf_counter()
+    for c, (base, R, n0) in enumerate((("burst2560", 12, 0), ("burst1024", 10, 8))):
+        cfg0 = synth.CONFIGS[base]
+        stf = torch.from_numpy(synth.stf_table(cfg0, screens=args.stf_screens)).cuda()
+        p = nv.default_params(128, v_radius=R, noise_bias=1, filter=1)
+        items = []
+        for i in range(8):
+            cfg = dataclasses.replace(cfg0, name=f"{base}-{i}", index=100 + n0 + i, F=int(Fs[n0 + i]))
+            fr = synth.make_burst(cfg)
+            d = torch.from_numpy(fr.view(np.int16)).cuda()
+            items.append((d, stf, torch.empty((cfg.H, cfg.W), device="cuda")))
+            del fr
+        classes.append((p, items))
+    print(f"[bench] generated 16 bursts (F = {list(map(int, Fs))}) in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    ctx = nv.nvsm_create(0)
+    terms = 0
+    cap = int(args.batch_ws_gib * (1 << 30))
+    ws_need = 0
+    for p, items in classes:
+        nv.nvsm_prepare(ctx, p)
+        info = nv.nvsm_plan(p, 128, 128, 1)
+        for d, _, _ in items:
+            F, H, W = d.shape
+            terms += nv.nvsm_plan(p, H, W, F).patches * info.s_count * F
+        lo, hi = nv.nvsm_batch_plan(p, [tuple(d.shape) for d, _, _ in items])
+        ws_need = max(ws_need, lo)
+    ws = torch.empty(max(ws_need, min(cap, ws_need * 16)), dtype=torch.uint8, device="cuda")
+    # tuned launch choices (identical outputs), one burst per class
+    tuned = []
+    for p, items in classes:
+        d = items[0][0]
+        info = nv.nvsm_plan(p, d.shape[1], d.shape[2], d.shape[0])
+        wt = ws if ws.numel() >= info.ws_reconstruct else torch.empty(info.ws_reconstruct, dtype=torch.uint8,
+                                                                          device="cuda")
+        tuned.append(nv.nvsm_autotune(ctx, p, d, wt))
+        del wt
+    wsr = {}
+
+    def plain():
+        for p, items in classes:
+            for d, stf, out in items:
+                F, H, W = d.shape
+                need = nv.nvsm_plan(p, H, W, F).ws_reconstruct
+                nv.nvsm_reconstruct(ctx, p, d, stf, out, ws if ws.numel() >= need else wsr.setdefault(
+                    need, torch.empty(need, dtype=torch.uint8, device="cuda")))
+
+    def batched():
+        for p, items in classes:
+            nv.nvsm_reconstruct_batch(ctx, p, items, ws)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    plain()
+    ref = [o.clone() for _, items in classes for _, _, o in items]
+    t_plain = timed(plain, args.steps)
+    batched()
+    same_b = all(torch.equal(o, r) for o, r in zip([o for _, items in classes for _, _, o in items], ref))
+    t_batch = timed(batched, args.steps)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batched()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batched()
+    t_graph = timed(g.replay, args.steps)
+    same_g = all(torch.equal(o, r) for o, r in zip([o for _, items in classes for _, _, o in items], ref))
+    stage = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        nv.nvsm_profile_read(ctx)
+        nv.nvsm_profile_enable(ctx, True)
+        fn()
+        torch.cuda.synchronize()
+        nv.nvsm_profile_enable(ctx, False)
+        stage[name] = {k: round(v[0], 3) for k, v in nv.nvsm_profile_read(ctx).items()}
+    out = {
+        "metric": "bursts/s of a 16-burst uneven batch (8 x 2560x2160 + 8 x 1024x1024, F in [80,150])",
+        "value": 16 / t_graph, "unit": "bursts/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_graph * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch16: 8 x 2560x2160 (|v|<=12) + 8 x 1024x1024 (|v|<=10) uint16 bursts, "
+                               f"F = {list(map(int, Fs))}, 128x128 patches, one HIP graph of two batch calls",
+                   "terms": int(terms), "workspace_GiB": ws.numel() / (1 << 30),
+                   "tuned_launch": [{"slots": k, "form": f} for k, f in tuned], "parallelism": "single GPU"},
+        "per_burst_plain": {"bursts_per_s": 16 / t_plain, "ms": t_plain * 1e3},
+        "batched_eager": {"bursts_per_s": 16 / t_batch, "ms": t_batch * 1e3, "identical": bool(same_b)},
+        "batched_graph": {"bursts_per_s": 16 / t_graph, "ms": t_graph * 1e3, "identical": bool(same_g)},
+        "terms_per_s": terms / t_graph,
+        "stage_ms_per_batch": stage,
+    }
+    print(json.dumps(out), flush=True)
+    del g
+    nv.nvsm_destroy(ctx)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,11 +232,15 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for traffic counters)")
+    ap.add_argument("--batch-ws-gib", type=float, default=96.0, help="workspace cap of the batch16 workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs the path on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
+    if args.workload == "batch16":
+        batch16(args)
+        return
 
     import oracle
     import synth

@@ -254,6 +254,25 @@ __device__ __forceinline__ void bispec_one(int L, float2 *lds0, float2 *lds1, co
                                  s_count, invF);
 }
 
+// Item of position o in the launch order.  The order takes, for each XCD
+// slot x = 0..7 in turn, slice x (an eighth of the patches) of every burst,
+// so that the 8 contiguous ranges the XCDs work on (see xcd_remap) hold the
+// same share of every burst even when the bursts' frame counts differ.
+// With one burst it is the plain patch-major order.
+__device__ __forceinline__ int item_at(const BurstTable &bt, int o, int n_items) {
+    if (bt.nb == 1) return o;
+    int ps = o / n_items;                      // patch position in the order
+    const int g = o % n_items;
+    for (int x = 0; x < 8; ++x)
+        for (int b = 0; b < bt.nb; ++b) {
+            const int P = (b + 1 < bt.nb ? bt.b[b + 1].patch0 : bt.patches) - bt.b[b].patch0;
+            const int lo = P * x / 8, cnt = P * (x + 1) / 8 - lo;
+            if (ps < cnt) return (bt.b[b].patch0 + lo + ps) * n_items + g;
+            ps -= cnt;
+        }
+    return o;                                  // not reached: o < patches * n_items
+}
+
 // One workgroup per item.
 template <int N, int K>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec(
@@ -264,8 +283,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
     // the other
     __shared__ float2 lds0[Region<K>::SZ];
     __shared__ float2 lds1[Region<K>::SZ];
-    bispec_one<N, K>(xcd_remap(blockIdx.x, total), lds0, lds1, bt, spec, n_items, items, group_xy, slot, out_idx,
-                     bispec, s_count);
+    bispec_one<N, K>(item_at(bt, xcd_remap(blockIdx.x, total), n_items), lds0, lds1, bt, spec, n_items, items,
+                     group_xy, slot, out_idx, bispec, s_count);
 }
 
 // Persistent form: as many workgroups as fit on the GPU at once, each
@@ -295,8 +314,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
             __syncthreads();
             const int i = __builtin_amdgcn_readfirstlane(next);
             if (i >= cnt) break;
-            bispec_one<N, K>(beg + i, lds0, lds1, bt, spec, n_items, items, group_xy, slot, out_idx, bispec,
-                             s_count);
+            bispec_one<N, K>(item_at(bt, beg + i, n_items), lds0, lds1, bt, spec, n_items, items, group_xy, slot,
+                             out_idx, bispec, s_count);
         }
     }
 }
