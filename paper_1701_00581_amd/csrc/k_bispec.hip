@@ -97,7 +97,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
                                             int64_t rec0, int F, int patch, int g, const int *__restrict__ it,
                                             const int *__restrict__ group_xy, const int *__restrict__ slot,
                                             const int *__restrict__ out_idx, float2 *__restrict__ bispec,
-                                            int64_t s_count, float invF) {
+                                            int64_t s_count, float invF, const AccState acc) {
     constexpr int HALF = N / 2;
     constexpr int FS = SpecRows<N>::FS;
     constexpr int FB = FS * (int)sizeof(float2);               // bytes per stored frame
@@ -158,12 +158,27 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         for (int q = 0; q < NQ; ++q) bv[q] = as_f2(__builtin_amdgcn_raw_buffer_load_b64(rsrc, sol[q], f * FB, 0));
     };
 
+    // output index of each slot for this lane, and the patch's rows of the
+    // bispectrum and compensation arrays
+    const size_t oi0 = (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
+    const size_t po = (size_t)patch * s_count;
     float2 t[NS], s[NS], c[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         t[k] = make_float2(0.f, 0.f);
         s[k] = make_float2(0.f, 0.f);
         c[k] = make_float2(0.f, 0.f);
+    }
+    if (acc.mode != 0) {
+        // continue the running (sum, compensation) of earlier frame groups
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int o = out_idx[oi0 + k * 64];
+            if (o >= 0) {
+                s[k] = bispec[po + o];
+                c[k] = acc.comp[po + o];
+            }
+        }
     }
 
     float2 cw, bv[NQ];
@@ -215,10 +230,24 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
 
     const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
     float2 *bo = bispec + (size_t)patch * s_count;
+    if (acc.mode == 1) {
+        // keep the running (sum, compensation) for the next frame group
+        float2 *co = acc.comp + (size_t)patch * s_count;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int o = oi[k * 64];
+            if (o >= 0) {
+                bo[o] = s[k];
+                co[o] = c[k];
+            }
+        }
+        return;
+    }
+    const float inv = acc.mode == 2 ? acc.inv_total : invF;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const int o = oi[k * 64];
-        if (o >= 0) bo[o] = make_float2((s[k].x - c[k].x) * invF, (s[k].y - c[k].y) * invF);
+        if (o >= 0) bo[o] = make_float2((s[k].x - c[k].x) * inv, (s[k].y - c[k].y) * inv);
     }
 }
 
@@ -227,14 +256,14 @@ template <int N, int K, int Q>
 __device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *lds1, const float2 *spec,
                                                 int64_t rec0, int F, int patch, int g, const int *it, const int *group_xy,
                                                 const int *slot, const int *out_idx, float2 *bispec,
-                                                int64_t s_count, float invF) {
+                                                int64_t s_count, float invF, const AccState &acc) {
     if constexpr (Q > 0) {
         if (nq == Q)
             bispec_item<N, K, 4 * Q>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
-                                     invF);
+                                     invF, acc);
         else
             bispec_dispatch<N, K, Q - 1>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
-                                         s_count, invF);
+                                         s_count, invF, acc);
     }
 }
 
@@ -242,7 +271,8 @@ __device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *ld
 template <int N, int K>
 __device__ __forceinline__ void bispec_one(int L, float2 *lds0, float2 *lds1, const BurstTable &bt,
                                            const float2 *spec, int n_items, const int *items, const int *group_xy,
-                                           const int *slot, const int *out_idx, float2 *bispec, int64_t s_count) {
+                                           const int *slot, const int *out_idx, float2 *bispec, int64_t s_count,
+                                           const AccState &acc) {
     const int patch = L / n_items, g = L % n_items;
     const int b = burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; });
     const int F = bt.b[b].F;
@@ -251,7 +281,7 @@ __device__ __forceinline__ void bispec_one(int L, float2 *lds0, float2 *lds1, co
     const int *it = items + g * BS_ITEM_INTS;
     const int nq = __builtin_amdgcn_readfirstlane(it[8]) >> 2;   // the item's slots per wave / 4
     bispec_dispatch<N, K, K / 4>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
-                                 s_count, invF);
+                                 s_count, invF, acc);
 }
 
 // Item of position o in the launch order.  The order takes, for each XCD
@@ -278,13 +308,13 @@ template <int N, int K>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec(
     const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
     const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
-    float2 *__restrict__ bispec, int64_t s_count) {
+    float2 *__restrict__ bispec, int64_t s_count, const AccState acc) {
     // two separate arrays, so that loads into one are known not to touch
     // the other
     __shared__ float2 lds0[Region<K>::SZ];
     __shared__ float2 lds1[Region<K>::SZ];
     bispec_one<N, K>(item_at(bt, xcd_remap(blockIdx.x, total), n_items), lds0, lds1, bt, spec, n_items, items,
-                     group_xy, slot, out_idx, bispec, s_count);
+                     group_xy, slot, out_idx, bispec, s_count, acc);
 }
 
 // Persistent form: as many workgroups as fit on the GPU at once, each
@@ -299,7 +329,7 @@ template <int N, int K>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec_queue(
     const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
     const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
-    float2 *__restrict__ bispec, int64_t s_count, int *__restrict__ queue) {
+    float2 *__restrict__ bispec, int64_t s_count, const AccState acc, int *__restrict__ queue) {
     __shared__ float2 lds0[Region<K>::SZ];
     __shared__ float2 lds1[Region<K>::SZ];
     __shared__ int next;
@@ -315,7 +345,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
             const int i = __builtin_amdgcn_readfirstlane(next);
             if (i >= cnt) break;
             bispec_one<N, K>(item_at(bt, beg + i, n_items), lds0, lds1, bt, spec, n_items, items, group_xy, slot,
-                             out_idx, bispec, s_count);
+                             out_idx, bispec, s_count, acc);
         }
     }
 }
@@ -328,7 +358,7 @@ template <int N, int K>
 hipError_t launch_bispec_t(const BispecArgs &a, int total, hipStream_t st) {
     if (a.form == 0) {
         hipLaunchKernelGGL((k_bispec<N, K>), dim3(total), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
-                           a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count);
+                           a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, a.acc);
         return hipGetLastError();
     }
     if (!a.queue) return hipErrorInvalidValue;
@@ -348,7 +378,7 @@ hipError_t launch_bispec_t(const BispecArgs &a, int total, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_bispec_queue<N, K>), dim3(grid), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
-                       a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, a.queue);
+                       a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, a.acc, a.queue);
     return hipGetLastError();
 }
 

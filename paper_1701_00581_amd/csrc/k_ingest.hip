@@ -8,6 +8,8 @@
 #include "device_common.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace nvsm {
 
 namespace {
@@ -228,6 +230,49 @@ __global__ __launch_bounds__(NT) void k_acc_finalize(const BurstTable bt, int ch
     }
 }
 
+// Streaming form of k_acc_finalize for one burst: adds the frame groups of
+// this launch to running compensated sums kept between launches,
+// sc = (sum, compensation) per value: power rows 0..N/2, the two mean
+// spectrum values and the mean level.  last != 0: then writes the means
+// over all frames, (sum - comp) * inv_total, as k_acc_finalize does.
+template <int N>
+__global__ __launch_bounds__(NT) void k_acc_stream(int nchunks, const float *__restrict__ ppart,
+                                                   const float *__restrict__ mpart,
+                                                   const float *__restrict__ mupart, float2 *__restrict__ psc,
+                                                   float2 *__restrict__ msc, float2 *__restrict__ musc, int last,
+                                                   float inv_total, float *__restrict__ power,
+                                                   float *__restrict__ mean_spec, float *__restrict__ mu) {
+    constexpr int HALF = N / 2, NP = (HALF + 1) * N;
+    const int patch = blockIdx.x;
+    const float *pp = ppart + (size_t)patch * nchunks * NP;
+    float2 *ps = psc + (size_t)patch * NP;
+    for (int j = threadIdx.x; j < NP; j += NT) {
+        float2 v = ps[j];
+        for (int k = 0; k < nchunks; ++k) kahan_add(v.x, v.y, pp[(size_t)k * NP + j]);
+        ps[j] = v;
+    }
+    if (threadIdx.x < 4) {
+        float2 v = msc[(size_t)patch * 4 + threadIdx.x];
+        for (int k = 0; k < nchunks; ++k) kahan_add(v.x, v.y, mpart[((size_t)patch * nchunks + k) * 4 + threadIdx.x]);
+        msc[(size_t)patch * 4 + threadIdx.x] = v;
+        if (last) mean_spec[(size_t)patch * 4 + threadIdx.x] = (v.x - v.y) * inv_total;
+    }
+    if (threadIdx.x == 4) {
+        float2 v = musc[patch];
+        for (int k = 0; k < nchunks; ++k) kahan_add(v.x, v.y, mupart[(size_t)patch * nchunks + k]);
+        musc[patch] = v;
+        if (last) mu[patch] = (v.x - v.y) * inv_total;
+    }
+    if (!last) return;
+    __syncthreads();
+    for (int j = threadIdx.x; j < N * N; j += NT) {
+        const int uy = j / N, ux = j % N;
+        const int src = uy <= HALF ? j : ((N - uy) * N + ((N - ux) & (N - 1)));
+        const float2 v = ps[src];
+        power[(size_t)patch * N * N + j] = (v.x - v.y) * inv_total;
+    }
+}
+
 template <int N, typename T>
 hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
     if (a.vec)
@@ -240,12 +285,32 @@ hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
                            a.mupart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_acc_finalize<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames, a.ppart,
-                       a.mpart, a.mupart, a.power, a.mean_spec, a.mu);
+    if (a.stream_mode == 0) {
+        hipLaunchKernelGGL((k_acc_finalize<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames,
+                           a.ppart, a.mpart, a.mupart, a.power, a.mean_spec, a.mu);
+    } else {
+        const int nchunks = (a.bt.b[0].F + a.chunk_frames - 1) / a.chunk_frames;
+        hipLaunchKernelGGL((k_acc_stream<N>), dim3(a.bt.patches), dim3(NT), 0, st, nchunks, a.ppart, a.mpart,
+                           a.mupart, a.psc, a.msc, a.musc, a.stream_mode == 2 ? 1 : 0, a.inv_total, a.power,
+                           a.mean_spec, a.mu);
+    }
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(NT) void k_zero(float4 *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 }  // namespace
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + NT - 1) / NT, 8192);
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(NT), 0, st, (float4 *)p, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_ingest(const IngestArgs &a, hipStream_t st) {
     if (a.bt.patches == 0) return hipSuccess;

@@ -43,8 +43,26 @@ struct IngestArgs {
     float2 *spectra = nullptr;            // [records][N/2 + 16][N], rows -16 .. N/2-1
     float *ppart = nullptr, *mpart = nullptr, *mupart = nullptr;   // per ingest workgroup
     float *power = nullptr, *mean_spec = nullptr, *mu = nullptr;   // per patch
+    // streaming (one burst): 0 all frames at once; 1 add this frame group
+    // to the running sums; 2 add the last group and write the means
+    int stream_mode = 0;
+    float2 *psc = nullptr, *msc = nullptr, *musc = nullptr;        // running (sum, compensation)
+    float inv_total = 0.f;
 };
 hipError_t launch_ingest(const IngestArgs &a, hipStream_t st);
+// Zeroes bytes (a multiple of 16, 16-byte aligned) with a fill kernel.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
+// Accumulator handling of the bispectrum launch.  mode 0: the launch covers
+// all frames and writes the mean.  mode 1: the launch adds a group of
+// frames to a running compensated sum kept between launches (sum in the
+// bispectrum array, compensation in comp).  mode 2: as 1 for the last group,
+// then writes the mean, (sum - comp) * inv_total, to the bispectrum array.
+struct AccState {
+    float2 *comp = nullptr;               // [P][|S|]
+    int mode = 0;
+    float inv_total = 0.f;
+};
 
 struct BispecArgs {
     int N = 0;
@@ -56,6 +74,7 @@ struct BispecArgs {
     int64_t s_count = 0;
     int form = 0;                         // 0: one workgroup per item, 1: persistent work queue
     int *queue = nullptr;                 // [8] counters for the work queue
+    AccState acc;
 };
 hipError_t launch_bispec(const BispecArgs &a, hipStream_t st);
 

@@ -160,6 +160,54 @@ size_t ws_rec(const Sizes &z) {
     return z.power + z.mean + z.mu + z.bispec + z.amp + z.phasor + z.patches + ws_acc(z);
 }
 
+// Streaming state of one burst: running (sum, compensation) of the
+// bispectrum and of the power / mean sums, then the solve and synthesis
+// buffers.  The bispectrum sum array receives the mean at the last group.
+struct StreamSizes {
+    size_t bis_s = 0, bis_c = 0, psc = 0, msc = 0, musc = 0;   // zeroed by nvsm_stream_begin
+    size_t power = 0, mean = 0, mu = 0, amp = 0, phasor = 0, patches = 0;
+    size_t acc() const { return bis_s + bis_c + psc + msc + musc; }
+    size_t total() const { return acc() + power + mean + mu + amp + phasor + patches; }
+};
+
+void stream_sizes(int N, int64_t P, int64_t nW, int64_t S, StreamSizes *z) {
+    const int64_t NP = (N / 2 + 1) * N;
+    z->bis_s = align_up((size_t)P * S * 8);
+    z->bis_c = align_up((size_t)P * S * 8);
+    z->psc = align_up((size_t)P * NP * 8);
+    z->msc = align_up((size_t)P * 4 * 8);
+    z->musc = align_up((size_t)P * 8);
+    z->power = align_up((size_t)P * N * N * 4);
+    z->mean = align_up((size_t)P * 4 * 4);
+    z->mu = align_up((size_t)P * 4);
+    z->amp = align_up((size_t)P * nW * 8);
+    z->phasor = align_up((size_t)P * nW * 16);
+    z->patches = align_up((size_t)P * N * N * 4);
+}
+
+struct StreamView {
+    float2 *bis_s, *bis_c, *psc, *msc, *musc;
+    float *power, *mean, *mu;
+    double *amp, *phasor;
+    float *patches;
+};
+
+StreamView stream_view(char *w, const StreamSizes &z) {
+    StreamView v;
+    v.bis_s = (float2 *)w; w += z.bis_s;
+    v.bis_c = (float2 *)w; w += z.bis_c;
+    v.psc = (float2 *)w; w += z.psc;
+    v.msc = (float2 *)w; w += z.msc;
+    v.musc = (float2 *)w; w += z.musc;
+    v.power = (float *)w; w += z.power;
+    v.mean = (float *)w; w += z.mean;
+    v.mu = (float *)w; w += z.mu;
+    v.amp = (double *)w; w += z.amp;
+    v.phasor = (double *)w; w += z.phasor;
+    v.patches = (float *)w;
+    return v;
+}
+
 void count_sets(const nvsm_params *p, int64_t *nW, int64_t *S, int *shells) {
     std::vector<int32_t> w, wv;
     enumerate_W(p->u_cut, &w);
@@ -752,6 +800,148 @@ nvsm_status nvsm_set_launch(nvsm_context *ctx, const nvsm_params *p, int32_t slo
     ctx->tuned[std::make_tuple(p->patch, p->u_cut, p->v_radius)] = std::make_pair((int)slots, (int)form);
     DevicePlan *dp;
     return get_plan(ctx, p, &dp);
+}
+
+nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t group_frames,
+                             size_t *state_bytes, size_t *group_ws_bytes) {
+    std::string msg;
+    if (!state_bytes || !group_ws_bytes) return NVSM_ERR_INVALID_ARG;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return s;
+    if ((s = check_shape(p, H, W, group_frames, &msg)) != NVSM_OK) return s;
+    int64_t nW, S;
+    int shells;
+    try {
+        count_sets(p, &nW, &S, &shells);
+    } catch (const std::bad_alloc &) {
+        return NVSM_ERR_OOM;
+    }
+    BurstIn bi;
+    bi.F = group_frames; bi.H = H; bi.W = W; bi.pitch = W;
+    BurstTable bt;
+    int64_t rec;
+    make_table(p, &bi, 1, &bt, &rec);
+    Sizes z;
+    sizes_for(p->patch, bt, rec, nW, S, &z);
+    StreamSizes ss;
+    stream_sizes(p->patch, bt.patches, nW, S, &ss);
+    *state_bytes = ss.total();
+    *group_ws_bytes = ws_acc(z);
+    return NVSM_OK;
+}
+
+static nvsm_status stream_prep(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, void *state,
+                               size_t state_bytes, DevicePlan **dp, BurstTable *bt, StreamSizes *ss) {
+    std::string msg;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    if ((s = check_shape(p, H, W, 1, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    if ((s = get_plan(ctx, p, dp)) != NVSM_OK) return s;
+    BurstIn bi;
+    bi.F = 1; bi.H = H; bi.W = W; bi.pitch = W;
+    int64_t rec;
+    make_table(p, &bi, 1, bt, &rec);
+    stream_sizes(p->patch, bt->patches, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, ss);
+    if (!state || state_bytes < ss->total()) return fail(ctx, NVSM_ERR_WORKSPACE, "stream state too small");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_stream_begin(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, void *state,
+                              size_t state_bytes, void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    DevicePlan *dp;
+    BurstTable bt;
+    StreamSizes ss;
+    nvsm_status s = stream_prep(ctx, p, H, W, state, state_bytes, &dp, &bt, &ss);
+    if (s != NVSM_OK) return s;
+    hipError_t e = launch_zero(state, ss.acc(), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream begin");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
+                            int32_t G, int32_t H, int32_t W, int64_t row_pitch, int32_t total_frames,
+                            void *state, size_t state_bytes, void *group_ws, size_t group_ws_bytes,
+                            void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!frames) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    if (total_frames < 0) return fail(ctx, NVSM_ERR_INVALID_ARG, "total_frames < 0");
+    DevicePlan *dp;
+    BurstTable bt1;
+    StreamSizes ss;
+    nvsm_status s = stream_prep(ctx, p, H, W, state, state_bytes, &dp, &bt1, &ss);
+    if (s != NVSM_OK) return s;
+    BurstIn bi;
+    bi.frames = frames; bi.F = G; bi.H = H; bi.W = W; bi.pitch = row_pitch;
+    std::string msg;
+    if ((s = check_burst(p, bi, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    if (total_frames != 0 && total_frames < G) return fail(ctx, NVSM_ERR_INVALID_ARG, "total_frames < G");
+    BurstTable bt;
+    int64_t rec;
+    make_table(p, &bi, 1, &bt, &rec);
+    Sizes z;
+    sizes_for(p->patch, bt, rec, (int64_t)(dp->h.W.size() / 2), dp->h.s_count, &z);
+    if (!group_ws || group_ws_bytes < ws_acc(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "group workspace too small");
+    StreamView v = stream_view((char *)state, ss);
+    const int mode = total_frames ? 2 : 1;
+    const float inv_total = total_frames ? 1.0f / (float)total_frames : 0.f;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)group_ws;
+    IngestArgs a;
+    a.N = p->patch;
+    a.f32 = dtype == NVSM_F32;
+    a.bt = bt;
+    a.stride = p->stride;
+    a.chunk_frames = CHUNK_FRAMES; a.window = p->window;
+    a.vec = vec_ok(p, bt, a.f32 ? 4 : 2);
+    a.inv_wsum = (float)(1.0 / (p->window ? dp->h.hann_sum2 : (double)p->patch * p->patch));
+    a.twiddle = dp->twiddle; a.hann = dp->hann;
+    a.spectra = (float2 *)ws;
+    a.ppart = (float *)(ws + z.spectra);
+    a.mpart = (float *)(ws + z.spectra + z.ppart);
+    a.mupart = (float *)(ws + z.spectra + z.ppart + z.mpart);
+    a.power = v.power; a.mean_spec = v.mean; a.mu = v.mu;
+    a.stream_mode = mode; a.psc = v.psc; a.msc = v.msc; a.musc = v.musc; a.inv_total = inv_total;
+    hipError_t e;
+    {
+        StageTimer t(ctx, ST_INGEST, st);
+        e = launch_ingest(a, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream ingest");
+    BispecArgs b;
+    b.N = p->patch; b.bt = bt; b.spectra = a.spectra;
+    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy;
+    b.slot_v = dp->slot; b.out_idx = dp->out_idx;
+    b.bispec = v.bis_s; b.s_count = z.S;
+    b.form = choice_of(ctx, p).second; b.queue = ctx->queue;
+    b.acc.comp = v.bis_c; b.acc.mode = mode; b.acc.inv_total = inv_total;
+    {
+        StageTimer t(ctx, ST_BISPEC, st);
+        e = launch_bispec(b, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream bispectrum");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_stream_finish(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, const double *stf,
+                               float *out, void *state, size_t state_bytes, void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!stf || !out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    DevicePlan *dp;
+    BurstTable bt;
+    StreamSizes ss;
+    nvsm_status s = stream_prep(ctx, p, H, W, state, state_bytes, &dp, &bt, &ss);
+    if (s != NVSM_OK) return s;
+    bt.b[0].stf = stf;
+    bt.b[0].out = out;
+    StreamView v = stream_view((char *)state, ss);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = run_solve(ctx, dp, p, bt, v.power, v.mean, (const float *)v.bis_s, v.amp, v.phasor, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream solve");
+    e = run_synth(ctx, dp, p, bt, v.amp, v.phasor, v.mu, v.patches, true, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream synthesize");
+    return NVSM_OK;
 }
 
 nvsm_status nvsm_profile_enable(nvsm_context *ctx, int32_t enable) {

@@ -1,0 +1,129 @@
+"""Streaming accumulation (frames arriving in groups) through the C ABI.
+
+One group holding the whole burst reproduces nvsm_accumulate and
+nvsm_reconstruct bit for bit.  Several groups change only where the running
+sums are folded, so the results stay within the parity tolerances of the
+FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import (BISPEC_TOL, MOSAIC_TOL, POWER_TOL, abs_bispectrum, as_complex, bispec_errors, burst,
+                         cube, oparams, say, stf, to_device)
+
+pytestmark = pytest.mark.gpu
+
+H, W, F = 384, 448, 30
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1701_00581_amd as nv
+    nv.lib()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def setup(torch_cuda):
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    fr = burst("burst1024", F=F, H=H, W=W)
+    p = nv.default_params(128, v_radius=10, noise_bias=1, filter=1)
+    d = to_device(fr)
+    st = torch.from_numpy(stf("burst1024", screens=100)).cuda()
+    info = nv.nvsm_plan(p, H, W, F)
+    ctx = nv.nvsm_create(0)
+    # whole-burst reference: accumulate (bispectrum, power) and reconstruct
+    ref = {}
+    ref["power"] = torch.empty((info.patches, 128, 128), device="cuda")
+    ref["mean"] = torch.empty((info.patches, 2, 2), device="cuda")
+    ref["mu"] = torch.empty(info.patches, device="cuda")
+    ref["bis"] = torch.empty((info.patches, info.s_count, 2), device="cuda")
+    nv.nvsm_accumulate(ctx, p, d, ref["power"], ref["mean"], ref["mu"], ref["bis"],
+                       torch.empty(info.ws_accumulate, dtype=torch.uint8, device="cuda"))
+    ref["img"] = torch.empty((H, W), device="cuda")
+    nv.nvsm_reconstruct(ctx, p, d, st, ref["img"], torch.empty(info.ws_reconstruct, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    yield dict(fr=fr, p=p, d=d, stf=st, info=info, ctx=ctx, ref=ref)
+    nv.nvsm_destroy(ctx)
+
+
+def _stream(nv, torch, s, groups):
+    p, d, info = s["p"], s["d"], s["info"]
+    state_b, gws_b = nv.nvsm_stream_plan(p, H, W, max(groups))
+    state = torch.empty(state_b, dtype=torch.uint8, device="cuda")
+    state.fill_(0xFF)                      # begin must clear what it needs
+    gws = torch.empty(gws_b, dtype=torch.uint8, device="cuda")
+    nv.nvsm_stream_begin(s["ctx"], p, H, W, state)
+    f0 = 0
+    for i, g in enumerate(groups):
+        last = i == len(groups) - 1
+        nv.nvsm_stream_add(s["ctx"], p, d[f0:f0 + g], F if last else 0, state, gws)
+        f0 += g
+    img = torch.full((H, W), float("nan"), device="cuda")
+    nv.nvsm_stream_finish(s["ctx"], p, H, W, s["stf"], img, state)
+    torch.cuda.synchronize()
+    bis = state[: info.patches * info.s_count * 8].view(torch.float32).view(info.patches, info.s_count, 2)
+    return img, bis
+
+
+def test_stream_one_group_is_exact(torch_cuda, setup):
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    img, bis = _stream(nv, torch, setup, [F])
+    same_b = torch.equal(bis, setup["ref"]["bis"])
+    same_i = torch.equal(img, setup["ref"]["img"])
+    say(f"[stream] one group: bispectrum identical={same_b}, image identical={same_i}")
+    assert same_b and same_i
+
+
+def test_stream_groups_within_tolerance(torch_cuda, setup):
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    groups = [7, 7, 9, 6, 1]
+    assert sum(groups) == F
+    img, bis = _stream(nv, torch, setup, groups)
+    ref = setup["ref"]
+    b = as_complex(bis)
+    br = as_complex(ref["bis"])
+    rel = float(np.linalg.norm(b - br) / np.linalg.norm(br))
+    ri = ref["img"].cpu().numpy()
+    gi = img.cpu().numpy()
+    core = (slice(64, H - 64), slice(64, W - 64))
+    irel = float(np.abs(gi[core] - ri[core]).max() / ri[core].std())
+    say(f"[stream] groups {groups}: bispectrum vs whole-burst {rel:.2e}, image {irel:.2e}")
+    assert rel < BISPEC_TOL
+    assert irel < MOSAIC_TOL
+    # against the FP64 oracle, two patches
+    op = oparams(setup["p"])
+    wv = nv.nvsm_bispectrum_index(setup["p"])
+    for k in (0, setup["info"].patches - 1):
+        c = cube(setup["fr"], setup["p"], k)
+        I, _ = oracle.patch_spectra(c, op.window)
+        bo = oracle.bispectrum(I, wv)
+        A = abs_bispectrum(I, wv)
+        nrm, mx = bispec_errors(b[k], bo, A)
+        say(f"[stream] patch {k} vs oracle: B norm {nrm:.2e} B/A max {mx:.2e}")
+        assert nrm < BISPEC_TOL and mx < BISPEC_TOL
+
+
+def test_stream_errors(torch_cuda, setup):
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    p = setup["p"]
+    state_b, gws_b = nv.nvsm_stream_plan(p, H, W, 5)
+    state = torch.empty(state_b - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(nv.NvsmError) as e:
+        nv.nvsm_stream_begin(setup["ctx"], p, H, W, state)
+    assert e.value.status == -3
+    state = torch.empty(state_b, dtype=torch.uint8, device="cuda")
+    small = torch.empty(gws_b - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(nv.NvsmError) as e:
+        nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 0, state, small)
+    assert e.value.status == -3
+    with pytest.raises(nv.NvsmError):
+        nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 3, state,
+                           torch.empty(gws_b, dtype=torch.uint8, device="cuda"))
