@@ -204,36 +204,42 @@ nvsm_status nvsm_reconstruct_batch(nvsm_context *ctx, const nvsm_params *p, nvsm
                                    void *workspace, size_t workspace_bytes, void *stream);
 
 /* Streaming accumulation of one burst whose frames arrive over time (for
- * a serving loop).  The per-burst state lives in a caller-owned device
- * buffer: running compensated (Kahan) sums of the bispectrum over S, of the
- * power spectrum and of the mean spectrum and level, plus the modulus,
- * phase and subimage buffers of the final stages.
- *   nvsm_stream_plan: state bytes for an H x W burst and workspace bytes
- *     for adding groups of up to group_frames frames (host call).
- *   nvsm_stream_begin: zeroes the running sums (a fill kernel on `stream`).
+ * a serving loop).  Two caller-owned device buffers:
+ *   state (one per burst in flight): the running compensated (Kahan)
+ *     sums, (sum, compensation) pairs, of the bispectrum terms, kept in the
+ *     kernel's own order so that every pass over them is coalesced, and of
+ *     the power spectrum, mean spectrum and mean level;
+ *   ws (one per stream of calls): scratch for one group of frames and the
+ *     final buffers.  After the last group its first P * |S| * 8 bytes
+ *     hold the bispectrum means, float [P][|S|][2] in S order, as
+ *     nvsm_accumulate writes them.
+ *   nvsm_stream_plan: state and ws bytes for an H x W burst added in groups
+ *     of up to group_frames frames (host call).
  *   nvsm_stream_add: ingests G frames (device [G][H][row_pitch]) and adds
- *     their terms to the running sums, as nvsm_accumulate does for a whole
- *     burst.  Within a group the frames are summed in blocks as usual; each
- *     group's sums are folded into the running (sum, compensation) pairs.
- *     total_frames = 0 for every group but the last; for the last it is the
- *     burst's frame count F, and the call then writes the means over all F
- *     frames.  One group of all F frames gives exactly nvsm_accumulate's
- *     values.
+ *     their terms to the running sums.  frames_before = frames of this
+ *     burst already added (0 for the first group, which starts the sums
+ *     from zero whatever the state holds); total_frames = 0 except for the
+ *     last group, where it is the burst's frame count (= frames_before + G)
+ *     and the call writes the means over all frames into ws.  Within a
+ *     group frames are summed in blocks as usual; each group's sums are
+ *     folded into the running pairs.  One group of all F frames gives
+ *     exactly nvsm_accumulate's values.
  *   nvsm_stream_finish: modulus, phase, subimages and mosaic (as
- *     nvsm_solve + nvsm_synthesize) from the state, into out [H][W].
- * Calls on one state must be ordered (same stream or events); states are
- * independent, so bursts of several channels may run on several streams.
- * None of these calls allocates device memory once the plan exists. */
+ *     nvsm_solve + nvsm_synthesize) from ws after the last group, into out
+ *     [H][W].
+ * Calls on one state or one ws must be ordered (same stream or events);
+ * different states are independent, so bursts of several channels may run
+ * on several streams, each with its own ws.  The slot count of p's launch
+ * choice must not change during a burst.  None of these calls allocates
+ * device memory once the plan exists. */
 nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t group_frames,
-                             size_t *state_bytes, size_t *group_ws_bytes);
-nvsm_status nvsm_stream_begin(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W,
-                              void *state, size_t state_bytes, void *stream);
+                             size_t *state_bytes, size_t *ws_bytes);
 nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void *frames,
                             nvsm_dtype dtype, int32_t G, int32_t H, int32_t W, int64_t row_pitch,
-                            int32_t total_frames, void *state, size_t state_bytes,
-                            void *group_ws, size_t group_ws_bytes, void *stream);
+                            int32_t frames_before, int32_t total_frames, void *state,
+                            size_t state_bytes, void *ws, size_t ws_bytes, void *stream);
 nvsm_status nvsm_stream_finish(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W,
-                               const double *stf, float *out, void *state, size_t state_bytes,
+                               const double *stf, float *out, void *ws, size_t ws_bytes,
                                void *stream);
 
 /* Launch tuning for the bispectrum stage of p's plan.  The candidates are

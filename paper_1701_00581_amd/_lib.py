@@ -28,8 +28,7 @@ EXPORTS = [
     "nvsm_default_params", "nvsm_plan", "nvsm_w_index", "nvsm_bispectrum_index",
     "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
     "nvsm_profile_enable", "nvsm_profile_read", "nvsm_batch_plan", "nvsm_reconstruct_batch",
-    "nvsm_autotune", "nvsm_set_launch", "nvsm_stream_plan", "nvsm_stream_begin", "nvsm_stream_add",
-    "nvsm_stream_finish",
+    "nvsm_autotune", "nvsm_set_launch", "nvsm_stream_plan", "nvsm_stream_add", "nvsm_stream_finish",
 ]
 STAGES = ["ingest", "bispectrum", "solve", "synthesize"]
 
@@ -102,9 +101,8 @@ def lib():
                                     ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
         L.nvsm_set_launch.argtypes = [c_p, P, c_i32, c_i32]
         L.nvsm_stream_plan.argtypes = [P, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz), ctypes.POINTER(c_sz)]
-        L.nvsm_stream_begin.argtypes = [c_p, P, c_i32, c_i32, c_p, c_sz, c_p]
-        L.nvsm_stream_add.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_i32, c_p, c_sz,
-                                      c_p, c_sz, c_p]
+        L.nvsm_stream_add.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_i32, c_i32, c_p,
+                                      c_sz, c_p, c_sz, c_p]
         L.nvsm_stream_finish.argtypes = [c_p, P, c_i32, c_i32, c_p, c_p, c_p, c_sz, c_p]
         L.nvsm_profile_enable.argtypes = [c_p, c_i32]
         L.nvsm_profile_read.argtypes = [c_p, c_p, c_p, c_i32]
@@ -288,7 +286,7 @@ def nvsm_set_launch(ctx, params, slots, form):
 
 
 def nvsm_stream_plan(params, H, W, group_frames):
-    """(state bytes, group workspace bytes)."""
+    """(state bytes, workspace bytes)."""
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
     _check(lib().nvsm_stream_plan(ctypes.byref(params), int(H), int(W), int(group_frames), ctypes.byref(a),
                                   ctypes.byref(b)), "nvsm_stream_plan")
@@ -299,22 +297,17 @@ def _nbytes(t):
     return t.numel() * t.element_size()
 
 
-def nvsm_stream_begin(ctx, params, H, W, state, stream=None):
-    _check(lib().nvsm_stream_begin(ctx, ctypes.byref(params), int(H), int(W), _ptr(state), _nbytes(state),
-                                   _stream(stream)), "nvsm_stream_begin", ctx)
-
-
-def nvsm_stream_add(ctx, params, frames, total_frames, state, group_ws, stream=None, row_pitch=None):
+def nvsm_stream_add(ctx, params, frames, frames_before, total_frames, state, ws, stream=None, row_pitch=None):
     G, H, W = frames.shape
     pitch = frames.stride(1) if row_pitch is None else row_pitch
     _check(lib().nvsm_stream_add(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), G, H, W, pitch,
-                                 int(total_frames), _ptr(state), _nbytes(state), _ptr(group_ws), _nbytes(group_ws),
-                                 _stream(stream)), "nvsm_stream_add", ctx)
+                                 int(frames_before), int(total_frames), _ptr(state), _nbytes(state), _ptr(ws),
+                                 _nbytes(ws), _stream(stream)), "nvsm_stream_add", ctx)
 
 
-def nvsm_stream_finish(ctx, params, H, W, stf, out, state, stream=None):
-    _check(lib().nvsm_stream_finish(ctx, ctypes.byref(params), int(H), int(W), _ptr(stf), _ptr(out), _ptr(state),
-                                    _nbytes(state), _stream(stream)), "nvsm_stream_finish", ctx)
+def nvsm_stream_finish(ctx, params, H, W, stf, out, ws, stream=None):
+    _check(lib().nvsm_stream_finish(ctx, ctypes.byref(params), int(H), int(W), _ptr(stf), _ptr(out), _ptr(ws),
+                                    _nbytes(ws), _stream(stream)), "nvsm_stream_finish", ctx)
 
 
 def nvsm_profile_enable(ctx, enable=True):

@@ -158,10 +158,10 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         for (int q = 0; q < NQ; ++q) bv[q] = as_f2(__builtin_amdgcn_raw_buffer_load_b64(rsrc, sol[q], f * FB, 0));
     };
 
-    // output index of each slot for this lane, and the patch's rows of the
-    // bispectrum and compensation arrays
-    const size_t oi0 = (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
-    const size_t po = (size_t)patch * s_count;
+    // running sums of earlier frame groups, in this launch's lane order:
+    // slot k of lane l of wave j of item (patch, g) at
+    // (((patch * n_items + g) * 4 + j) * K + k) * 64 + l
+    const size_t ls0 = (((size_t)patch * acc.n_items + g) * BS_WAVES + wave) * K * 64 + lane;
     float2 t[NS], s[NS], c[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -169,15 +169,11 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         s[k] = make_float2(0.f, 0.f);
         c[k] = make_float2(0.f, 0.f);
     }
-    if (acc.mode != 0) {
-        // continue the running (sum, compensation) of earlier frame groups
+    if (acc.mode != 0 && !acc.first) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            const int o = out_idx[oi0 + k * 64];
-            if (o >= 0) {
-                s[k] = bispec[po + o];
-                c[k] = acc.comp[po + o];
-            }
+            s[k] = acc.sum[ls0 + k * 64];
+            c[k] = acc.comp[ls0 + k * 64];
         }
     }
 
@@ -228,21 +224,17 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     }
     wait_vm<0>();
 
-    const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
-    float2 *bo = bispec + (size_t)patch * s_count;
     if (acc.mode == 1) {
         // keep the running (sum, compensation) for the next frame group
-        float2 *co = acc.comp + (size_t)patch * s_count;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            const int o = oi[k * 64];
-            if (o >= 0) {
-                bo[o] = s[k];
-                co[o] = c[k];
-            }
+            acc.sum[ls0 + k * 64] = s[k];
+            acc.comp[ls0 + k * 64] = c[k];
         }
         return;
     }
+    const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
+    float2 *bo = bispec + (size_t)patch * s_count;
     const float inv = acc.mode == 2 ? acc.inv_total : invF;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {

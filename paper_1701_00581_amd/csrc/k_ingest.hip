@@ -231,15 +231,16 @@ __global__ __launch_bounds__(NT) void k_acc_finalize(const BurstTable bt, int ch
 }
 
 // Streaming form of k_acc_finalize for one burst: adds the frame groups of
-// this launch to running compensated sums kept between launches,
-// sc = (sum, compensation) per value: power rows 0..N/2, the two mean
-// spectrum values and the mean level.  last != 0: then writes the means
-// over all frames, (sum - comp) * inv_total, as k_acc_finalize does.
+// this launch to running compensated sums kept between launches (from zero
+// when first), sc = (sum, compensation) per value: power rows 0..N/2, the
+// two mean spectrum values and the mean level.  last != 0: then writes the
+// means over all frames, (sum - comp) * inv_total, as k_acc_finalize does.
 template <int N>
 __global__ __launch_bounds__(NT) void k_acc_stream(int nchunks, const float *__restrict__ ppart,
                                                    const float *__restrict__ mpart,
                                                    const float *__restrict__ mupart, float2 *__restrict__ psc,
-                                                   float2 *__restrict__ msc, float2 *__restrict__ musc, int last,
+                                                   float2 *__restrict__ msc, float2 *__restrict__ musc, int first,
+                                                   int last,
                                                    float inv_total, float *__restrict__ power,
                                                    float *__restrict__ mean_spec, float *__restrict__ mu) {
     constexpr int HALF = N / 2, NP = (HALF + 1) * N;
@@ -247,18 +248,18 @@ __global__ __launch_bounds__(NT) void k_acc_stream(int nchunks, const float *__r
     const float *pp = ppart + (size_t)patch * nchunks * NP;
     float2 *ps = psc + (size_t)patch * NP;
     for (int j = threadIdx.x; j < NP; j += NT) {
-        float2 v = ps[j];
+        float2 v = first ? make_float2(0.f, 0.f) : ps[j];
         for (int k = 0; k < nchunks; ++k) kahan_add(v.x, v.y, pp[(size_t)k * NP + j]);
         ps[j] = v;
     }
     if (threadIdx.x < 4) {
-        float2 v = msc[(size_t)patch * 4 + threadIdx.x];
+        float2 v = first ? make_float2(0.f, 0.f) : msc[(size_t)patch * 4 + threadIdx.x];
         for (int k = 0; k < nchunks; ++k) kahan_add(v.x, v.y, mpart[((size_t)patch * nchunks + k) * 4 + threadIdx.x]);
         msc[(size_t)patch * 4 + threadIdx.x] = v;
         if (last) mean_spec[(size_t)patch * 4 + threadIdx.x] = (v.x - v.y) * inv_total;
     }
     if (threadIdx.x == 4) {
-        float2 v = musc[patch];
+        float2 v = first ? make_float2(0.f, 0.f) : musc[patch];
         for (int k = 0; k < nchunks; ++k) kahan_add(v.x, v.y, mupart[(size_t)patch * nchunks + k]);
         musc[patch] = v;
         if (last) mu[patch] = (v.x - v.y) * inv_total;
@@ -291,7 +292,8 @@ hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
     } else {
         const int nchunks = (a.bt.b[0].F + a.chunk_frames - 1) / a.chunk_frames;
         hipLaunchKernelGGL((k_acc_stream<N>), dim3(a.bt.patches), dim3(NT), 0, st, nchunks, a.ppart, a.mpart,
-                           a.mupart, a.psc, a.msc, a.musc, a.stream_mode == 2 ? 1 : 0, a.inv_total, a.power,
+                           a.mupart, a.psc, a.msc, a.musc, a.stream_first, a.stream_mode == 2 ? 1 : 0, a.inv_total,
+                           a.power,
                            a.mean_spec, a.mu);
     }
     return hipGetLastError();

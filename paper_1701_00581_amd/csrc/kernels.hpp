@@ -44,8 +44,9 @@ struct IngestArgs {
     float *ppart = nullptr, *mpart = nullptr, *mupart = nullptr;   // per ingest workgroup
     float *power = nullptr, *mean_spec = nullptr, *mu = nullptr;   // per patch
     // streaming (one burst): 0 all frames at once; 1 add this frame group
-    // to the running sums; 2 add the last group and write the means
-    int stream_mode = 0;
+    // to the running sums (from zero when stream_first); 2 add the last
+    // group and write the means
+    int stream_mode = 0, stream_first = 0;
     float2 *psc = nullptr, *msc = nullptr, *musc = nullptr;        // running (sum, compensation)
     float inv_total = 0.f;
 };
@@ -55,12 +56,13 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 
 // Accumulator handling of the bispectrum launch.  mode 0: the launch covers
 // all frames and writes the mean.  mode 1: the launch adds a group of
-// frames to a running compensated sum kept between launches (sum in the
-// bispectrum array, compensation in comp).  mode 2: as 1 for the last group,
-// then writes the mean, (sum - comp) * inv_total, to the bispectrum array.
+// frames to running (sum, compensation) pairs kept between launches in the
+// kernel's lane order (coalesced), starting from zero when first.  mode 2:
+// as 1 for the last group, then writes the mean, (sum - comp) * inv_total,
+// to the bispectrum array in S order.
 struct AccState {
-    float2 *comp = nullptr;               // [P][|S|]
-    int mode = 0;
+    float2 *sum = nullptr, *comp = nullptr;   // [P * n_items * 4 * slots * 64]
+    int mode = 0, first = 0, n_items = 0;
     float inv_total = 0.f;
 };
 

@@ -160,51 +160,62 @@ size_t ws_rec(const Sizes &z) {
     return z.power + z.mean + z.mu + z.bispec + z.amp + z.phasor + z.patches + ws_acc(z);
 }
 
-// Streaming state of one burst: running (sum, compensation) of the
-// bispectrum and of the power / mean sums, then the solve and synthesis
-// buffers.  The bispectrum sum array receives the mean at the last group.
+// Streaming buffers.  The state of one burst holds the running
+// (sum, compensation) pairs: the bispectrum terms in the kernel's lane order
+// (every computed slot of every item), then the power rows, mean spectrum
+// and mean level.  The workspace of one stream holds the final means (the
+// bispectrum in S order first), the solve and synthesis buffers, then the
+// scratch for one group of frames.
 struct StreamSizes {
-    size_t bis_s = 0, bis_c = 0, psc = 0, msc = 0, musc = 0;   // zeroed by nvsm_stream_begin
-    size_t power = 0, mean = 0, mu = 0, amp = 0, phasor = 0, patches = 0;
-    size_t acc() const { return bis_s + bis_c + psc + msc + musc; }
-    size_t total() const { return acc() + power + mean + mu + amp + phasor + patches; }
+    size_t acc_s = 0, acc_c = 0, psc = 0, msc = 0, musc = 0;            // state
+    size_t bis = 0, power = 0, mean = 0, mu = 0, amp = 0, phasor = 0, patches = 0, group = 0;   // workspace
+    size_t state() const { return acc_s + acc_c + psc + msc + musc; }
+    size_t ws() const { return bis + power + mean + mu + amp + phasor + patches + group; }
 };
 
-void stream_sizes(int N, int64_t P, int64_t nW, int64_t S, StreamSizes *z) {
+void stream_sizes(int N, int64_t P, int64_t nW, int64_t S, int64_t lane_terms, size_t group, StreamSizes *z) {
     const int64_t NP = (N / 2 + 1) * N;
-    z->bis_s = align_up((size_t)P * S * 8);
-    z->bis_c = align_up((size_t)P * S * 8);
+    z->acc_s = align_up((size_t)P * lane_terms * 8);
+    z->acc_c = align_up((size_t)P * lane_terms * 8);
     z->psc = align_up((size_t)P * NP * 8);
     z->msc = align_up((size_t)P * 4 * 8);
     z->musc = align_up((size_t)P * 8);
+    z->bis = align_up((size_t)P * S * 8);
     z->power = align_up((size_t)P * N * N * 4);
     z->mean = align_up((size_t)P * 4 * 4);
     z->mu = align_up((size_t)P * 4);
     z->amp = align_up((size_t)P * nW * 8);
     z->phasor = align_up((size_t)P * nW * 16);
     z->patches = align_up((size_t)P * N * N * 4);
+    z->group = group;
 }
 
 struct StreamView {
-    float2 *bis_s, *bis_c, *psc, *msc, *musc;
+    float2 *acc_s, *acc_c, *psc, *msc, *musc;            // state
+    float2 *bis;                                          // workspace
     float *power, *mean, *mu;
     double *amp, *phasor;
     float *patches;
+    char *group;
 };
 
-StreamView stream_view(char *w, const StreamSizes &z) {
-    StreamView v;
-    v.bis_s = (float2 *)w; w += z.bis_s;
-    v.bis_c = (float2 *)w; w += z.bis_c;
-    v.psc = (float2 *)w; w += z.psc;
-    v.msc = (float2 *)w; w += z.msc;
-    v.musc = (float2 *)w; w += z.musc;
-    v.power = (float *)w; w += z.power;
-    v.mean = (float *)w; w += z.mean;
-    v.mu = (float *)w; w += z.mu;
-    v.amp = (double *)w; w += z.amp;
-    v.phasor = (double *)w; w += z.phasor;
-    v.patches = (float *)w;
+StreamView stream_view(char *st, char *ws, const StreamSizes &z) {
+    StreamView v{};
+    if (st) {
+        v.acc_s = (float2 *)st; st += z.acc_s;
+        v.acc_c = (float2 *)st; st += z.acc_c;
+        v.psc = (float2 *)st; st += z.psc;
+        v.msc = (float2 *)st; st += z.msc;
+        v.musc = (float2 *)st;
+    }
+    v.bis = (float2 *)ws; ws += z.bis;
+    v.power = (float *)ws; ws += z.power;
+    v.mean = (float *)ws; ws += z.mean;
+    v.mu = (float *)ws; ws += z.mu;
+    v.amp = (double *)ws; ws += z.amp;
+    v.phasor = (double *)ws; ws += z.phasor;
+    v.patches = (float *)ws; ws += z.patches;
+    v.group = ws;
     return v;
 }
 
@@ -803,91 +814,89 @@ nvsm_status nvsm_set_launch(nvsm_context *ctx, const nvsm_params *p, int32_t slo
 }
 
 nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t group_frames,
-                             size_t *state_bytes, size_t *group_ws_bytes) {
+                             size_t *state_bytes, size_t *ws_bytes) {
     std::string msg;
-    if (!state_bytes || !group_ws_bytes) return NVSM_ERR_INVALID_ARG;
+    if (!state_bytes || !ws_bytes) return NVSM_ERR_INVALID_ARG;
     nvsm_status s = check_params(p, &msg);
     if (s != NVSM_OK) return s;
     if ((s = check_shape(p, H, W, group_frames, &msg)) != NVSM_OK) return s;
-    int64_t nW, S;
-    int shells;
+    HostPlan h;
     try {
-        count_sets(p, &nW, &S, &shells);
+        if (!build_plan(p->patch, p->u_cut, p->v_radius, 16, &h, &msg)) return NVSM_ERR_INVALID_ARG;
     } catch (const std::bad_alloc &) {
         return NVSM_ERR_OOM;
     }
+    // sized for the larger slot count, so a tuned launch also fits
+    HostPlan h24;
+    try {
+        if (!build_plan(p->patch, p->u_cut, p->v_radius, 24, &h24, &msg)) return NVSM_ERR_INVALID_ARG;
+    } catch (const std::bad_alloc &) {
+        return NVSM_ERR_OOM;
+    }
+    const int64_t lane_terms = std::max((int64_t)h.n_items * BS_WAVES * 16 * 64,
+                                        (int64_t)h24.n_items * BS_WAVES * 24 * 64);
     BurstIn bi;
     bi.F = group_frames; bi.H = H; bi.W = W; bi.pitch = W;
     BurstTable bt;
     int64_t rec;
     make_table(p, &bi, 1, &bt, &rec);
     Sizes z;
-    sizes_for(p->patch, bt, rec, nW, S, &z);
+    sizes_for(p->patch, bt, rec, (int64_t)h.W.size() / 2, h.s_count, &z);
     StreamSizes ss;
-    stream_sizes(p->patch, bt.patches, nW, S, &ss);
-    *state_bytes = ss.total();
-    *group_ws_bytes = ws_acc(z);
+    stream_sizes(p->patch, bt.patches, (int64_t)h.W.size() / 2, h.s_count, lane_terms, ws_acc(z), &ss);
+    *state_bytes = ss.state();
+    *ws_bytes = ss.ws();
     return NVSM_OK;
 }
 
-static nvsm_status stream_prep(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, void *state,
-                               size_t state_bytes, DevicePlan **dp, BurstTable *bt, StreamSizes *ss) {
+static nvsm_status stream_prep(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, int32_t G,
+                               DevicePlan **dp, BurstTable *bt, Sizes *z, StreamSizes *ss) {
     std::string msg;
     nvsm_status s = check_params(p, &msg);
     if (s != NVSM_OK) return fail(ctx, s, msg);
-    if ((s = check_shape(p, H, W, 1, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    if ((s = check_shape(p, H, W, G, &msg)) != NVSM_OK) return fail(ctx, s, msg);
     if ((s = get_plan(ctx, p, dp)) != NVSM_OK) return s;
     BurstIn bi;
-    bi.F = 1; bi.H = H; bi.W = W; bi.pitch = W;
+    bi.F = G; bi.H = H; bi.W = W; bi.pitch = W;
     int64_t rec;
     make_table(p, &bi, 1, bt, &rec);
-    stream_sizes(p->patch, bt->patches, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, ss);
-    if (!state || state_bytes < ss->total()) return fail(ctx, NVSM_ERR_WORKSPACE, "stream state too small");
-    return NVSM_OK;
-}
-
-nvsm_status nvsm_stream_begin(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, void *state,
-                              size_t state_bytes, void *stream) {
-    if (!ctx) return NVSM_ERR_INVALID_ARG;
-    DevicePlan *dp;
-    BurstTable bt;
-    StreamSizes ss;
-    nvsm_status s = stream_prep(ctx, p, H, W, state, state_bytes, &dp, &bt, &ss);
-    if (s != NVSM_OK) return s;
-    hipError_t e = launch_zero(state, ss.acc(), (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "stream begin");
+    sizes_for(p->patch, *bt, rec, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, z);
+    const int64_t lane_terms = (int64_t)(*dp)->h.n_items * BS_WAVES * (*dp)->h.slots * 64;
+    stream_sizes(p->patch, bt->patches, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, lane_terms, ws_acc(*z),
+                 ss);
     return NVSM_OK;
 }
 
 nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
-                            int32_t G, int32_t H, int32_t W, int64_t row_pitch, int32_t total_frames,
-                            void *state, size_t state_bytes, void *group_ws, size_t group_ws_bytes,
+                            int32_t G, int32_t H, int32_t W, int64_t row_pitch, int32_t frames_before,
+                            int32_t total_frames, void *state, size_t state_bytes, void *ws, size_t ws_bytes,
                             void *stream) {
     if (!ctx) return NVSM_ERR_INVALID_ARG;
     if (!frames) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
     if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
-    if (total_frames < 0) return fail(ctx, NVSM_ERR_INVALID_ARG, "total_frames < 0");
+    if (frames_before < 0) return fail(ctx, NVSM_ERR_INVALID_ARG, "frames_before < 0");
+    if (total_frames != 0 && total_frames != frames_before + G)
+        return fail(ctx, NVSM_ERR_INVALID_ARG, "total_frames must be 0 or frames_before + G");
     DevicePlan *dp;
-    BurstTable bt1;
+    BurstTable bt;
+    Sizes z;
     StreamSizes ss;
-    nvsm_status s = stream_prep(ctx, p, H, W, state, state_bytes, &dp, &bt1, &ss);
+    nvsm_status s = stream_prep(ctx, p, H, W, G, &dp, &bt, &z, &ss);
     if (s != NVSM_OK) return s;
     BurstIn bi;
     bi.frames = frames; bi.F = G; bi.H = H; bi.W = W; bi.pitch = row_pitch;
     std::string msg;
     if ((s = check_burst(p, bi, &msg)) != NVSM_OK) return fail(ctx, s, msg);
-    if (total_frames != 0 && total_frames < G) return fail(ctx, NVSM_ERR_INVALID_ARG, "total_frames < G");
-    BurstTable bt;
-    int64_t rec;
-    make_table(p, &bi, 1, &bt, &rec);
-    Sizes z;
-    sizes_for(p->patch, bt, rec, (int64_t)(dp->h.W.size() / 2), dp->h.s_count, &z);
-    if (!group_ws || group_ws_bytes < ws_acc(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "group workspace too small");
-    StreamView v = stream_view((char *)state, ss);
+    bt.b[0].frames = frames;
+    bt.b[0].pitch = row_pitch;
+    if (!state || state_bytes < ss.state()) return fail(ctx, NVSM_ERR_WORKSPACE, "stream state too small");
+    if (!ws || ws_bytes < ss.ws()) return fail(ctx, NVSM_ERR_WORKSPACE, "stream workspace too small");
+    StreamView v = stream_view((char *)state, (char *)ws, ss);
     const int mode = total_frames ? 2 : 1;
+    const int first = frames_before == 0;
     const float inv_total = total_frames ? 1.0f / (float)total_frames : 0.f;
     hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)group_ws;
+    char *gw = v.group;
     IngestArgs a;
     a.N = p->patch;
     a.f32 = dtype == NVSM_F32;
@@ -897,12 +906,13 @@ nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void 
     a.vec = vec_ok(p, bt, a.f32 ? 4 : 2);
     a.inv_wsum = (float)(1.0 / (p->window ? dp->h.hann_sum2 : (double)p->patch * p->patch));
     a.twiddle = dp->twiddle; a.hann = dp->hann;
-    a.spectra = (float2 *)ws;
-    a.ppart = (float *)(ws + z.spectra);
-    a.mpart = (float *)(ws + z.spectra + z.ppart);
-    a.mupart = (float *)(ws + z.spectra + z.ppart + z.mpart);
+    a.spectra = (float2 *)gw;
+    a.ppart = (float *)(gw + z.spectra);
+    a.mpart = (float *)(gw + z.spectra + z.ppart);
+    a.mupart = (float *)(gw + z.spectra + z.ppart + z.mpart);
     a.power = v.power; a.mean_spec = v.mean; a.mu = v.mu;
-    a.stream_mode = mode; a.psc = v.psc; a.msc = v.msc; a.musc = v.musc; a.inv_total = inv_total;
+    a.stream_mode = mode; a.stream_first = first;
+    a.psc = v.psc; a.msc = v.msc; a.musc = v.musc; a.inv_total = inv_total;
     hipError_t e;
     {
         StageTimer t(ctx, ST_INGEST, st);
@@ -913,9 +923,10 @@ nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void 
     b.N = p->patch; b.bt = bt; b.spectra = a.spectra;
     b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy;
     b.slot_v = dp->slot; b.out_idx = dp->out_idx;
-    b.bispec = v.bis_s; b.s_count = z.S;
+    b.bispec = v.bis; b.s_count = z.S;
     b.form = choice_of(ctx, p).second; b.queue = ctx->queue;
-    b.acc.comp = v.bis_c; b.acc.mode = mode; b.acc.inv_total = inv_total;
+    b.acc.sum = v.acc_s; b.acc.comp = v.acc_c; b.acc.mode = mode; b.acc.first = first;
+    b.acc.n_items = dp->h.n_items; b.acc.inv_total = inv_total;
     {
         StageTimer t(ctx, ST_BISPEC, st);
         e = launch_bispec(b, st);
@@ -925,19 +936,22 @@ nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void 
 }
 
 nvsm_status nvsm_stream_finish(nvsm_context *ctx, const nvsm_params *p, int32_t H, int32_t W, const double *stf,
-                               float *out, void *state, size_t state_bytes, void *stream) {
+                               float *out, void *ws, size_t ws_bytes, void *stream) {
     if (!ctx) return NVSM_ERR_INVALID_ARG;
     if (!stf || !out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
     DevicePlan *dp;
     BurstTable bt;
+    Sizes z;
     StreamSizes ss;
-    nvsm_status s = stream_prep(ctx, p, H, W, state, state_bytes, &dp, &bt, &ss);
+    nvsm_status s = stream_prep(ctx, p, H, W, 1, &dp, &bt, &z, &ss);
     if (s != NVSM_OK) return s;
+    const size_t final_bytes = ss.ws() - ss.group;
+    if (!ws || ws_bytes < final_bytes) return fail(ctx, NVSM_ERR_WORKSPACE, "stream workspace too small");
     bt.b[0].stf = stf;
     bt.b[0].out = out;
-    StreamView v = stream_view((char *)state, ss);
+    StreamView v = stream_view(nullptr, (char *)ws, ss);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = run_solve(ctx, dp, p, bt, v.power, v.mean, (const float *)v.bis_s, v.amp, v.phasor, st);
+    hipError_t e = run_solve(ctx, dp, p, bt, v.power, v.mean, (const float *)v.bis, v.amp, v.phasor, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "stream solve");
     e = run_synth(ctx, dp, p, bt, v.amp, v.phasor, v.mu, v.patches, true, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "stream synthesize");

@@ -2,19 +2,25 @@
 and are reconstructed as they complete (continuous batching).
 
 Each channel has its own HIP stream, a device staging buffer for one group
-of frames and a group workspace.  Per-burst device memory comes from a pool
+of frames and a workspace (group scratch and final buffers).  Per-burst device memory comes from a pool
 of slots sized to an HBM budget; a burst is admitted when its first frame
 arrives and a slot of its channel's shape is free, otherwise its frames
 wait on the host until one frees (admission by HBM footprint).  Work of
 different channels overlaps on the device through their streams.
 
-Two policies, the same images for a given burst however the bursts mix
-(every result depends only on its own frames, through the same kernels):
+Two policies.  Every result depends only on its own frames and on where
+its running sums were folded, never on the other bursts: with fixed groups
+(max_group == group) a burst gives the same image, bit for bit, alone or in
+any mix; adaptive groups change only the fold points, within the parity
+tolerances.
 
 * ``stream`` -- the burst's running sums live in its slot
-  (``nvsm_stream_*``): every ``group`` arriving frames are ingested and
-  added at once, so only the last group, the phase solve and the synthesis
-  remain after the last frame.
+  (``nvsm_stream_*``): arriving frames are ingested and added in groups, so
+  only the last group, the phase solve and the synthesis remain after the
+  last frame.  A group is launched once ``group`` frames wait and the
+  channel's previous group has finished on the device, or once
+  ``max_group`` frames wait: an idle GPU gets small groups (low latency), a
+  busy one larger groups (fewer passes over the running sums).
 * ``plain`` -- frames are kept on the device and the burst is reconstructed
   with one ``nvsm_reconstruct`` after its last frame.
 
@@ -49,6 +55,7 @@ class Done:
     image: object             # device float32 [H][W] (owned by the caller after poll)
     t_last_frame: float       # host clock when the last frame was submitted
     t_done: float             # host clock when the image was seen ready
+    groups: int = 1           # device passes over the burst's running sums
     @property
     def latency_ms(self):
         return (self.t_done - self.t_last_frame) * 1e3
@@ -64,17 +71,20 @@ class _Burst:
         self.t_last = None
         self.event = None
         self.image = None
+        self.groups = 0            # device passes over the running sums
 
 
 class Server:
     """policy: "stream" or "plain"; budget: bytes of HBM for burst slots;
     max_frames: the largest burst (plain policy keeps every frame)."""
 
-    def __init__(self, channels, policy="stream", group=10, budget=64 << 30, max_frames=150, device=0):
+    def __init__(self, channels, policy="stream", group=10, budget=64 << 30, max_frames=150, device=0,
+                 max_group=None):
         import torch
         self.torch = torch
         self.policy = policy
         self.group = int(group)
+        self.max_group = int(max_group or group)
         self.dev = torch.device("cuda", device)
         self.ctx = _lib.nvsm_create(device)
         self.ch = {}
@@ -83,16 +93,16 @@ class Server:
             _lib.nvsm_prepare(self.ctx, c.params)
             st = torch.cuda.Stream(device=self.dev)           # default priority
             if policy == "stream":
-                slot_b, gws_b = _lib.nvsm_stream_plan(c.params, c.H, c.W, self.group)
+                slot_b, gws_b = _lib.nvsm_stream_plan(c.params, c.H, c.W, self.max_group)
                 gws = torch.empty(gws_b, dtype=torch.uint8, device=self.dev)
-                stage = torch.empty((self.group, c.H, c.W), dtype=torch.int16, device=self.dev)
+                stage = torch.empty((self.max_group, c.H, c.W), dtype=torch.int16, device=self.dev)
             else:
                 info = _lib.nvsm_plan(c.params, c.H, c.W, max_frames)
                 slot_b = max_frames * c.H * c.W * 2
                 gws = torch.empty(info.ws_reconstruct, dtype=torch.uint8, device=self.dev)
                 stage = None
             self.ch[c.name] = dict(spec=c, stream=st, gws=gws, stage=stage, slot_bytes=slot_b, free=[],
-                                   queue=collections.deque(), active={}, order=collections.deque())
+                                   active={}, order=collections.deque(), add_ev=None)
             need.append((c.name, slot_b))
         # slots: one per channel first, then round robin while the budget lasts
         used = 0
@@ -131,9 +141,6 @@ class Server:
         if b.slot is None and c["free"] and c["order"] and c["order"][0] is b:
             b.slot = c["free"].pop()
             c["order"].popleft()
-            if self.policy == "stream":
-                with self.torch.cuda.stream(c["stream"]):
-                    _lib.nvsm_stream_begin(self.ctx, c["spec"].params, c["spec"].H, c["spec"].W, b.slot)
         return b.slot is not None
 
     def _advance(self, c):
@@ -144,18 +151,26 @@ class Server:
                 break                                  # bursts are admitted in arrival order
             with torch.cuda.stream(c["stream"]):
                 if self.policy == "stream":
-                    while len(b.pending) >= self.group or (b.total and b.pending):
-                        g = min(self.group, len(b.pending))
+                    while b.pending:
+                        idle = c["add_ev"] is None or c["add_ev"].query()
+                        if not (b.total or len(b.pending) >= self.max_group or
+                                (len(b.pending) >= self.group and idle)):
+                            break
+                        g = min(self.max_group, len(b.pending))
                         for i in range(g):
                             c["stage"][i].copy_(torch.from_numpy(b.pending[i].view(np.int16)), non_blocking=True)
                         del b.pending[:g]
                         b.count += g
                         final = b.total if (b.total and not b.pending) else 0
-                        _lib.nvsm_stream_add(self.ctx, spec.params, c["stage"][:g], final, b.slot, c["gws"])
+                        _lib.nvsm_stream_add(self.ctx, spec.params, c["stage"][:g], b.count - g, final, b.slot,
+                                             c["gws"])
+                        c["add_ev"] = torch.cuda.Event()
+                        c["add_ev"].record(c["stream"])
+                        b.groups += 1
                         if final:
                             b.image = torch.empty((spec.H, spec.W), dtype=torch.float32, device=self.dev)
                             _lib.nvsm_stream_finish(self.ctx, spec.params, spec.H, spec.W, spec.stf, b.image,
-                                                    b.slot)
+                                                    c["gws"])
                         # the staging buffer is reused by the next group:
                         # the copies above are ordered on this stream
                 else:
@@ -186,7 +201,7 @@ class Server:
                 c = self.ch[b.ch]
                 c["free"].append(b.slot)
                 b.slot = None
-                out.append(Done(b.ch, b.bid, b.total, b.image, b.t_last, now))
+                out.append(Done(b.ch, b.bid, b.total, b.image, b.t_last, now, max(1, b.groups)))
             else:
                 keep.append(b)
         self.inflight = keep

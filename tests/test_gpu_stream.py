@@ -53,20 +53,19 @@ def setup(torch_cuda):
 
 def _stream(nv, torch, s, groups):
     p, d, info = s["p"], s["d"], s["info"]
-    state_b, gws_b = nv.nvsm_stream_plan(p, H, W, max(groups))
+    state_b, ws_b = nv.nvsm_stream_plan(p, H, W, max(groups))
     state = torch.empty(state_b, dtype=torch.uint8, device="cuda")
-    state.fill_(0xFF)                      # begin must clear what it needs
-    gws = torch.empty(gws_b, dtype=torch.uint8, device="cuda")
-    nv.nvsm_stream_begin(s["ctx"], p, H, W, state)
+    state.fill_(0xFF)                      # the first group must not read it
+    ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
     f0 = 0
     for i, g in enumerate(groups):
         last = i == len(groups) - 1
-        nv.nvsm_stream_add(s["ctx"], p, d[f0:f0 + g], F if last else 0, state, gws)
+        nv.nvsm_stream_add(s["ctx"], p, d[f0:f0 + g], f0, F if last else 0, state, ws)
         f0 += g
     img = torch.full((H, W), float("nan"), device="cuda")
-    nv.nvsm_stream_finish(s["ctx"], p, H, W, s["stf"], img, state)
+    nv.nvsm_stream_finish(s["ctx"], p, H, W, s["stf"], img, ws)
     torch.cuda.synchronize()
-    bis = state[: info.patches * info.s_count * 8].view(torch.float32).view(info.patches, info.s_count, 2)
+    bis = ws[: info.patches * info.s_count * 8].view(torch.float32).view(info.patches, info.s_count, 2)
     return img, bis
 
 
@@ -114,16 +113,16 @@ def test_stream_errors(torch_cuda, setup):
     import paper_1701_00581_amd as nv
     torch = torch_cuda
     p = setup["p"]
-    state_b, gws_b = nv.nvsm_stream_plan(p, H, W, 5)
-    state = torch.empty(state_b - 256, dtype=torch.uint8, device="cuda")
-    with pytest.raises(nv.NvsmError) as e:
-        nv.nvsm_stream_begin(setup["ctx"], p, H, W, state)
-    assert e.value.status == -3
+    state_b, ws_b = nv.nvsm_stream_plan(p, H, W, 5)
     state = torch.empty(state_b, dtype=torch.uint8, device="cuda")
-    small = torch.empty(gws_b - 256, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
+    small = torch.empty(state_b // 4, dtype=torch.uint8, device="cuda")
     with pytest.raises(nv.NvsmError) as e:
-        nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 0, state, small)
+        nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 0, 0, small, ws)
     assert e.value.status == -3
-    with pytest.raises(nv.NvsmError):
-        nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 3, state,
-                           torch.empty(gws_b, dtype=torch.uint8, device="cuda"))
+    small = torch.empty(ws_b - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(nv.NvsmError) as e:
+        nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 0, 0, state, small)
+    assert e.value.status == -3
+    with pytest.raises(nv.NvsmError):               # total must be frames_before + G
+        nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 0, 3, state, ws)
