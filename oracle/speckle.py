@@ -19,8 +19,8 @@ import numpy as np
 __all__ = [
     "tiling", "hann", "window2d", "patch_spectra", "frequency_half_disk",
     "bispectrum_set", "accumulate_patch", "bispectrum", "noise_bias",
-    "amplitude", "phase_recursion", "diffraction_filter", "synthesize_patch",
-    "mosaic", "reconstruct", "Params",
+    "amplitude", "phase_recursion", "phase_least_squares", "diffraction_filter",
+    "synthesize_patch", "mosaic", "reconstruct", "Params",
 ]
 
 
@@ -28,7 +28,8 @@ class Params:
     """Reconstruction parameters (defaults follow the patch size N)."""
 
     def __init__(self, patch=128, stride=None, u_cut=None, v_radius=10,
-                 window=1, noise_bias=0, filter=0, stf_floor=1e-6):
+                 window=1, noise_bias=0, filter=0, stf_floor=1e-6,
+                 phase_method=0, lsq_iters=10):
         self.patch = int(patch)
         self.stride = int(patch // 2 if stride is None else stride)
         self.u_cut = int(patch // 2 - 1 if u_cut is None else u_cut)
@@ -37,6 +38,8 @@ class Params:
         self.noise_bias = int(noise_bias)
         self.filter = int(filter)
         self.stf_floor = float(stf_floor)
+        self.phase_method = int(phase_method)   # 0 recursion, 1 + least squares
+        self.lsq_iters = int(lsq_iters)
 
 
 # ---------------------------------------------------------------------------
@@ -258,6 +261,66 @@ def phase_recursion(B, M10, M01, Wset, S, woff, N):
     return out
 
 
+def phase_least_squares(B, e0, Wset, S, woff, iters):
+    """Least-squares refinement of the phasors (an alternative to the
+    recursion named in the paper's description of the phase step).
+
+    Every sample is a closure phi(w - v) + phi(v) - phi(w) = arg B(w, v);
+    the refinement raises the |B|-weighted closure agreement
+        J(e) = sum_S Re[ e(w - v) e(v) conj(e(w)) conj(B(w, v)) ]
+    over unit phasors with e(-u) = conj(e(u)), keeping the two seeds
+    (1,0) and (0,1) (they fix the translation).  For fixed other phasors J is
+    largest at e(u) = g(u) / |g(u)|, where g(u) sums, over every sample in
+    which u appears:
+        as w:        e(w - v) e(v) conj(B)
+        as w - v:    conj(e(v)) e(w) B
+        as v:        conj(e(w - v)) e(w) B
+    (conjugated where the sample holds -u).  One step moves every phasor
+    halfway to that target, all at once from the previous phasors:
+        e'(u) = unit(unit(g(u)) + e(u))   (e(u) kept where g(u) = 0).
+    ``iters`` steps from ``e0`` (normally the recursion's phasors).
+    Returns complex128 [|W|].
+    """
+    Wset = np.asarray(Wset)
+    S = np.asarray(S)
+    pos = {(int(x), int(y)): i for i, (x, y) in enumerate(Wset)}
+
+    def index_of(x, y):
+        """W index of +-(x, y) and whether the sample holds the conjugate."""
+        j = np.empty(len(x), dtype=np.int64)
+        cj = np.empty(len(x), dtype=bool)
+        for k, (a, b) in enumerate(zip(x.tolist(), y.tolist())):
+            if (a, b) in pos:
+                j[k], cj[k] = pos[(a, b)], False
+            else:
+                j[k], cj[k] = pos[(-a, -b)], True
+        return j, cj
+
+    wx, wy, vx, vy = S[:, 0], S[:, 1], S[:, 2], S[:, 3]
+    iw = np.array([pos[(int(a), int(b))] for a, b in zip(wx, wy)], dtype=np.int64)
+    ia, ca = index_of(wx - vx, wy - vy)
+    ib, cb = index_of(vx, vy)
+    seeds = [pos[(1, 0)], pos[(0, 1)]]
+    e = np.array(e0, dtype=np.complex128)
+    for _ in range(iters):
+        ea = np.where(ca, np.conj(e[ia]), e[ia])
+        eb = np.where(cb, np.conj(e[ib]), e[ib])
+        ec = e[iw]
+        g = np.zeros(len(Wset), dtype=np.complex128)
+        np.add.at(g, iw, ea * eb * np.conj(B))
+        t = np.conj(eb) * ec * B
+        np.add.at(g, ia, np.where(ca, np.conj(t), t))
+        t = np.conj(ea) * ec * B
+        np.add.at(g, ib, np.where(cb, np.conj(t), t))
+        new = e.copy()
+        nz = np.abs(g) > 0
+        new[nz] = g[nz] / np.abs(g[nz]) + e[nz]
+        new[nz] = new[nz] / np.abs(new[nz])
+        new[seeds] = e[seeds]
+        e = new
+    return e
+
+
 # ---------------------------------------------------------------------------
 # Inverse transform and mosaic (Section 3.2).
 # ---------------------------------------------------------------------------
@@ -328,6 +391,8 @@ def reconstruct(frames, params, stf, patch_list=None, keep=False):
         nb = noise_bias(acc["P"]) if params.noise_bias else 0.0
         amp = amplitude(acc["P"], stf, Wset, nb, params.stf_floor)
         ph = phase_recursion(acc["B"], acc["M10"], acc["M01"], Wset, S, woff, N)
+        if params.phase_method == 1:
+            ph = phase_least_squares(acc["B"], ph, Wset, S, woff, params.lsq_iters)
         r = synthesize_patch(amp, ph, Wset, N, acc["mu"], params.window, filt)
         res[(i, j)] = dict(acc, amp=amp, phasor=ph, patch=r, nbias=nb)
     out = dict(tiles=res, ys=ys, xs=xs, Wset=Wset, S=S, woff=woff)
