@@ -298,6 +298,9 @@ def main():
     ap.add_argument("--frames", type=int, default=None, help="override the frame count")
     ap.add_argument("--stf-screens", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phase-method", type=int, default=0, choices=(0, 1),
+                    help="0: the recursion; 1: the recursion followed by least-squares steps")
+    ap.add_argument("--lsq-iters", type=int, default=10, help="least-squares steps with --phase-method 1")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for traffic counters)")
@@ -338,7 +341,8 @@ def main():
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
         op = oracle.Params(patch=wl["patch"], v_radius=wl["v_radius"], window=wl.get("window", 1),
-                           noise_bias=wl["noise_bias"], filter=wl["filter"])
+                           noise_bias=wl["noise_bias"], filter=wl["filter"], phase_method=args.phase_method,
+                           lsq_iters=args.lsq_iters)
         cpu = cpu_baseline(frames, stf, op, len(ys) * len(xs), len(ys), len(xs), workers)
         print(f"[bench] cpu baseline {cpu['value']:.3e} bursts/s ({cpu['sample']})", file=sys.stderr, flush=True)
 
@@ -347,6 +351,8 @@ def main():
     dev = torch.device("cuda", 0)
     p = nv.default_params(wl["patch"], v_radius=wl["v_radius"], window=wl.get("window", 1),
                           noise_bias=wl["noise_bias"], filter=wl["filter"])
+    p.phase_method = args.phase_method
+    p.lsq_iters = args.lsq_iters
     s = nv.Session(p, H, W, F)
     # host -> device upload of the burst (pinned), reported beside the value
     raw = frames.view(np.int16) if frames.dtype == np.uint16 else frames
@@ -417,7 +423,8 @@ def main():
         "config": {
             "workload": f"{args.workload}: {W}x{H} x {F} {'uint16 12-bit' if frames.dtype == np.uint16 else 'float32'} "
                         f"frames, {p.patch}x{p.patch} patches at stride {p.stride} ({info.patches_x}x{info.patches_y}), "
-                        f"|v|<={p.v_radius}, u_cut {p.u_cut}, FP32 compensated accumulation, FP64 solve",
+                        f"|v|<={p.v_radius}, u_cut {p.u_cut}, FP32 compensated accumulation, FP64 solve"
+                        + (f", {p.lsq_iters} least-squares phase steps" if p.phase_method == 1 else ""),
             "frames": F, "height": H, "width": W, "patch": p.patch, "v_radius": p.v_radius,
             "patches": P, "bispectrum_samples_per_patch": S, "parallelism": "single GPU",
         },

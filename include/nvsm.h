@@ -70,10 +70,13 @@ typedef struct {
     int32_t u_cut;        /* largest |w| reconstructed, < N/2 (default N/2-1) */
     int32_t v_radius;     /* R, largest |v| in the bispectrum, 1..16, < u_cut */
     int32_t window;       /* 0 none, 1 periodic Hann taper (default 1)      */
-    int32_t phase_method; /* 0 recursive speckle-masking solve              */
+    int32_t phase_method; /* 0 recursive speckle-masking solve; 1 the same, then
+                           * lsq_iters least-squares refinement steps      */
     int32_t noise_bias;   /* 0 off, 1 subtract the mean power beyond |u| > N/2+2 */
     int32_t filter;       /* 0 none, 1 diffraction-limited OTF of the pupil  */
     double  stf_floor;    /* modulus 0 where STF < stf_floor (default 1e-6) */
+    int32_t lsq_iters;    /* refinement steps for phase_method 1, 1..10000 (default 10) */
+    int32_t reserved;     /* 0                                              */
 } nvsm_params;
 
 /* Sizes derived from parameters and a burst shape (nvsm_plan). */
@@ -100,7 +103,8 @@ const char *nvsm_status_string(nvsm_status s);
 const char *nvsm_last_error(const nvsm_context *ctx);
 
 /* Defaults for patch size N (64 or 128): stride N/2, u_cut N/2-1, R 10,
- * Hann window, recursive phase, no noise bias, no filter, floor 1e-6. */
+ * Hann window, recursive phase (10 refinement steps if phase_method is set
+ * to 1), no noise bias, no filter, floor 1e-6. */
 nvsm_status nvsm_default_params(int32_t patch, nvsm_params *out);
 
 /* Validates params against an H x W x F burst and fills *out.  Host only. */
@@ -144,6 +148,13 @@ nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p,
  *                  the unit phasors of mean_spec, and every other w takes the
  *                  phase of sum_v e(w-v) e(v) conj B(w,v) over its samples,
  *                  in increasing |w| (e(-u) = conj e(u); 1 when the sum is 0).
+ *   phase_method 1 then refines the phasors by least squares: lsq_iters
+ *                  steps, each moving every e(u) but the two seeds halfway
+ *                  (e' = unit(unit(g) + e)) to the unit of
+ *                    g(u) = sum over the samples holding u of the derivative
+ *                           of sum_S Re[e(w-v) e(v) conj e(w) conj B] by
+ *                           conj e(u),
+ *                  all from the previous step's phasors (Jacobi). 
  * Inputs: power, mean_spec, bispec as produced by nvsm_accumulate for
  * `patches` patches; stf: device double [N][N] in DFT order. */
 nvsm_status nvsm_solve(nvsm_context *ctx, const nvsm_params *p, int64_t patches,

@@ -222,6 +222,98 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
     }
 }
 
+// Least-squares refinement of the phasors of one patch per workgroup (FP64).
+// The phasor table of the patch sits in LDS; each step computes, for every
+// w but the two seeds, g(w) = the sum over the samples holding w of the
+// derivative of the closure agreement by conj e(w):
+//   w as the sample's w:   e(w - v) e(v) conj B    (samples woff[w] ..)
+//   w as the side w - v:   conj e(v) e(w') B       (side entries, w' the
+//   w as the side v:       conj e(w' - v) e(w') B   sample's w)
+// conjugated where the sample holds -w, and the new phasor
+// e'(w) = unit(unit(g) + e(w)).  All g use the previous step's table
+// (Jacobi): wave j takes w = 2 + j + 8 m (m = 0, 1, ...), its lanes split the
+// samples, a wave sum combines them, and lane m mod 64 keeps e'(w) in
+// register slot m / 64 until every wave is done; then the table is
+// rewritten between two barriers.
+constexpr int LSQ_MAXW = 6240;
+constexpr int LSQ_SLOTS = ((LSQ_MAXW - 2) / NWAVE + 63) / 64;
+
+__global__ __launch_bounds__(NT) void k_lsq(int nW, int iters, const int *__restrict__ woff,
+                                            const unsigned *__restrict__ code, const int *__restrict__ side_off,
+                                            const uint2 *__restrict__ side_ent, const float2 *__restrict__ bispec,
+                                            int64_t s_count, double2 *__restrict__ phasor) {
+    __shared__ double2 e[LSQ_MAXW];
+    const int patch = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    double2 *ph = phasor + (size_t)patch * nW;
+    const float2 *B = bispec + (size_t)patch * s_count;
+    for (int i = tid; i < nW; i += NT) e[i] = ph[i];
+    __syncthreads();
+    auto get = [&](unsigned c) __attribute__((always_inline)) {     // e of a code (index | conj << 15)
+        double2 v = e[c & 0x7fffu];
+        if (c & 0x8000u) v.y = -v.y;
+        return v;
+    };
+    for (int it = 0; it < iters; ++it) {
+        double2 res[LSQ_SLOTS];
+#pragma unroll
+        for (int j = 0; j < LSQ_SLOTS; ++j) {
+            res[j] = make_double2(1.0, 0.0);
+            for (int l = 0; l < 64; ++l) {
+                const int w = 2 + wave + NWAVE * (64 * j + l);
+                if (w >= nW) break;
+                double gx = 0.0, gy = 0.0;
+                const int t0 = woff[w], t1 = woff[w + 1];
+                for (int t = t0 + lane; t < t1; t += 64) {
+                    const unsigned cd = code[t];
+                    const double2 a = get(cd >> 16), b = get(cd & 0xffffu);
+                    const double bx = (double)B[t].x, by = (double)B[t].y;
+                    const double px = a.x * b.x - a.y * b.y, py = a.x * b.y + a.y * b.x;
+                    gx += px * bx + py * by;                   // (a b) conj(B)
+                    gy += py * bx - px * by;
+                }
+                const int k0 = side_off[w], k1 = side_off[w + 1];
+                for (int k = k0 + lane; k < k1; k += 64) {
+                    const uint2 en = side_ent[k];
+                    const unsigned t = en.x & 0x3fffffffu;
+                    const unsigned cd = code[t];
+                    // the other side of the sample: v when w is the side w - v
+                    const double2 o = get((en.x >> 30) & 1u ? (cd >> 16) : (cd & 0xffffu));
+                    const double2 c = e[en.y];
+                    const double bx = (double)B[t].x, by = (double)B[t].y;
+                    const double qx = o.x * c.x + o.y * c.y, qy = o.x * c.y - o.y * c.x;   // conj(o) c
+                    const double rx = qx * bx - qy * by, ry = qx * by + qy * bx;           // times B
+                    gx += rx;
+                    gy += (en.x >> 31) ? -ry : ry;             // conjugated when the sample holds -w
+                }
+                gx = wave_sum_d(gx);
+                gy = wave_sum_d(gy);
+                const double2 old = e[w];
+                double2 nw = old;
+                const double m = sqrt(gx * gx + gy * gy);
+                if (m > 0.0) {
+                    const double sx = gx / m + old.x, sy = gy / m + old.y;
+                    const double n = sqrt(sx * sx + sy * sy);
+                    if (n > 0.0) nw = make_double2(sx / n, sy / n);
+                }
+                if (lane == l) res[j] = nw;
+            }
+        }
+        __syncthreads();                                   // every g read the old table
+#pragma unroll
+        for (int j = 0; j < LSQ_SLOTS; ++j) {
+            const int w = 2 + wave + NWAVE * (64 * j + lane);
+            if (w < nW) {
+                e[w] = res[j];
+                if (it + 1 == iters) ph[w] = res[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int N, int TPL, int BIG>
 hipError_t launch_solve_t(const SolveArgs &a, hipStream_t st) {
     hipLaunchKernelGGL((k_solve<N, TPL, BIG>), dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.nshell, a.shell_wb,
@@ -239,8 +331,19 @@ hipError_t launch_solve_n(const SolveArgs &a, hipStream_t st) {
 
 }  // namespace
 
+hipError_t launch_lsq(const SolveArgs &a, hipStream_t st) {
+    if (a.nW > LSQ_MAXW || a.nW < 2 || a.lsq_iters < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lsq, dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.lsq_iters, a.woff, a.wcode, a.side_off,
+                       a.side_ent, a.bispec, a.s_count, a.phasor);
+    return hipGetLastError();
+}
+
 hipError_t launch_solve(const SolveArgs &a, hipStream_t st) {
     if (a.bt.patches == 0) return hipSuccess;
+    if (a.phase_method == 1) {
+        hipError_t e = launch_solve(SolveArgs(a, 0), st);
+        return e != hipSuccess ? e : launch_lsq(a, st);
+    }
     if (a.max_sw > 512) return hipErrorInvalidValue;
     const bool small = a.n_inner <= Win<0>::INNER && a.ring <= Win<0>::RING;
     if (!small && (a.n_inner > Win<1>::INNER || a.ring > Win<1>::RING)) return hipErrorInvalidValue;

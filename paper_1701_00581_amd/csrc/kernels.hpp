@@ -94,6 +94,13 @@ struct SolveArgs {
     int noise_bias = 0;
     double *amp = nullptr;
     double2 *phasor = nullptr;
+    // least-squares refinement (phase_method 1)
+    int phase_method = 0, lsq_iters = 0;
+    const unsigned *wcode = nullptr;      // sample codes with W indices
+    const int *side_off = nullptr;        // [|W| + 1]
+    const uint2 *side_ent = nullptr;      // [2 |S|] entries (see plan.hpp)
+    SolveArgs() = default;
+    SolveArgs(const SolveArgs &o, int method) : SolveArgs(o) { phase_method = method; }
 };
 hipError_t launch_solve(const SolveArgs &a, hipStream_t st);
 

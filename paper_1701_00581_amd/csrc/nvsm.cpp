@@ -32,7 +32,8 @@ struct DevicePlan {
     std::vector<void *> bufs;
     int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr,
         *group_xy = nullptr, *slot = nullptr, *out_idx = nullptr;
-    unsigned *code = nullptr;
+    unsigned *code = nullptr, *wcode = nullptr, *side_ent = nullptr;
+    int *side_off = nullptr;
     float2 *twiddle = nullptr;
     float *hann = nullptr, *filt = nullptr;
     ~DevicePlan() {
@@ -82,7 +83,11 @@ nvsm_status check_params(const nvsm_params *p, std::string *msg) {
         return NVSM_ERR_INVALID_ARG;
     }
     if (p->window != 0 && p->window != 1) { *msg = "window must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
-    if (p->phase_method != 0) { *msg = "only the recursive phase solve (0) is available"; return NVSM_ERR_NOT_IMPLEMENTED; }
+    if (p->phase_method != 0 && p->phase_method != 1) { *msg = "phase_method must be 0 or 1"; return NVSM_ERR_NOT_IMPLEMENTED; }
+    if (p->phase_method == 1 && (p->lsq_iters < 1 || p->lsq_iters > 10000)) {
+        *msg = "lsq_iters must be in [1, 10000]";
+        return NVSM_ERR_INVALID_ARG;
+    }
     if (p->noise_bias != 0 && p->noise_bias != 1) { *msg = "noise_bias must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
     if (p->filter != 0 && p->filter != 1) { *msg = "filter must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
     if (!(p->stf_floor >= 0.0) || !std::isfinite(p->stf_floor)) { *msg = "stf_floor must be finite and >= 0"; return NVSM_ERR_INVALID_ARG; }
@@ -288,6 +293,9 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
         (s = upload(dp.get(), h.shell_wb, &dp->shell_wb, &msg)) ||
         (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
         (s = upload(dp.get(), h.phase_slot_code, &dp->code, &msg)) ||
+        (s = upload(dp.get(), h.phase_code, &dp->wcode, &msg)) ||
+        (s = upload(dp.get(), h.side_off, &dp->side_off, &msg)) ||
+        (s = upload(dp.get(), h.side_ent, &dp->side_ent, &msg)) ||
         (s = upload(dp.get(), h.items, &dp->items, &msg)) ||
         (s = upload(dp.get(), h.group_xy, &dp->group_xy, &msg)) ||
         (s = upload(dp.get(), h.slot_v, &dp->slot, &msg)) ||
@@ -384,6 +392,8 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, co
     a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;
     a.floor = p->stf_floor; a.noise_bias = p->noise_bias; a.amp = amp;
     a.phasor = (double2 *)phasor;
+    a.phase_method = p->phase_method; a.lsq_iters = p->lsq_iters;
+    a.wcode = dp->wcode; a.side_off = dp->side_off; a.side_ent = (const uint2 *)dp->side_ent;
     StageTimer t(ctx, ST_SOLVE, st);
     return launch_solve(a, st);
 }
@@ -489,6 +499,8 @@ nvsm_status nvsm_default_params(int32_t patch, nvsm_params *out) {
     out->noise_bias = 0;
     out->filter = 0;
     out->stf_floor = 1e-6;
+    out->lsq_iters = 10;
+    out->reserved = 0;
     return NVSM_OK;
 }
 

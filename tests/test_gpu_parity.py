@@ -298,3 +298,89 @@ def test_full_burst2560_sampled(torch_cuda):
     merr = np.linalg.norm(g - win) / np.linalg.norm(win - win.mean())
     say(f"[burst2560] mosaic window {merr:.2e}")
     assert merr <= MOSAIC_TOL
+
+
+def _lsq_case(torch, nv, name, F, H, W, v_radius, ks, iters, screens):
+    """Least-squares refinement on identical FP32-rounded inputs: the GPU
+    solve with phase_method 1 against the oracle's recursion followed by
+    its least-squares steps, patch by patch."""
+    fr = burst(name, F=F, H=H, W=W)
+    p = nv.default_params(128, v_radius=v_radius, noise_bias=1)
+    p.phase_method = 1
+    p.lsq_iters = iters
+    op = oparams(p)
+    Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+    Ps, Ms, Bs = [], [], []
+    for k in ks:
+        acc = oracle.accumulate_patch(cube(fr, p, k), op, S)
+        Ps.append(acc["P"].astype(np.float32))
+        Ms.append(np.array([[acc["M10"].real, acc["M10"].imag], [acc["M01"].real, acc["M01"].imag]], np.float32))
+        Bs.append(np.stack([acc["B"].real, acc["B"].imag], -1).astype(np.float32))
+    st = stf(name, screens=screens)
+    ctx = nv.nvsm_create(0)
+    try:
+        n = len(ks)
+        amp = torch.empty(n, len(Wset), dtype=torch.float64, device="cuda")
+        ph = torch.empty(n, len(Wset), 2, dtype=torch.float64, device="cuda")
+        nv.nvsm_solve(ctx, p, n, torch.from_numpy(np.stack(Ps)).cuda(), torch.from_numpy(np.stack(Ms)).cuda(),
+                      torch.from_numpy(np.stack(Bs)).cuda(), torch.from_numpy(st).cuda(), amp, ph)
+        torch.cuda.synchronize()
+    finally:
+        nv.nvsm_destroy(ctx)
+    ph = as_complex(ph)
+    for i in range(len(ks)):
+        B64 = Bs[i][..., 0].astype(np.float64) + 1j * Bs[i][..., 1].astype(np.float64)
+        e0 = oracle.phase_recursion(B64, complex(*Ms[i][0].astype(np.float64)),
+                                    complex(*Ms[i][1].astype(np.float64)), Wset, S, woff, p.patch)
+        eo = oracle.phase_least_squares(B64, e0, Wset, S, woff, iters)
+        rms, mx = phase_rms(ph[i], eo)
+        moved, _ = phase_rms(eo, e0)
+        say(f"[lsq {name} R={v_radius} it={iters}] patch {ks[i]}: vs oracle rms {rms:.2e} max {mx:.2e} "
+            f"(refinement moved the phases by rms {moved:.2e})")
+        assert moved > 1e-6               # the steps did something
+        assert rms <= 1e-9
+        assert np.max(np.abs(ph[i][:2] - e0[:2])) < 1e-12     # the seeds stay
+
+
+def test_lsq_on_identical_inputs(torch_cuda):
+    """Crop of the 1024 burst, N = 128, R = 10, three patches (corner, inner,
+    edge), 10 steps; then one step, where a wrong side entry shows alone."""
+    import paper_1701_00581_amd as nv
+    say("case lsq: burst1024 crop 250x300 F=37 N=128 R=10, iters 10 and 1")
+    _lsq_case(torch_cuda, nv, "burst1024", 37, 250, 300, 10, [0, 5, 11], 10, 100)
+    _lsq_case(torch_cuda, nv, "burst1024", 37, 250, 300, 10, [5], 1, 100)
+
+
+def test_lsq_full_size_patch(torch_cuda):
+    """The 2160x2560 burst's configuration (N = 128, R = 12, all of W): one
+    patch, 8 frames, 10 steps."""
+    import paper_1701_00581_amd as nv
+    say("case lsq: burst2560 patch 0 F=8 N=128 R=12, iters 10")
+    _lsq_case(torch_cuda, nv, "burst2560", 8, 128, 128, 12, [0], 10, 60)
+
+
+def test_single64_lsq_whole_path(torch_cuda):
+    """The whole path with the least-squares phase (phase_method 1) against
+    the oracle's reconstruction with the same method."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case single64 lsq: accumulate/solve/synthesize, F=100, N=64, R=8, 10 steps")
+    fr = burst("single64")
+    p = nv.default_params(64, v_radius=8, window=0)
+    p.phase_method = 1
+    p.lsq_iters = 10
+    s = _session(p, 64, 64, 100)
+    s.accumulate(to_device(fr))
+    st = stf("single64")
+    s.solve(torch.from_numpy(st).cuda())
+    s.synthesize()
+    torch.cuda.synchronize()
+    ref = oracle.reconstruct(fr, oparams(p), st)
+    t = ref["tiles"][(0, 0)]
+    rms, mx = phase_rms(as_complex(s.phasor)[0], t["phasor"])
+    img = s.image.cpu().numpy()
+    o = ref["image"]
+    merr = np.linalg.norm(img - o) / np.linalg.norm(o - o.mean())
+    say(f"[single64 lsq] phase rms {rms:.2e} max {mx:.2e} mosaic {merr:.2e}")
+    assert rms <= PHASE_RMS_TOL
+    assert merr <= MOSAIC_TOL

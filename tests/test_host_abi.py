@@ -75,8 +75,13 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
         setattr(p, field, bad)
         assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG, field
     p = nv.default_params(128)
-    p.phase_method = 1
+    p.phase_method = 2
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_NOT_IMPLEMENTED
+    p = nv.default_params(128)
+    p.phase_method = 1
+    assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_OK
+    p.lsq_iters = 0
+    assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG
     p = nv.default_params(128)
     assert L.nvsm_plan(ctypes.byref(p), 100, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 0, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
