@@ -19,6 +19,7 @@ import numpy as np
 __all__ = [
     "tiling", "hann", "window2d", "patch_spectra", "frequency_half_disk",
     "bispectrum_set", "accumulate_patch", "bispectrum", "noise_bias",
+    "photon_noise_terms", "debias_bispectrum",
     "amplitude", "phase_recursion", "phase_least_squares", "diffraction_filter",
     "synthesize_patch", "mosaic", "reconstruct", "Params",
 ]
@@ -29,13 +30,14 @@ class Params:
 
     def __init__(self, patch=128, stride=None, u_cut=None, v_radius=10,
                  window=1, noise_bias=0, filter=0, stf_floor=1e-6,
-                 phase_method=0, lsq_iters=10):
+                 phase_method=0, lsq_iters=10, photons_per_adu=1.0):
         self.patch = int(patch)
         self.stride = int(patch // 2 if stride is None else stride)
         self.u_cut = int(patch // 2 - 1 if u_cut is None else u_cut)
         self.v_radius = int(v_radius)
         self.window = int(window)
-        self.noise_bias = int(noise_bias)
+        self.noise_bias = int(noise_bias)      # 0 off, 1 corner level, 2 photon model
+        self.photons_per_adu = float(photons_per_adu)
         self.filter = int(filter)
         self.stf_floor = float(stf_floor)
         self.phase_method = int(phase_method)   # 0 recursion, 1 + least squares
@@ -166,11 +168,53 @@ def bispectrum(I, wv):
     return acc / F
 
 
+def photon_noise_terms(cube, window, gain):
+    """Photon-noise terms of the power spectrum and bispectrum of a cube.
+
+    Model (the paper gives none): a pixel value is p = c / G with c photon
+    counts, Poisson given the noise-free image, and G = ``gain`` photons per
+    unit of p.  Per pixel the noise then has variance E[p] / G and third
+    cumulant E[p] / G^2, both estimated without bias by the data itself.
+    With t the taper, I = FFT2((p - mu) t) as in ``patch_spectra`` and
+    Q(u) = FFT2(t^2 p)(u) / G, per frame:
+        C(u) = conj(I(u)) Q(u),   q0 = sum(t^2 p) / G,   T = sum(t^3 p) / G^2.
+    The noise adds q0 (in expectation) to |I(u)|^2 and
+        C(w) + conj C(v) + conj C(w - v) - 2 T
+    to I(w - v) I(v) conj I(w), where the taper's transform vanishes at
+    the three frequencies (for the Hann taper: each has a component of
+    modulus >= 2; with no taper: each is non-zero); there the mean removal
+    adds terms that these estimates leave out.
+    Returns (C [N][N] complex = <C(u)>, q0 = <q0>, T = <T>) over frames.
+    """
+    cube = np.asarray(cube, dtype=np.float64)
+    F, N, _ = cube.shape
+    t = window2d(N, window)
+    I, _ = patch_spectra(cube, window)
+    Q = np.fft.fft2(cube * (t * t)[None], axes=(1, 2)) / gain
+    C = np.mean(np.conj(I) * Q, axis=0)
+    q0 = float(np.mean(np.sum(cube * (t * t)[None], axis=(1, 2)))) / gain
+    T = float(np.mean(np.sum(cube * (t * t * t)[None], axis=(1, 2)))) / (gain * gain)
+    return C, q0, T
+
+
+def debias_bispectrum(B, C, T, wv):
+    """B(w, v) - [C(w) + conj C(v) + conj C(w - v)] + 2 T on the samples
+    ``wv`` ([n][4] of (wx, wy, vx, vy)); C on the N x N grid (DFT order)."""
+    N = C.shape[0]
+    wx, wy, vx, vy = (np.asarray(wv)[:, i] for i in range(4))
+    cw = C[wy % N, wx % N]
+    cv = C[vy % N, vx % N]
+    cd = C[(wy - vy) % N, (wx - vx) % N]
+    return B - (cw + np.conj(cv) + np.conj(cd)) + 2.0 * T
+
+
 def accumulate_patch(cube, params, S=None):
     """Power spectrum, mean spectrum, mean level and bispectrum of a cube.
 
     Returns dict with P [N][N] = <|I|^2>, M10 = <I(1,0)>, M01 = <I(0,1)>,
-    mu = <mu_f>, B [|S|] complex (None when S is None).
+    mu = <mu_f>, B [|S|] complex (None when S is None).  With the photon
+    noise model (noise_bias 2) P and B are the corrected means of
+    ``photon_noise_terms`` (P - q0, and ``debias_bispectrum``).
     """
     I, mu = patch_spectra(np.asarray(cube, dtype=np.float64), params.window)
     P = np.mean(np.abs(I) ** 2, axis=0)
@@ -178,6 +222,11 @@ def accumulate_patch(cube, params, S=None):
     out = dict(P=P, M10=M[0, 1], M01=M[1, 0], mu=float(np.mean(mu)), B=None)
     if S is not None:
         out["B"] = bispectrum(I, S)
+    if params.noise_bias == 2:
+        C, q0, T = photon_noise_terms(cube, params.window, params.photons_per_adu)
+        out["P"] = P - q0
+        if S is not None:
+            out["B"] = debias_bispectrum(out["B"], C, T, S)
     return out
 
 
@@ -388,7 +437,7 @@ def reconstruct(frames, params, stf, patch_list=None, keep=False):
     for (i, j) in tiles:
         cube = frames[:, ys[i]:ys[i] + N, xs[j]:xs[j] + N]
         acc = accumulate_patch(cube, params, S)
-        nb = noise_bias(acc["P"]) if params.noise_bias else 0.0
+        nb = noise_bias(acc["P"]) if params.noise_bias == 1 else 0.0
         amp = amplitude(acc["P"], stf, Wset, nb, params.stf_floor)
         ph = phase_recursion(acc["B"], acc["M10"], acc["M01"], Wset, S, woff, N)
         if params.phase_method == 1:
