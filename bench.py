@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--phase-method", type=int, default=0, choices=(0, 1),
                     help="0: the recursion; 1: the recursion followed by least-squares steps")
     ap.add_argument("--lsq-iters", type=int, default=10, help="least-squares steps with --phase-method 1")
+    ap.add_argument("--noise-bias", type=int, default=None, choices=(0, 1, 2),
+                    help="override the workload's noise term: 0 none, 1 corner level, 2 photon-noise model")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for traffic counters)")
@@ -333,7 +335,11 @@ def main():
     gen_s = time.perf_counter() - t
     print(f"[bench] generated {args.workload} {F}x{H}x{W} {frames.dtype} in {gen_s:.1f} s", file=sys.stderr,
           flush=True)
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.noise_bias is not None:
+        wl["noise_bias"] = args.noise_bias
+    # photon-noise gain of the synthetic frames: 12-bit units of photons / 2048, or photon counts
+    gain = cfg.photons / 2048.0 if frames.dtype == np.uint16 else 1.0
 
     # CPU baseline first, before the GPU runtime exists in this process
     cpu = None
@@ -342,7 +348,7 @@ def main():
         workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
         op = oracle.Params(patch=wl["patch"], v_radius=wl["v_radius"], window=wl.get("window", 1),
                            noise_bias=wl["noise_bias"], filter=wl["filter"], phase_method=args.phase_method,
-                           lsq_iters=args.lsq_iters)
+                           lsq_iters=args.lsq_iters, photons_per_adu=gain)
         cpu = cpu_baseline(frames, stf, op, len(ys) * len(xs), len(ys), len(xs), workers)
         print(f"[bench] cpu baseline {cpu['value']:.3e} bursts/s ({cpu['sample']})", file=sys.stderr, flush=True)
 
@@ -353,6 +359,7 @@ def main():
                           noise_bias=wl["noise_bias"], filter=wl["filter"])
     p.phase_method = args.phase_method
     p.lsq_iters = args.lsq_iters
+    p.photons_per_adu = gain
     s = nv.Session(p, H, W, F)
     # host -> device upload of the burst (pinned), reported beside the value
     raw = frames.view(np.int16) if frames.dtype == np.uint16 else frames
@@ -424,7 +431,8 @@ def main():
             "workload": f"{args.workload}: {W}x{H} x {F} {'uint16 12-bit' if frames.dtype == np.uint16 else 'float32'} "
                         f"frames, {p.patch}x{p.patch} patches at stride {p.stride} ({info.patches_x}x{info.patches_y}), "
                         f"|v|<={p.v_radius}, u_cut {p.u_cut}, FP32 compensated accumulation, FP64 solve"
-                        + (f", {p.lsq_iters} least-squares phase steps" if p.phase_method == 1 else ""),
+                        + (f", {p.lsq_iters} least-squares phase steps" if p.phase_method == 1 else "")
+                        + (", photon-noise terms" if p.noise_bias == 2 else ""),
             "frames": F, "height": H, "width": W, "patch": p.patch, "v_radius": p.v_radius,
             "patches": P, "bispectrum_samples_per_patch": S, "parallelism": "single GPU",
         },

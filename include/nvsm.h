@@ -72,11 +72,16 @@ typedef struct {
     int32_t window;       /* 0 none, 1 periodic Hann taper (default 1)      */
     int32_t phase_method; /* 0 recursive speckle-masking solve; 1 the same, then
                            * lsq_iters least-squares refinement steps      */
-    int32_t noise_bias;   /* 0 off, 1 subtract the mean power beyond |u| > N/2+2 */
+    int32_t noise_bias;   /* 0 off; 1 subtract the mean power beyond |u| > N/2+2
+                           * in the solve; 2 photon-noise model (see
+                           * nvsm_accumulate), gain photons_per_adu       */
     int32_t filter;       /* 0 none, 1 diffraction-limited OTF of the pupil  */
     double  stf_floor;    /* modulus 0 where STF < stf_floor (default 1e-6) */
     int32_t lsq_iters;    /* refinement steps for phase_method 1, 1..10000 (default 10) */
     int32_t reserved;     /* 0                                              */
+    double  photons_per_adu; /* G for noise_bias 2: photons per unit of pixel
+                           * value, finite and > 0 (default 1: frames in
+                           * photon counts)                                 */
 } nvsm_params;
 
 /* Sizes derived from parameters and a burst shape (nvsm_plan). */
@@ -104,7 +109,7 @@ const char *nvsm_last_error(const nvsm_context *ctx);
 
 /* Defaults for patch size N (64 or 128): stride N/2, u_cut N/2-1, R 10,
  * Hann window, recursive phase (10 refinement steps if phase_method is set
- * to 1), no noise bias, no filter, floor 1e-6. */
+ * to 1), no noise bias (photons_per_adu 1), no filter, floor 1e-6. */
 nvsm_status nvsm_default_params(int32_t patch, nvsm_params *out);
 
 /* Validates params against an H x W x F burst and fills *out.  Host only. */
@@ -133,7 +138,17 @@ nvsm_status nvsm_prepare(nvsm_context *ctx, const nvsm_params *p);
  *   bispec    [P][|S|][2] float <I_f(w-v) I_f(v) conj I_f(w)> in S order,
  *             or NULL to skip the bispectrum.
  * frames: device [F][H][row_pitch] of uint16 or float32.
- * Arithmetic: FP32; sums over frames use compensated (Kahan) summation. */
+ * Arithmetic: FP32; sums over frames use compensated (Kahan) summation.
+ * noise_bias 2 (photon noise; the paper gives no noise model): pixel values
+ * are Poisson photon counts over G = photons_per_adu.  With
+ * Q_f = FFT2(t^2 p_f) / G, C(u) = <conj I_f(u) Q_f(u)>, q0 = <sum t^2 p_f> / G
+ * and T = <sum t^3 p_f> / G^2, power is returned as <|I_f|^2> - q0 and
+ * bispec as the mean minus C(w) + conj C(v) + conj C(w-v) - 2T: the noise
+ * terms in expectation wherever the taper's transform vanishes at w, v and
+ * w - v (for the Hann taper: each has a component of modulus >= 2; with no
+ * taper: all of them), in the manner of the photon-counting corrections of
+ * speckle interferometry and speckle masking.  The streaming calls reject
+ * noise_bias 2 (NVSM_ERR_NOT_IMPLEMENTED). */
 nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p,
                             const void *frames, nvsm_dtype dtype, int32_t F,
                             int32_t H, int32_t W, int64_t row_pitch,
@@ -142,8 +157,9 @@ nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p,
 
 /* Modulus and phase per patch, FP64 (Eq. 1; speckle-masking recursion).
  *   amp[k][i]    = sqrt(max(power(w_i) - n, 0) / stf(w_i)), 0 where
- *                  stf(w_i) < stf_floor; n is the noise level (0 unless
- *                  noise_bias).  double [P][|W|].
+ *                  stf(w_i) < stf_floor; n is the corner noise level
+ *                  with noise_bias 1, else 0 (noise_bias 2 corrects power
+ *                  in the accumulation).  double [P][|W|].
  *   phasor[k][i] = e(w_i) (re, im), double [P][|W|][2]: e(1,0), e(0,1) are
  *                  the unit phasors of mean_spec, and every other w takes the
  *                  phase of sum_v e(w-v) e(v) conj B(w,v) over its samples,

@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
         ("patch", ctypes.c_int32), ("stride", ctypes.c_int32), ("u_cut", ctypes.c_int32),
         ("v_radius", ctypes.c_int32), ("window", ctypes.c_int32), ("phase_method", ctypes.c_int32),
         ("noise_bias", ctypes.c_int32), ("filter", ctypes.c_int32), ("stf_floor", ctypes.c_double),
-        ("lsq_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("lsq_iters", ctypes.c_int32), ("reserved", ctypes.c_int32), ("photons_per_adu", ctypes.c_double),
     ]
 
 

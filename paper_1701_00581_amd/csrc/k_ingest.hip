@@ -299,6 +299,233 @@ hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Photon-noise terms of one (patch, frame group), over the ingest grid.
+// Each frame is transformed as z = (p - mu) t + i (p - mu) t^2: both halves
+// have the scale of the fluctuations, so the FP32 rounding of one does not
+// swamp the other.  One FFT gives I(u) = (Z(u) + conj Z(-u)) / 2 and
+// Y(u) = (Z(u) - conj Z(-u)) / (2i), and Q(u) = (Y(u) + mu D(u)) / G with D
+// the transform of t^2 (for the periodic Hann taper the product of
+// 3N/8, -N/4, N/16 at per-axis frequency 0, +-1, +-2 and 0 elsewhere; N^2
+// at u = 0 without taper).  The group's sums of conj I(u) Q(u) (rows
+// 0..N/2), of q0 = sum(t^2 p) / G and of T = sum(t^3 p) / G^2 go to the
+// workgroup's partials.
+// DFT of the squared taper at (ux, uy) (indices mod N): real, separable.
+template <int N>
+__device__ __forceinline__ float taper2_dft(int window, int ux, int uy) {
+    if (!window) return (ux == 0 && uy == 0) ? (float)(N * N) : 0.f;
+    auto axis = [](int k) {
+        const int m = k <= N / 2 ? k : k - N;          // signed frequency
+        return m == 0 ? 0.375f * N : (m == 1 || m == -1) ? -0.25f * N : (m == 2 || m == -2) ? 0.0625f * N : 0.f;
+    };
+    return axis(ux) * axis(uy);
+}
+
+template <int N, typename T, bool VEC>
+__global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, int chunk_frames, int window,
+                                              float inv_wsum, float inv_gain, const float2 *__restrict__ twiddle,
+                                              const float *__restrict__ hann, float2 *__restrict__ cpart,
+                                              float *__restrict__ spart) {
+    constexpr int P = LdsPitch<N>::v;
+    constexpr int HALF = N / 2;
+    constexpr int NP = (HALF + 1) * N;
+    constexpr int NPT = (NP + NT - 1) / NT;
+    constexpr int QPT = N * N / 4 / NT;
+    __shared__ float2 z[N * P];
+    __shared__ float2 tw[N];
+    __shared__ float hw[N];
+    __shared__ float red[3][NT / 64];
+
+    const int L = xcd_remap(blockIdx.x, bt.ingest_wgs);
+    const int b = burst_of(bt, L, [](const BurstDesc &d) { return (int64_t)d.ingest0; });
+    const BurstDesc &bd = bt.b[b];
+    const int F = bd.F, H = bd.H, W = bd.W, nx = bd.nx;
+    const int64_t pitch = bd.pitch;
+    const T *frames = (const T *)bd.frames;
+    const int nchunks = (F + chunk_frames - 1) / chunk_frames;
+    const int local = L - bd.ingest0;
+    const int lpatch = local / nchunks, chunk = local % nchunks;
+    const int py = lpatch / nx, px = lpatch % nx;
+    const int y0 = min(py * stride, H - N), x0 = min(px * stride, W - N);
+    const int f0 = chunk * chunk_frames, f1 = min(F, f0 + chunk_frames);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += NT) {
+        tw[i] = twiddle[i];
+        hw[i] = window ? hann[i] : 1.0f;
+    }
+    float2 cs[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) cs[i] = make_float2(0.f, 0.f);
+    float q0s = 0.f, q0c = 0.f, ts = 0.f, tc = 0.f;
+    __syncthreads();
+
+    for (int f = f0; f < f1; ++f) {
+        const T *pf = frames + (size_t)f * H * pitch + (size_t)y0 * pitch + x0;
+        float s1 = 0.f, c1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            Quad<T, VEC> v;
+            v.load(pf + (size_t)y * pitch + x);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float w = hw[y] * hw[x + e];
+                const float wp = w * v[e];
+                kahan_add(s1, c1, wp);
+                s2 += w * wp;
+                s3 += w * w * wp;
+                z[y * P + x + e] = make_float2(v[e], 0.f);
+            }
+        }
+        const float r1 = wave_sum(s1 - c1), r2 = wave_sum(s2), r3 = wave_sum(s3);
+        if ((tid & 63) == 0) { red[0][tid >> 6] = r1; red[1][tid >> 6] = r2; red[2][tid >> 6] = r3; }
+        __syncthreads();
+        float mu = 0.f, q0 = 0.f, t3 = 0.f;
+#pragma unroll
+        for (int k = 0; k < NT / 64; ++k) { mu += red[0][k]; q0 += red[1][k]; t3 += red[2][k]; }
+        mu *= inv_wsum;
+        if (tid == 0) {
+            kahan_add(q0s, q0c, q0 * inv_gain);
+            kahan_add(ts, tc, t3 * inv_gain * inv_gain);
+        }
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float w = hw[y] * hw[x + e];
+                const float d = (z[y * P + x + e].x - mu) * w;
+                z[y * P + x + e] = make_float2(d, d * w);
+            }
+        }
+        __syncthreads();
+        fft2d_lds<N, NT>(z, tw);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int j = k * NT + tid;
+            if (j < NP) {
+                const int uy = j / N, ux = j % N;
+                const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
+                const float2 Zm = z[fft_pos<N>((N - uy) & (N - 1)) * P + fft_pos<N>((N - ux) & (N - 1))];
+                const float2 I = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+                float2 Q = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+                Q.x = (Q.x + mu * taper2_dft<N>(window, ux, uy)) * inv_gain;
+                Q.y *= inv_gain;
+                cs[k].x += I.x * Q.x + I.y * Q.y;         // conj(I) Q
+                cs[k].y += I.x * Q.y - I.y * Q.x;
+            }
+        }
+        __syncthreads();
+    }
+    float2 *cp = cpart + (size_t)L * NP;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int j = k * NT + tid;
+        if (j < NP) cp[j] = cs[k];
+    }
+    if (tid == 0) {
+        spart[(size_t)L * 2] = q0s - q0c;
+        spart[(size_t)L * 2 + 1] = ts - tc;
+    }
+}
+
+// Sums the frame groups of k_noise per patch (compensated), divides by F,
+// keeps C on W, and subtracts q0 from the patch's power spectrum.
+template <int N>
+__global__ __launch_bounds__(NT) void k_noise_finalize(const BurstTable bt, int chunk_frames,
+                                                       const float2 *__restrict__ cpart,
+                                                       const float *__restrict__ spart, int nW,
+                                                       const int *__restrict__ Wxy, float *__restrict__ power,
+                                                       float2 *__restrict__ cw, float *__restrict__ nbar) {
+    constexpr int HALF = N / 2, NP = (HALF + 1) * N;
+    const int patch = blockIdx.x;
+    const int b = burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; });
+    const BurstDesc &bd = bt.b[b];
+    const int nchunks = (bd.F + chunk_frames - 1) / chunk_frames;
+    const float invF = 1.0f / (float)bd.F;
+    const size_t wg0 = (size_t)bd.ingest0 + (size_t)(patch - bd.patch0) * nchunks;
+    // every thread forms the same two means in the same order
+    float q0 = 0.f, q0c = 0.f, t3 = 0.f, t3c = 0.f;
+    for (int k = 0; k < nchunks; ++k) {
+        kahan_add(q0, q0c, spart[(wg0 + k) * 2]);
+        kahan_add(t3, t3c, spart[(wg0 + k) * 2 + 1]);
+    }
+    q0 = (q0 - q0c) * invF;
+    t3 = (t3 - t3c) * invF;
+    if (threadIdx.x == 0) {
+        nbar[(size_t)patch * 2] = q0;
+        nbar[(size_t)patch * 2 + 1] = t3;
+    }
+    const float2 *cp = cpart + wg0 * NP;
+    for (int i = threadIdx.x; i < nW; i += NT) {
+        const int wx = Wxy[2 * i], wy = Wxy[2 * i + 1];          // 0 <= wy < N/2
+        const int j = wy * N + (wx & (N - 1));
+        float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f;
+        for (int k = 0; k < nchunks; ++k) {
+            const float2 v = cp[(size_t)k * NP + j];
+            kahan_add(sx, cx, v.x);
+            kahan_add(sy, cy, v.y);
+        }
+        cw[(size_t)patch * nW + i] = make_float2((sx - cx) * invF, (sy - cy) * invF);
+    }
+    float *pw = power + (size_t)patch * N * N;
+    for (int j = threadIdx.x; j < N * N; j += NT) pw[j] -= q0;
+}
+
+// B(w, v) -= C(w) + conj C(w - v) + conj C(v) - 2T for the samples of DEB_W
+// consecutive w of one patch (grid: w blocks x patches).  The codes give
+// the W index of w - v and v and whether the sample holds the conjugate
+// (C(-u) = conj C(u)); each thread finds the w of its sample by bisection
+// of the block's sample offsets.
+constexpr int DEB_W = 64;
+__global__ __launch_bounds__(NT) void k_debias(int nW, const int *__restrict__ woff,
+                                               const unsigned *__restrict__ wcode, const float2 *__restrict__ cw,
+                                               const float *__restrict__ nbar, float2 *__restrict__ bispec,
+                                               int64_t s_count) {
+    __shared__ int off[DEB_W + 1];
+    const int patch = blockIdx.y;
+    const int w0 = blockIdx.x * DEB_W, n = min(nW, w0 + DEB_W) - w0;
+    for (int i = threadIdx.x; i <= n; i += NT) off[i] = woff[w0 + i];
+    __syncthreads();
+    const float2 *C = cw + (size_t)patch * nW;
+    const float t2 = 2.0f * nbar[(size_t)patch * 2 + 1];
+    float2 *B = bispec + (size_t)patch * s_count;
+    for (int t = off[0] + threadIdx.x; t < off[n]; t += NT) {
+        int lo = 0, hi = n;                                  // off[lo] <= t < off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= t) lo = mid; else hi = mid;
+        }
+        const unsigned cd = wcode[t];
+        const float2 c_w = C[w0 + lo];
+        float2 ca = C[(cd >> 16) & 0x7fffu];
+        if (cd >> 31) ca.y = -ca.y;
+        float2 cb = C[cd & 0x7fffu];
+        if (cd & 0x8000u) cb.y = -cb.y;
+        float2 v = B[t];
+        v.x -= c_w.x + ca.x + cb.x - t2;
+        v.y -= c_w.y - ca.y - cb.y;
+        B[t] = v;
+    }
+}
+
+template <int N, typename T>
+hipError_t launch_noise_t(const NoiseArgs &na, hipStream_t st) {
+    const IngestArgs &a = na.in;
+    if (a.vec)
+        hipLaunchKernelGGL((k_noise<N, T, true>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+                           a.chunk_frames, a.window, a.inv_wsum, na.inv_gain, a.twiddle, a.hann, na.cpart,
+                           na.spart);
+    else
+        hipLaunchKernelGGL((k_noise<N, T, false>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+                           a.chunk_frames, a.window, a.inv_wsum, na.inv_gain, a.twiddle, a.hann, na.cpart,
+                           na.spart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_noise_finalize<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames, na.cpart,
+                       na.spart, na.nW, na.Wxy, a.power, na.cw, na.nbar);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(NT) void k_zero(float4 *__restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -311,6 +538,22 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((n + NT - 1) / NT, 8192);
     hipLaunchKernelGGL(k_zero, dim3(grid), dim3(NT), 0, st, (float4 *)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise(const NoiseArgs &na, hipStream_t st) {
+    const IngestArgs &a = na.in;
+    if (a.bt.patches == 0) return hipSuccess;
+    if (na.nW < 1 || na.nW > 0x8000) return hipErrorInvalidValue;
+    if (a.N == 128) return a.f32 ? launch_noise_t<128, float>(na, st) : launch_noise_t<128, uint16_t>(na, st);
+    return a.f32 ? launch_noise_t<64, float>(na, st) : launch_noise_t<64, uint16_t>(na, st);
+}
+
+hipError_t launch_debias(const NoiseArgs &na, hipStream_t st) {
+    if (na.in.bt.patches == 0) return hipSuccess;
+    if (na.nW < 1 || na.nW > 0x8000 || na.in.bt.patches > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_debias, dim3((na.nW + DEB_W - 1) / DEB_W, na.in.bt.patches), dim3(NT), 0, st, na.nW,
+                       na.woff, na.wcode, na.cw, na.nbar, na.bispec, na.s_count);
     return hipGetLastError();
 }
 

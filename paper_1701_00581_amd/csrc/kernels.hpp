@@ -51,6 +51,31 @@ struct IngestArgs {
     float inv_total = 0.f;
 };
 hipError_t launch_ingest(const IngestArgs &a, hipStream_t st);
+
+// Photon-noise terms (pixel values Poisson counts over a gain G).  Per patch
+// and frame, with t the taper and I the spectrum of the ingest:
+// Q = FFT2(t^2 p) / G, C(u) = conj I(u) Q(u), q0 = sum(t^2 p) / G,
+// T = sum(t^3 p) / G^2.  launch_noise accumulates their means over the
+// frames (the workgroups of the ingest grid, then one pass per patch that
+// keeps C on W and subtracts q0 from the power spectrum); launch_debias
+// subtracts C(w) + conj C(v) + conj C(w - v) - 2T from every bispectrum
+// sample in place.
+struct NoiseArgs {
+    IngestArgs in;                        // grid, frames, taper, power spectrum
+    float inv_gain = 0.f;                 // 1 / G
+    float2 *cpart = nullptr;              // [ingest wgs][N/2 + 1][N] sums of C over a frame group
+    float *spart = nullptr;               // [ingest wgs][2] sums of q0 and T
+    float2 *cw = nullptr;                 // [P][nW] mean C on W
+    float *nbar = nullptr;                // [P][2] mean q0 and T
+    int nW = 0;
+    const int *Wxy = nullptr, *woff = nullptr;
+    const unsigned *wcode = nullptr;      // per sample: codes of w - v (high half) and v
+    float2 *bispec = nullptr;             // [P][s_count], corrected in place
+    int64_t s_count = 0;
+};
+hipError_t launch_noise(const NoiseArgs &a, hipStream_t st);
+hipError_t launch_debias(const NoiseArgs &a, hipStream_t st);
+
 // Zeroes bytes (a multiple of 16, 16-byte aligned) with a fill kernel.
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 

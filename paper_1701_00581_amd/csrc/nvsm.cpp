@@ -88,7 +88,11 @@ nvsm_status check_params(const nvsm_params *p, std::string *msg) {
         *msg = "lsq_iters must be in [1, 10000]";
         return NVSM_ERR_INVALID_ARG;
     }
-    if (p->noise_bias != 0 && p->noise_bias != 1) { *msg = "noise_bias must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
+    if (p->noise_bias < 0 || p->noise_bias > 2) { *msg = "noise_bias must be 0, 1 or 2"; return NVSM_ERR_INVALID_ARG; }
+    if (p->noise_bias == 2 && !(p->photons_per_adu > 0.0 && std::isfinite(p->photons_per_adu))) {
+        *msg = "photons_per_adu must be finite and > 0";
+        return NVSM_ERR_INVALID_ARG;
+    }
     if (p->filter != 0 && p->filter != 1) { *msg = "filter must be 0 or 1"; return NVSM_ERR_INVALID_ARG; }
     if (!(p->stf_floor >= 0.0) || !std::isfinite(p->stf_floor)) { *msg = "stf_floor must be finite and >= 0"; return NVSM_ERR_INVALID_ARG; }
     return NVSM_OK;
@@ -104,6 +108,7 @@ nvsm_status check_shape(const nvsm_params *p, int H, int W, int F, std::string *
 struct Sizes {
     int64_t P = 0, nW = 0, S = 0, records = 0, wgs = 0;
     size_t spectra = 0, ppart = 0, mpart = 0, mupart = 0;      // accumulate scratch
+    size_t cpart = 0, spart = 0, cw = 0, nbar = 0;             // photon-noise terms (noise_bias 2)
     size_t power = 0, mean = 0, mu = 0, bispec = 0, amp = 0, phasor = 0, patches = 0;
 };
 
@@ -141,7 +146,7 @@ void make_table(const nvsm_params *p, const BurstIn *in, int n, BurstTable *bt, 
     *records = rec;
 }
 
-void sizes_for(int N, const BurstTable &bt, int64_t records, int64_t nW, int64_t S, Sizes *z) {
+void sizes_for(int N, const BurstTable &bt, int64_t records, int64_t nW, int64_t S, Sizes *z, bool photon) {
     z->P = bt.patches;
     z->nW = nW;
     z->S = S;
@@ -158,9 +163,17 @@ void sizes_for(int N, const BurstTable &bt, int64_t records, int64_t nW, int64_t
     z->amp = align_up((size_t)z->P * nW * 8);
     z->phasor = align_up((size_t)z->P * nW * 16);
     z->patches = align_up((size_t)z->P * N * N * 4);
+    if (photon) {
+        z->cpart = align_up((size_t)z->wgs * (N / 2 + 1) * N * 8);
+        z->spart = align_up((size_t)z->wgs * 2 * 4);
+        z->cw = align_up((size_t)z->P * nW * 8);
+        z->nbar = align_up((size_t)z->P * 2 * 4);
+    }
 }
 
-size_t ws_acc(const Sizes &z) { return z.spectra + z.ppart + z.mpart + z.mupart; }
+size_t ws_acc(const Sizes &z) {
+    return z.spectra + z.ppart + z.mpart + z.mupart + z.cpart + z.spart + z.cw + z.nbar;
+}
 size_t ws_rec(const Sizes &z) {
     return z.power + z.mean + z.mu + z.bispec + z.amp + z.phasor + z.patches + ws_acc(z);
 }
@@ -367,9 +380,22 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
     a.mupart = (float *)(ws + z.spectra + z.ppart + z.mpart);
     a.power = power; a.mean_spec = mean_spec; a.mu = mu;
     hipError_t e;
+    NoiseArgs na;
+    if (p->noise_bias == 2) {
+        char *q = ws + z.spectra + z.ppart + z.mpart + z.mupart;
+        na.in = a;
+        na.inv_gain = (float)(1.0 / p->photons_per_adu);
+        na.cpart = (float2 *)q; q += z.cpart;
+        na.spart = (float *)q; q += z.spart;
+        na.cw = (float2 *)q; q += z.cw;
+        na.nbar = (float *)q;
+        na.nW = (int)z.nW; na.Wxy = dp->W; na.woff = dp->woff; na.wcode = dp->wcode;
+        na.bispec = (float2 *)bispec; na.s_count = z.S;
+    }
     {
         StageTimer t(ctx, ST_INGEST, st);
         e = launch_ingest(a, st);
+        if (e == hipSuccess && p->noise_bias == 2) e = launch_noise(na, st);
     }
     if (e != hipSuccess || bispec == nullptr) return e;
     BispecArgs b;
@@ -379,7 +405,9 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
     b.bispec = (float2 *)bispec; b.s_count = z.S;
     b.form = choice_of(ctx, p).second; b.queue = ctx->queue;
     StageTimer t(ctx, ST_BISPEC, st);
-    return launch_bispec(b, st);
+    e = launch_bispec(b, st);
+    if (e == hipSuccess && p->noise_bias == 2) e = launch_debias(na, st);
+    return e;
 }
 
 hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
@@ -390,7 +418,7 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, co
     a.max_sw = dp->max_sw; a.shell_wb = dp->shell_wb; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
     a.w_slot = dp->w_slot; a.n_inner = dp->h.n_inner; a.ring = dp->h.ring_size;
     a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;
-    a.floor = p->stf_floor; a.noise_bias = p->noise_bias; a.amp = amp;
+    a.floor = p->stf_floor; a.noise_bias = p->noise_bias == 1; a.amp = amp;
     a.phasor = (double2 *)phasor;
     a.phase_method = p->phase_method; a.lsq_iters = p->lsq_iters;
     a.wcode = dp->wcode; a.side_off = dp->side_off; a.side_ent = (const uint2 *)dp->side_ent;
@@ -450,7 +478,7 @@ nvsm_status prepare_call(nvsm_context *ctx, const nvsm_params *p, const BurstIn 
     if ((s = get_plan(ctx, p, dp)) != NVSM_OK) return s;
     int64_t rec;
     make_table(p, &bi, 1, bt, &rec);
-    sizes_for(p->patch, *bt, rec, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, z);
+    sizes_for(p->patch, *bt, rec, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, z, p->noise_bias == 2);
     return NVSM_OK;
 }
 
@@ -501,6 +529,7 @@ nvsm_status nvsm_default_params(int32_t patch, nvsm_params *out) {
     out->stf_floor = 1e-6;
     out->lsq_iters = 10;
     out->reserved = 0;
+    out->photons_per_adu = 1.0;
     return NVSM_OK;
 }
 
@@ -523,7 +552,7 @@ nvsm_status nvsm_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t F, nvs
     int64_t rec;
     make_table(p, &bi, 1, &bt, &rec);
     Sizes z;
-    sizes_for(p->patch, bt, rec, nW, S, &z);
+    sizes_for(p->patch, bt, rec, nW, S, &z, p->noise_bias == 2);
     out->patches_y = bt.b[0].ny;
     out->patches_x = bt.b[0].nx;
     out->patches = z.P;
@@ -668,11 +697,11 @@ static void batch_groups(const nvsm_params *p, const BurstIn *bi, int n, int64_t
         int64_t rec;
         Sizes z;
         make_table(p, bi + i, 1, &bt, &rec);
-        sizes_for(p->patch, bt, rec, nW, S, &z);
+        sizes_for(p->patch, bt, rec, nW, S, &z, p->noise_bias == 2);
         size_t need = ws_rec(z);
         while (j < n && j - i < MAX_BURSTS) {
             make_table(p, bi + i, j + 1 - i, &bt, &rec);
-            sizes_for(p->patch, bt, rec, nW, S, &z);
+            sizes_for(p->patch, bt, rec, nW, S, &z, p->noise_bias == 2);
             if (ws_rec(z) > cap) break;
             need = ws_rec(z);
             ++j;
@@ -744,7 +773,7 @@ nvsm_status nvsm_reconstruct_batch(nvsm_context *ctx, const nvsm_params *p, nvsm
         int64_t rec;
         Sizes z;
         make_table(p, bi.data() + g.first, g.second - g.first, &bt, &rec);
-        sizes_for(p->patch, bt, rec, nW, S, &z);
+        sizes_for(p->patch, bt, rec, nW, S, &z, p->noise_bias == 2);
         hipError_t e = run_reconstruct(ctx, dp, p, bt, z, dtype, (char *)workspace, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "batch launch");
     }
@@ -831,6 +860,7 @@ nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t
     if (!state_bytes || !ws_bytes) return NVSM_ERR_INVALID_ARG;
     nvsm_status s = check_params(p, &msg);
     if (s != NVSM_OK) return s;
+    if (p->noise_bias == 2) return NVSM_ERR_NOT_IMPLEMENTED;
     if ((s = check_shape(p, H, W, group_frames, &msg)) != NVSM_OK) return s;
     HostPlan h;
     try {
@@ -853,7 +883,7 @@ nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t
     int64_t rec;
     make_table(p, &bi, 1, &bt, &rec);
     Sizes z;
-    sizes_for(p->patch, bt, rec, (int64_t)h.W.size() / 2, h.s_count, &z);
+    sizes_for(p->patch, bt, rec, (int64_t)h.W.size() / 2, h.s_count, &z, p->noise_bias == 2);
     StreamSizes ss;
     stream_sizes(p->patch, bt.patches, (int64_t)h.W.size() / 2, h.s_count, lane_terms, ws_acc(z), &ss);
     *state_bytes = ss.state();
@@ -866,13 +896,15 @@ static nvsm_status stream_prep(nvsm_context *ctx, const nvsm_params *p, int32_t 
     std::string msg;
     nvsm_status s = check_params(p, &msg);
     if (s != NVSM_OK) return fail(ctx, s, msg);
+    if (p->noise_bias == 2)
+        return fail(ctx, NVSM_ERR_NOT_IMPLEMENTED, "the streaming calls do not carry the photon-noise terms");
     if ((s = check_shape(p, H, W, G, &msg)) != NVSM_OK) return fail(ctx, s, msg);
     if ((s = get_plan(ctx, p, dp)) != NVSM_OK) return s;
     BurstIn bi;
     bi.F = G; bi.H = H; bi.W = W; bi.pitch = W;
     int64_t rec;
     make_table(p, &bi, 1, bt, &rec);
-    sizes_for(p->patch, *bt, rec, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, z);
+    sizes_for(p->patch, *bt, rec, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, z, p->noise_bias == 2);
     const int64_t lane_terms = (int64_t)(*dp)->h.n_items * BS_WAVES * (*dp)->h.slots * 64;
     stream_sizes(p->patch, bt->patches, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, lane_terms, ws_acc(*z),
                  ss);

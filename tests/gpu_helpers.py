@@ -47,7 +47,7 @@ def to_device(fr):
 def oparams(p):
     return oracle.Params(patch=p.patch, stride=p.stride, u_cut=p.u_cut, v_radius=p.v_radius,
                          window=p.window, noise_bias=p.noise_bias, filter=p.filter, stf_floor=p.stf_floor,
-                         phase_method=p.phase_method, lsq_iters=p.lsq_iters)
+                         phase_method=p.phase_method, lsq_iters=p.lsq_iters, photons_per_adu=p.photons_per_adu)
 
 
 def cube(frames, p, k):

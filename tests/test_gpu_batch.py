@@ -100,6 +100,23 @@ def test_batch_equals_alone(torch_cuda, bursts):
             assert same
 
 
+def test_batch_photon_noise_equals_alone(torch_cuda, bursts):
+    """With the photon-noise terms (noise_bias 2) as well."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    p = _params()
+    p.noise_bias = 2
+    p.photons_per_adu = synth.CONFIGS["burst1024"].photons / 2048.0
+    ref = _alone(torch, p, bursts)
+    _, ws_all = nv.nvsm_batch_plan(p, [tuple(d.shape) for d, _ in bursts])
+    got = _batch(torch, p, bursts, ws_all)
+    for i, (g, r) in enumerate(zip(got, ref)):
+        same = torch.equal(g, r)
+        say(f"[batch photon] burst {i} identical={same}")
+        assert torch.isfinite(g).all()
+        assert same
+
+
 def test_batch_workspace_errors(torch_cuda, bursts):
     import paper_1701_00581_amd as nv
     torch = torch_cuda

@@ -384,3 +384,79 @@ def test_single64_lsq_whole_path(torch_cuda):
     say(f"[single64 lsq] phase rms {rms:.2e} max {mx:.2e} mosaic {merr:.2e}")
     assert rms <= PHASE_RMS_TOL
     assert merr <= MOSAIC_TOL
+
+
+def _photon_burst(photons, F, H, W):
+    """The 1024 burst's scene at a low photon level (12-bit frames, gain
+    photons / 2048 photons per unit), so the noise terms are large."""
+    import dataclasses
+    import synth
+    cfg = dataclasses.replace(synth.CONFIGS["burst1024"], photons=float(photons), index=91)
+    return np.ascontiguousarray(synth.make_burst(cfg, frames=F)[:, :H, :W]), photons / 2048.0
+
+
+def test_photon_noise_accumulate(torch_cuda):
+    """noise_bias 2 on a 250x300 crop, 37 frames, 40 photons per pixel:
+    corrected power spectrum and bispectrum against the oracle's, and the
+    correction itself far above the tolerance."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case photon noise: burst1024 scene at 40 photons/px, crop 250x300 F=37, N=128, R=10")
+    fr, gain = _photon_burst(40, 37, 250, 300)
+    p = nv.default_params(128, v_radius=10, noise_bias=2, photons_per_adu=gain)
+    s = _session(p, 250, 300, 37)
+    s.accumulate(to_device(fr))
+    torch.cuda.synchronize()
+    op = oparams(p)
+    op0 = oparams(nv.default_params(128, v_radius=10))
+    S = oracle.bispectrum_set(p.u_cut, p.v_radius)[1]
+    P = s.power.cpu().numpy()
+    B = as_complex(s.bispec)
+    for k in (0, 6, 11):
+        c = cube(fr, p, k)
+        acc = oracle.accumulate_patch(c, op, S)
+        raw = oracle.accumulate_patch(c, op0, S)
+        I, _ = oracle.patch_spectra(c, op.window)
+        A = abs_bispectrum(I, S)
+        perr = np.linalg.norm(P[k] - acc["P"]) / np.linalg.norm(acc["P"])
+        nerr, aerr = bispec_errors(B[k], acc["B"], A)
+        moved = np.max(np.abs(acc["B"] - raw["B"]) / A)
+        pmoved = np.linalg.norm(acc["P"] - raw["P"]) / np.linalg.norm(raw["P"])
+        say(f"[photon] patch {k}: P {perr:.2e} B norm {nerr:.2e} B/A max {aerr:.2e} "
+            f"(correction: B/A up to {moved:.2e}, P by {pmoved:.2e})")
+        assert perr <= POWER_TOL
+        assert nerr <= BISPEC_TOL and aerr <= BISPEC_TOL
+        assert moved > 100 * BISPEC_TOL and pmoved > 100 * POWER_TOL
+
+
+def test_photon_noise_whole_path(torch_cuda):
+    """noise_bias 2 through nvsm_reconstruct on a 160x192 crop (N = 64,
+    R = 8, 20 patches, 24 frames at 400 photons per pixel) against the
+    oracle's reconstruction with the same model.  (Far fewer photons make
+    the corrected power of most high frequencies a small difference of
+    large numbers, which the division by the transfer function then
+    magnifies: the mosaic is no longer a stable function of the inputs.)"""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case photon noise whole path: 160x192 F=24, N=64, R=8, 400 photons/px")
+    fr, gain = _photon_burst(400, 24, 160, 192)
+    p = nv.default_params(64, v_radius=8, noise_bias=2, photons_per_adu=gain, filter=1)
+    import synth
+    st = synth.stf_table(synth.CONFIGS["burst1024"], screens=60, patch=64)
+    info = nv.nvsm_plan(p, 160, 192, 24)
+    ctx = nv.nvsm_create(0)
+    try:
+        img = torch.empty((160, 192), device="cuda")
+        nv.nvsm_reconstruct(ctx, p, to_device(fr), torch.from_numpy(st).cuda(), img,
+                            torch.empty(info.ws_reconstruct, dtype=torch.uint8, device="cuda"))
+        torch.cuda.synchronize()
+    finally:
+        nv.nvsm_destroy(ctx)
+    ref = oracle.reconstruct(fr, oparams(p), st)["image"]
+    ref0 = oracle.reconstruct(fr, oparams(nv.default_params(64, v_radius=8, filter=1)), st)["image"]
+    g = img.cpu().numpy()
+    err = np.linalg.norm(g - ref) / np.linalg.norm(ref - ref.mean())
+    moved = np.linalg.norm(ref0 - ref) / np.linalg.norm(ref - ref.mean())
+    say(f"[photon path] mosaic vs oracle {err:.2e} (the correction moved the image by {moved:.2e})")
+    assert err <= MOSAIC_TOL
+    assert moved > 10 * MOSAIC_TOL

@@ -82,6 +82,21 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_OK
     p.lsq_iters = 0
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG
+    # photon-noise model: a positive finite gain; larger workspaces; not in the streaming calls
+    p = nv.default_params(128)
+    assert p.photons_per_adu == 1.0
+    assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_OK
+    plain = (info.ws_accumulate, info.ws_reconstruct)
+    p.noise_bias = 2
+    assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_OK
+    assert info.ws_accumulate > plain[0] and info.ws_reconstruct > plain[1]
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        p.photons_per_adu = bad
+        assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG
+    p.photons_per_adu = 4.0
+    with pytest.raises(nv.NvsmError) as e:
+        nv.nvsm_stream_plan(p, 1024, 1024, 10)
+    assert e.value.status == _lib.NVSM_ERR_NOT_IMPLEMENTED
     p = nv.default_params(128)
     assert L.nvsm_plan(ctypes.byref(p), 100, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 0, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
