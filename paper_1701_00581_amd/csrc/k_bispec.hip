@@ -92,7 +92,7 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(15 | (7 
 // past a chunk's real v hold a valid v of the item; their results are
 // dropped.  The frame's slot loop is one branch-free block, so its LDS reads
 // can be issued ahead.
-template <int N, int K, int NS, bool STREAM>
+template <int N, int K, int NS, int MODE>
 __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const float2 *__restrict__ spec,
                                             int64_t rec0, int F, int patch, int g, const int *__restrict__ it,
                                             const int *__restrict__ group_xy, const int *__restrict__ slot,
@@ -170,7 +170,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         s[k] = make_float2(0.f, 0.f);
         c[k] = make_float2(0.f, 0.f);
     }
-    if (STREAM && !acc.first) {
+    if (MODE == 1 && !acc.first) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             s[k] = acc.sum[ls0 + k * 64 + lane];
@@ -225,7 +225,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     }
     wait_vm<0>();
 
-    if (STREAM && acc.mode == 1) {
+    if (MODE == 1 && acc.mode == 1) {
         // keep the running (sum, compensation) for the next frame group
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -236,32 +236,55 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     }
     const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
     float2 *bo = bispec + (size_t)patch * s_count;
-    const float inv = STREAM ? acc.inv_total : invF;
+    const float inv = MODE == 1 ? acc.inv_total : invF;
+    if constexpr (MODE == 2) {
+        // photon-noise terms: B -= C(w) + conj C(v) + conj C(w - v) - 2T,
+        // C of the patch in the record layout of the spectra (the slot
+        // table gives v's record index; w - v lies within the record's rows)
+        // (w's row and column come from its record index, which stays live)
+        const float2 *Cp = acc.noise_c + (size_t)patch * FS;
+        const float t2 = 2.0f * acc.noise_t[(size_t)patch * 2 + 1];
+        const int wi = wo / (int)sizeof(float2);
+        // the means first, so the compensation registers are free for the loads
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const int o = oi[k * 64];
-        if (o >= 0) bo[o] = make_float2((s[k].x - c[k].x) * inv, (s[k].y - c[k].y) * inv);
+        for (int k = 0; k < NS; ++k) s[k] = make_float2((s[k].x - c[k].x) * inv, (s[k].y - c[k].y) * inv);
+        const float2 c_w = Cp[wi];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int vo = sl[2 * k + 1];
+            const float2 c_v = Cp[vo];
+            const float2 c_d = Cp[(wi / N - vo / N + SPEC_NEG_ROWS) * N + ((wi - vo) & (N - 1))];
+            const int o = oi[k * 64];
+            if (o >= 0)
+                bo[o] = make_float2(s[k].x - (c_w.x + c_v.x + c_d.x - t2), s[k].y - (c_w.y - c_v.y - c_d.y));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int o = oi[k * 64];
+            if (o >= 0) bo[o] = make_float2((s[k].x - c[k].x) * inv, (s[k].y - c[k].y) * inv);
+        }
     }
 }
 
 // Runs the item with its slot count (one of 4, 8, ..., Q * 4).
-template <int N, int K, int Q, bool STREAM>
+template <int N, int K, int Q, int MODE>
 __device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *lds1, const float2 *spec,
                                                 int64_t rec0, int F, int patch, int g, const int *it, const int *group_xy,
                                                 const int *slot, const int *out_idx, float2 *bispec,
                                                 int64_t s_count, float invF, const AccState &acc) {
     if constexpr (Q > 0) {
         if (nq == Q)
-            bispec_item<N, K, 4 * Q, STREAM>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
+            bispec_item<N, K, 4 * Q, MODE>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
                                      invF, acc);
         else
-            bispec_dispatch<N, K, Q - 1, STREAM>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
+            bispec_dispatch<N, K, Q - 1, MODE>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
                                          s_count, invF, acc);
     }
 }
 
 // Item L of the launch: (patch, work item) = (L / n_items, L % n_items).
-template <int N, int K, bool STREAM>
+template <int N, int K, int MODE>
 __device__ __forceinline__ void bispec_one(int L, float2 *lds0, float2 *lds1, const BurstTable &bt,
                                            const float2 *spec, int n_items, const int *items, const int *group_xy,
                                            const int *slot, const int *out_idx, float2 *bispec, int64_t s_count,
@@ -273,7 +296,7 @@ __device__ __forceinline__ void bispec_one(int L, float2 *lds0, float2 *lds1, co
     const float invF = 1.0f / (float)F;
     const int *it = items + g * BS_ITEM_INTS;
     const int nq = __builtin_amdgcn_readfirstlane(it[8]) >> 2;   // the item's slots per wave / 4
-    bispec_dispatch<N, K, K / 4, STREAM>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
+    bispec_dispatch<N, K, K / 4, MODE>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
                                  s_count, invF, acc);
 }
 
@@ -296,12 +319,13 @@ __device__ __forceinline__ int item_at(const BurstTable &bt, int o, int n_items)
     return o;                                  // not reached: o < patches * n_items
 }
 
-// One workgroup per item.  STREAM: the launch adds a frame group to the
-// running sums of acc (modes 1 and 2) instead of writing the mean of all
-// frames (mode 0); a separate instantiation, so that the plain form carries
-// none of its registers.
-template <int N, int K, bool STREAM>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec(
+// One workgroup per item.  MODE 0 writes the mean of all frames; MODE 1
+// adds a frame group to the running sums of acc (acc.mode 1 and 2); MODE 2
+// writes the mean less the photon-noise terms of acc.noise_c/noise_t.  Each
+// is a separate instantiation, so that the plain form carries none of the
+// others' registers.
+template <int N, int K, int MODE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? (MODE == 2 ? 4 : 3) : 2))) void k_bispec(
     const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
     const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
     float2 *__restrict__ bispec, int64_t s_count, const AccState acc) {
@@ -309,7 +333,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
     // the other
     __shared__ float2 lds0[Region<K>::SZ];
     __shared__ float2 lds1[Region<K>::SZ];
-    bispec_one<N, K, STREAM>(item_at(bt, xcd_remap(blockIdx.x, total), n_items), lds0, lds1, bt, spec, n_items, items,
+    bispec_one<N, K, MODE>(item_at(bt, xcd_remap(blockIdx.x, total), n_items), lds0, lds1, bt, spec, n_items, items,
                      group_xy, slot, out_idx, bispec, s_count, acc);
 }
 
@@ -321,7 +345,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
 // first, then helps the others.  queue[8] counts the items taken from each
 // range and must be zero at launch.  Every workgroup ends after finding all
 // 8 ranges exhausted.
-template <int N, int K, bool STREAM>
+template <int N, int K, int MODE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec_queue(
     const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
     const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
@@ -340,7 +364,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 
             __syncthreads();
             const int i = __builtin_amdgcn_readfirstlane(next);
             if (i >= cnt) break;
-            bispec_one<N, K, STREAM>(item_at(bt, beg + i, n_items), lds0, lds1, bt, spec, n_items, items, group_xy, slot,
+            bispec_one<N, K, MODE>(item_at(bt, beg + i, n_items), lds0, lds1, bt, spec, n_items, items, group_xy, slot,
                              out_idx, bispec, s_count, acc);
         }
     }
@@ -350,19 +374,19 @@ __global__ void k_queue_reset(int *queue) {
     if (threadIdx.x < 8) queue[threadIdx.x] = 0;
 }
 
-template <int N, int K, bool STREAM>
+template <int N, int K, int MODE>
 hipError_t launch_bispec_t(const BispecArgs &a, int total, hipStream_t st) {
     if (a.form == 0) {
-        hipLaunchKernelGGL((k_bispec<N, K, STREAM>), dim3(total), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
+        hipLaunchKernelGGL((k_bispec<N, K, MODE>), dim3(total), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
                            a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, a.acc);
         return hipGetLastError();
     }
     if (!a.queue) return hipErrorInvalidValue;
-    static int resident[2][2] = {{0, 0}, {0, 0}};   // workgroups per CU, per slot count and form
-    int &per_cu = resident[K == 16 ? 0 : 1][STREAM ? 1 : 0];
+    static int resident[2][3] = {{0, 0, 0}, {0, 0, 0}};   // workgroups per CU, per slot count and mode
+    int &per_cu = resident[K == 16 ? 0 : 1][MODE];
     if (per_cu == 0) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_bispec_queue<N, K, STREAM>, NT, 0) != hipSuccess || n < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_bispec_queue<N, K, MODE>, NT, 0) != hipSuccess || n < 1)
             n = 1;
         per_cu = n;
     }
@@ -373,7 +397,7 @@ hipError_t launch_bispec_t(const BispecArgs &a, int total, hipStream_t st) {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, a.queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_bispec_queue<N, K, STREAM>), dim3(grid), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
+    hipLaunchKernelGGL((k_bispec_queue<N, K, MODE>), dim3(grid), dim3(NT), 0, st, a.bt, a.spectra, a.n_items, total,
                        a.items, a.group_xy, a.slot_v, a.out_idx, a.bispec, a.s_count, a.acc, a.queue);
     return hipGetLastError();
 }
@@ -386,13 +410,20 @@ hipError_t launch_bispec(const BispecArgs &a, hipStream_t st) {
     if (total64 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const int total = (int)total64;
     if (a.acc.mode < 0 || a.acc.mode > 2) return hipErrorInvalidValue;
+    if (a.acc.mode != 0 && a.acc.noise_c) return hipErrorInvalidValue;   // no photon terms when streaming
     if (a.acc.mode != 0) {
-        if (a.slots == 16) return a.N == 128 ? launch_bispec_t<128, 16, true>(a, total, st) : launch_bispec_t<64, 16, true>(a, total, st);
-        if (a.slots == 24) return a.N == 128 ? launch_bispec_t<128, 24, true>(a, total, st) : launch_bispec_t<64, 24, true>(a, total, st);
+        if (a.slots == 16) return a.N == 128 ? launch_bispec_t<128, 16, 1>(a, total, st) : launch_bispec_t<64, 16, 1>(a, total, st);
+        if (a.slots == 24) return a.N == 128 ? launch_bispec_t<128, 24, 1>(a, total, st) : launch_bispec_t<64, 24, 1>(a, total, st);
         return hipErrorInvalidValue;
     }
-    if (a.slots == 16) return a.N == 128 ? launch_bispec_t<128, 16, false>(a, total, st) : launch_bispec_t<64, 16, false>(a, total, st);
-    if (a.slots == 24) return a.N == 128 ? launch_bispec_t<128, 24, false>(a, total, st) : launch_bispec_t<64, 24, false>(a, total, st);
+    if (a.acc.noise_c) {
+        if (!a.acc.noise_t) return hipErrorInvalidValue;
+        if (a.slots == 16) return a.N == 128 ? launch_bispec_t<128, 16, 2>(a, total, st) : launch_bispec_t<64, 16, 2>(a, total, st);
+        if (a.slots == 24) return a.N == 128 ? launch_bispec_t<128, 24, 2>(a, total, st) : launch_bispec_t<64, 24, 2>(a, total, st);
+        return hipErrorInvalidValue;
+    }
+    if (a.slots == 16) return a.N == 128 ? launch_bispec_t<128, 16, 0>(a, total, st) : launch_bispec_t<64, 16, 0>(a, total, st);
+    if (a.slots == 24) return a.N == 128 ? launch_bispec_t<128, 24, 0>(a, total, st) : launch_bispec_t<64, 24, 0>(a, total, st);
     return hipErrorInvalidValue;
 }
 

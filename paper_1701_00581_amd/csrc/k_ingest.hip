@@ -429,14 +429,16 @@ __global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, i
 }
 
 // Sums the frame groups of k_noise per patch (compensated), divides by F,
-// keeps C on W, and subtracts q0 from the patch's power spectrum.
+// writes C in the record layout of the spectra (rows -16 .. N/2-1, the rows
+// below 0 as C(u) = conj C(-u)), and subtracts q0 from the patch's power
+// spectrum.
 template <int N>
 __global__ __launch_bounds__(NT) void k_noise_finalize(const BurstTable bt, int chunk_frames,
                                                        const float2 *__restrict__ cpart,
-                                                       const float *__restrict__ spart, int nW,
-                                                       const int *__restrict__ Wxy, float *__restrict__ power,
-                                                       float2 *__restrict__ cw, float *__restrict__ nbar) {
+                                                       const float *__restrict__ spart, float *__restrict__ power,
+                                                       float2 *__restrict__ cgrid, float *__restrict__ nbar) {
     constexpr int HALF = N / 2, NP = (HALF + 1) * N;
+    constexpr int FS = SpecRows<N>::FS;
     const int patch = blockIdx.x;
     const int b = burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; });
     const BurstDesc &bd = bt.b[b];
@@ -456,56 +458,21 @@ __global__ __launch_bounds__(NT) void k_noise_finalize(const BurstTable bt, int 
         nbar[(size_t)patch * 2 + 1] = t3;
     }
     const float2 *cp = cpart + wg0 * NP;
-    for (int i = threadIdx.x; i < nW; i += NT) {
-        const int wx = Wxy[2 * i], wy = Wxy[2 * i + 1];          // 0 <= wy < N/2
-        const int j = wy * N + (wx & (N - 1));
+    for (int i = threadIdx.x; i < FS; i += NT) {
+        const int y = i / N - SPEC_NEG_ROWS, x = i % N;
+        const bool mirror = y < 0;
+        const int j = mirror ? (-y) * N + ((N - x) & (N - 1)) : y * N + x;
         float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f;
         for (int k = 0; k < nchunks; ++k) {
             const float2 v = cp[(size_t)k * NP + j];
             kahan_add(sx, cx, v.x);
             kahan_add(sy, cy, v.y);
         }
-        cw[(size_t)patch * nW + i] = make_float2((sx - cx) * invF, (sy - cy) * invF);
+        const float im = (sy - cy) * invF;
+        cgrid[(size_t)patch * FS + i] = make_float2((sx - cx) * invF, mirror ? -im : im);
     }
     float *pw = power + (size_t)patch * N * N;
     for (int j = threadIdx.x; j < N * N; j += NT) pw[j] -= q0;
-}
-
-// B(w, v) -= C(w) + conj C(w - v) + conj C(v) - 2T for the samples of DEB_W
-// consecutive w of one patch (grid: w blocks x patches).  The codes give
-// the W index of w - v and v and whether the sample holds the conjugate
-// (C(-u) = conj C(u)); each thread finds the w of its sample by bisection
-// of the block's sample offsets.
-constexpr int DEB_W = 64;
-__global__ __launch_bounds__(NT) void k_debias(int nW, const int *__restrict__ woff,
-                                               const unsigned *__restrict__ wcode, const float2 *__restrict__ cw,
-                                               const float *__restrict__ nbar, float2 *__restrict__ bispec,
-                                               int64_t s_count) {
-    __shared__ int off[DEB_W + 1];
-    const int patch = blockIdx.y;
-    const int w0 = blockIdx.x * DEB_W, n = min(nW, w0 + DEB_W) - w0;
-    for (int i = threadIdx.x; i <= n; i += NT) off[i] = woff[w0 + i];
-    __syncthreads();
-    const float2 *C = cw + (size_t)patch * nW;
-    const float t2 = 2.0f * nbar[(size_t)patch * 2 + 1];
-    float2 *B = bispec + (size_t)patch * s_count;
-    for (int t = off[0] + threadIdx.x; t < off[n]; t += NT) {
-        int lo = 0, hi = n;                                  // off[lo] <= t < off[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (off[mid] <= t) lo = mid; else hi = mid;
-        }
-        const unsigned cd = wcode[t];
-        const float2 c_w = C[w0 + lo];
-        float2 ca = C[(cd >> 16) & 0x7fffu];
-        if (cd >> 31) ca.y = -ca.y;
-        float2 cb = C[cd & 0x7fffu];
-        if (cd & 0x8000u) cb.y = -cb.y;
-        float2 v = B[t];
-        v.x -= c_w.x + ca.x + cb.x - t2;
-        v.y -= c_w.y - ca.y - cb.y;
-        B[t] = v;
-    }
 }
 
 template <int N, typename T>
@@ -522,7 +489,7 @@ hipError_t launch_noise_t(const NoiseArgs &na, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_noise_finalize<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames, na.cpart,
-                       na.spart, na.nW, na.Wxy, a.power, na.cw, na.nbar);
+                       na.spart, a.power, na.cgrid, na.nbar);
     return hipGetLastError();
 }
 
@@ -544,17 +511,8 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
 hipError_t launch_noise(const NoiseArgs &na, hipStream_t st) {
     const IngestArgs &a = na.in;
     if (a.bt.patches == 0) return hipSuccess;
-    if (na.nW < 1 || na.nW > 0x8000) return hipErrorInvalidValue;
     if (a.N == 128) return a.f32 ? launch_noise_t<128, float>(na, st) : launch_noise_t<128, uint16_t>(na, st);
     return a.f32 ? launch_noise_t<64, float>(na, st) : launch_noise_t<64, uint16_t>(na, st);
-}
-
-hipError_t launch_debias(const NoiseArgs &na, hipStream_t st) {
-    if (na.in.bt.patches == 0) return hipSuccess;
-    if (na.nW < 1 || na.nW > 0x8000 || na.in.bt.patches > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_debias, dim3((na.nW + DEB_W - 1) / DEB_W, na.in.bt.patches), dim3(NT), 0, st, na.nW,
-                       na.woff, na.wcode, na.cw, na.nbar, na.bispec, na.s_count);
-    return hipGetLastError();
 }
 
 hipError_t launch_ingest(const IngestArgs &a, hipStream_t st) {

@@ -223,91 +223,139 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
 }
 
 // Least-squares refinement of the phasors of one patch per workgroup (FP64).
-// The phasor table of the patch sits in LDS; each step computes, for every
-// w but the two seeds, g(w) = the sum over the samples holding w of the
-// derivative of the closure agreement by conj e(w):
-//   w as the sample's w:   e(w - v) e(v) conj B    (samples woff[w] ..)
-//   w as the side w - v:   conj e(v) e(w') B       (side entries, w' the
-//   w as the side v:       conj e(w' - v) e(w') B   sample's w)
-// conjugated where the sample holds -w, and the new phasor
-// e'(w) = unit(unit(g) + e(w)).  All g use the previous step's table
-// (Jacobi): wave j takes w = 2 + j + 8 m (m = 0, 1, ...), its lanes split the
-// samples, a wave sum combines them, and lane m mod 64 keeps e'(w) in
-// register slot m / 64 until every wave is done; then the table is
-// rewritten between two barriers.
+// The phasor table of the patch sits in LDS.  Each step computes, for every
+// u but the two seeds, g(u) = the sum over the samples holding u of the
+// derivative of the closure agreement by conj e(u):
+//   u as the sample's w:   e(w - v) e(v) conj B
+//   u as the side w - v:   conj e(v) e(w) B
+//   u as the side v:       conj e(w - v) e(w) B
+// conjugated where the sample holds -u, and the new phasor
+// e'(u) = unit(unit(g) + e(u)), all from the previous step's table (Jacobi).
+// The samples are read in storage order (one w per wave, its samples over
+// the lanes), so B streams contiguously; each contribution is added to the
+// accumulator of its target in LDS.  The accumulators of all targets do not
+// fit beside the table, so a step makes two passes, each for half of the
+// targets.  The adds are 64-bit fixed point (scale 2^60 / sum |Re B| + |Im B|
+// of the patch, which bounds every |g| below 2^62): integer sums do not
+// depend on the order of the adds, so the result is reproducible bit for
+// bit.  Thread i keeps e'(u) for u = i + 1024 m in registers until both
+// passes are done; then the table is rewritten between two barriers.
 constexpr int LSQ_MAXW = 6240;
-constexpr int LSQ_SLOTS = ((LSQ_MAXW - 2) / NWAVE + 63) / 64;
+constexpr int LSQ_HALF = LSQ_MAXW / 2;
+constexpr int LSQ_NT = 1024;                 // 16 waves: the one workgroup a CU holds hides latency
+constexpr int LSQ_NWAVE = LSQ_NT / 64;
+constexpr int LSQ_SLOTS = (LSQ_MAXW + LSQ_NT - 1) / LSQ_NT;
+constexpr int LSQ_UNROLL = 4;
 
-__global__ __launch_bounds__(NT) void k_lsq(int nW, int iters, const int *__restrict__ woff,
-                                            const unsigned *__restrict__ code, const int *__restrict__ side_off,
-                                            const uint2 *__restrict__ side_ent, const float2 *__restrict__ bispec,
+__global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int iters, const int *__restrict__ woff,
+                                            const unsigned *__restrict__ code, const float2 *__restrict__ bispec,
                                             int64_t s_count, double2 *__restrict__ phasor) {
     __shared__ double2 e[LSQ_MAXW];
+    __shared__ unsigned long long acc[2 * LSQ_HALF];
+    __shared__ double red[LSQ_NWAVE];
     const int patch = blockIdx.x;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     double2 *ph = phasor + (size_t)patch * nW;
     const float2 *B = bispec + (size_t)patch * s_count;
-    for (int i = tid; i < nW; i += NT) e[i] = ph[i];
+    for (int i = tid; i < nW; i += LSQ_NT) e[i] = ph[i];
+    // fixed-point scale from sum |Re B| + |Im B| (fixed summation order)
+    double s1 = 0.0;
+    for (int64_t t = tid; t < s_count; t += LSQ_NT) s1 += fabs((double)B[t].x) + fabs((double)B[t].y);
+    s1 = wave_sum_d(s1);
+    if (lane == 0) red[wave] = s1;
     __syncthreads();
+    s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < LSQ_NWAVE; ++k) s1 += red[k];
+    if (!(s1 > 0.0) || !isfinite(s1)) return;          // no usable samples: the phasors stay
+    const double scale = 0x1p60 / s1, inv_scale = s1 * 0x1p-60;
     auto get = [&](unsigned c) __attribute__((always_inline)) {     // e of a code (index | conj << 15)
         double2 v = e[c & 0x7fffu];
         if (c & 0x8000u) v.y = -v.y;
         return v;
     };
+    auto add = [&](unsigned k, double x, double y) __attribute__((always_inline)) {
+        atomicAdd(&acc[2 * k], (unsigned long long)__double2ll_rn(x * scale));
+        atomicAdd(&acc[2 * k + 1], (unsigned long long)__double2ll_rn(y * scale));
+    };
+    const int half = (nW + 1) / 2;
     for (int it = 0; it < iters; ++it) {
         double2 res[LSQ_SLOTS];
-#pragma unroll
-        for (int j = 0; j < LSQ_SLOTS; ++j) {
-            res[j] = make_double2(1.0, 0.0);
-            for (int l = 0; l < 64; ++l) {
-                const int w = 2 + wave + NWAVE * (64 * j + l);
-                if (w >= nW) break;
-                double gx = 0.0, gy = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int lo = pass ? half : 0, n = pass ? nW - half : half;     // targets [lo, lo + n)
+            for (int i = tid; i < 2 * n; i += LSQ_NT) acc[i] = 0ull;
+            __syncthreads();
+            for (int w = wave; w < nW; w += LSQ_NWAVE) {
                 const int t0 = woff[w], t1 = woff[w + 1];
-                for (int t = t0 + lane; t < t1; t += 64) {
-                    const unsigned cd = code[t];
-                    const double2 a = get(cd >> 16), b = get(cd & 0xffffu);
-                    const double bx = (double)B[t].x, by = (double)B[t].y;
-                    const double px = a.x * b.x - a.y * b.y, py = a.x * b.y + a.y * b.x;
-                    gx += px * bx + py * by;                   // (a b) conj(B)
-                    gy += py * bx - px * by;
+                const double2 cw = e[w];
+                const bool own = (unsigned)(w - lo) < (unsigned)n;
+                double gx = 0.0, gy = 0.0;
+                for (int tb = t0; tb < t1; tb += 64 * LSQ_UNROLL) {
+                    unsigned cd[LSQ_UNROLL];
+                    float2 bb[LSQ_UNROLL];
+#pragma unroll
+                    for (int k = 0; k < LSQ_UNROLL; ++k) {
+                        const int t = tb + 64 * k + lane;
+                        cd[k] = t < t1 ? code[t] : 0u;
+                        bb[k] = t < t1 ? B[t] : make_float2(0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int k = 0; k < LSQ_UNROLL; ++k) {
+                        if (tb + 64 * k + lane >= t1) continue;
+                        const double2 a = get(cd[k] >> 16), b = get(cd[k] & 0xffffu);
+                        const double bx = (double)bb[k].x, by = (double)bb[k].y;
+                        if (own) {                                  // (a b) conj(B)
+                            const double px = a.x * b.x - a.y * b.y, py = a.x * b.y + a.y * b.x;
+                            gx += px * bx + py * by;
+                            gy += py * bx - px * by;
+                        }
+                        const unsigned ia = ((cd[k] >> 16) & 0x7fffu) - lo, ib = (cd[k] & 0x7fffu) - lo;
+                        if (ia < (unsigned)n) {                     // conj(b) e(w) B
+                            const double qx = b.x * cw.x + b.y * cw.y, qy = b.x * cw.y - b.y * cw.x;
+                            const double ry = qx * by + qy * bx;
+                            add(ia, qx * bx - qy * by, (cd[k] >> 31) ? -ry : ry);
+                        }
+                        if (ib < (unsigned)n) {                     // conj(a) e(w) B
+                            const double qx = a.x * cw.x + a.y * cw.y, qy = a.x * cw.y - a.y * cw.x;
+                            const double ry = qx * by + qy * bx;
+                            add(ib, qx * bx - qy * by, (cd[k] & 0x8000u) ? -ry : ry);
+                        }
+                    }
                 }
-                const int k0 = side_off[w], k1 = side_off[w + 1];
-                for (int k = k0 + lane; k < k1; k += 64) {
-                    const uint2 en = side_ent[k];
-                    const unsigned t = en.x & 0x3fffffffu;
-                    const unsigned cd = code[t];
-                    // the other side of the sample: v when w is the side w - v
-                    const double2 o = get((en.x >> 30) & 1u ? (cd >> 16) : (cd & 0xffffu));
-                    const double2 c = e[en.y];
-                    const double bx = (double)B[t].x, by = (double)B[t].y;
-                    const double qx = o.x * c.x + o.y * c.y, qy = o.x * c.y - o.y * c.x;   // conj(o) c
-                    const double rx = qx * bx - qy * by, ry = qx * by + qy * bx;           // times B
-                    gx += rx;
-                    gy += (en.x >> 31) ? -ry : ry;             // conjugated when the sample holds -w
+                if (own) {
+                    gx = wave_sum_d(gx);
+                    gy = wave_sum_d(gy);
+                    if (lane == 0) add((unsigned)(w - lo), gx, gy);
                 }
-                gx = wave_sum_d(gx);
-                gy = wave_sum_d(gy);
-                const double2 old = e[w];
-                double2 nw = old;
-                const double m = sqrt(gx * gx + gy * gy);
-                if (m > 0.0) {
-                    const double sx = gx / m + old.x, sy = gy / m + old.y;
-                    const double n = sqrt(sx * sx + sy * sy);
-                    if (n > 0.0) nw = make_double2(sx / n, sy / n);
-                }
-                if (lane == l) res[j] = nw;
             }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < LSQ_SLOTS; ++j) {
+                const int u = tid + LSQ_NT * j;
+                if (u >= 2 && (unsigned)(u - lo) < (unsigned)n) {
+                    const double gx = (double)(long long)acc[2 * (u - lo)] * inv_scale;
+                    const double gy = (double)(long long)acc[2 * (u - lo) + 1] * inv_scale;
+                    const double2 old = e[u];
+                    double2 nw = old;
+                    const double m = sqrt(gx * gx + gy * gy);
+                    if (m > 0.0) {
+                        const double sx = gx / m + old.x, sy = gy / m + old.y;
+                        const double r = sqrt(sx * sx + sy * sy);
+                        if (r > 0.0) nw = make_double2(sx / r, sy / r);
+                    }
+                    res[j] = nw;
+                }
+            }
+            __syncthreads();                               // accumulators read before the next pass clears them
         }
-        __syncthreads();                                   // every g read the old table
 #pragma unroll
         for (int j = 0; j < LSQ_SLOTS; ++j) {
-            const int w = 2 + wave + NWAVE * (64 * j + lane);
-            if (w < nW) {
-                e[w] = res[j];
-                if (it + 1 == iters) ph[w] = res[j];
+            const int u = tid + LSQ_NT * j;
+            if (u >= 2 && u < nW) {
+                e[u] = res[j];
+                if (it + 1 == iters) ph[u] = res[j];
             }
         }
         __syncthreads();
@@ -333,8 +381,8 @@ hipError_t launch_solve_n(const SolveArgs &a, hipStream_t st) {
 
 hipError_t launch_lsq(const SolveArgs &a, hipStream_t st) {
     if (a.nW > LSQ_MAXW || a.nW < 2 || a.lsq_iters < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lsq, dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.lsq_iters, a.woff, a.wcode, a.side_off,
-                       a.side_ent, a.bispec, a.s_count, a.phasor);
+    hipLaunchKernelGGL(k_lsq, dim3(a.bt.patches), dim3(LSQ_NT), 0, st, a.nW, a.lsq_iters, a.woff, a.wcode, a.bispec,
+                       a.s_count, a.phasor);
     return hipGetLastError();
 }
 

@@ -57,24 +57,18 @@ hipError_t launch_ingest(const IngestArgs &a, hipStream_t st);
 // Q = FFT2(t^2 p) / G, C(u) = conj I(u) Q(u), q0 = sum(t^2 p) / G,
 // T = sum(t^3 p) / G^2.  launch_noise accumulates their means over the
 // frames (the workgroups of the ingest grid, then one pass per patch that
-// keeps C on W and subtracts q0 from the power spectrum); launch_debias
-// subtracts C(w) + conj C(v) + conj C(w - v) - 2T from every bispectrum
-// sample in place.
+// writes C in the record layout of the spectra and subtracts q0 from the
+// power spectrum); the bispectrum launch then subtracts
+// C(w) + conj C(v) + conj C(w - v) - 2T as it writes each mean.
 struct NoiseArgs {
     IngestArgs in;                        // grid, frames, taper, power spectrum
     float inv_gain = 0.f;                 // 1 / G
     float2 *cpart = nullptr;              // [ingest wgs][N/2 + 1][N] sums of C over a frame group
     float *spart = nullptr;               // [ingest wgs][2] sums of q0 and T
-    float2 *cw = nullptr;                 // [P][nW] mean C on W
+    float2 *cgrid = nullptr;              // [P][N/2 + 16][N] mean C, record layout
     float *nbar = nullptr;                // [P][2] mean q0 and T
-    int nW = 0;
-    const int *Wxy = nullptr, *woff = nullptr;
-    const unsigned *wcode = nullptr;      // per sample: codes of w - v (high half) and v
-    float2 *bispec = nullptr;             // [P][s_count], corrected in place
-    int64_t s_count = 0;
 };
 hipError_t launch_noise(const NoiseArgs &a, hipStream_t st);
-hipError_t launch_debias(const NoiseArgs &a, hipStream_t st);
 
 // Zeroes bytes (a multiple of 16, 16-byte aligned) with a fill kernel.
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
@@ -85,10 +79,15 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 // kernel's lane order (coalesced), starting from zero when first.  mode 2:
 // as 1 for the last group, then writes the mean, (sum - comp) * inv_total,
 // to the bispectrum array in S order.
+// noise_c/noise_t (mode 0 only): photon-noise terms to subtract from the
+// mean, C per patch in the record layout of the spectra ([P][N/2 + 16][N])
+// and (q0, T) per patch (see NoiseArgs).
 struct AccState {
     float2 *sum = nullptr, *comp = nullptr;   // [P * n_items * 4 * slots * 64]
     int mode = 0, first = 0, n_items = 0;
     float inv_total = 0.f;
+    const float2 *noise_c = nullptr;
+    const float *noise_t = nullptr;
 };
 
 struct BispecArgs {
@@ -122,8 +121,6 @@ struct SolveArgs {
     // least-squares refinement (phase_method 1)
     int phase_method = 0, lsq_iters = 0;
     const unsigned *wcode = nullptr;      // sample codes with W indices
-    const int *side_off = nullptr;        // [|W| + 1]
-    const uint2 *side_ent = nullptr;      // [2 |S|] entries (see plan.hpp)
     SolveArgs() = default;
     SolveArgs(const SolveArgs &o, int method) : SolveArgs(o) { phase_method = method; }
 };

@@ -32,8 +32,7 @@ struct DevicePlan {
     std::vector<void *> bufs;
     int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr,
         *group_xy = nullptr, *slot = nullptr, *out_idx = nullptr;
-    unsigned *code = nullptr, *wcode = nullptr, *side_ent = nullptr;
-    int *side_off = nullptr;
+    unsigned *code = nullptr, *wcode = nullptr;
     float2 *twiddle = nullptr;
     float *hann = nullptr, *filt = nullptr;
     ~DevicePlan() {
@@ -166,7 +165,7 @@ void sizes_for(int N, const BurstTable &bt, int64_t records, int64_t nW, int64_t
     if (photon) {
         z->cpart = align_up((size_t)z->wgs * (N / 2 + 1) * N * 8);
         z->spart = align_up((size_t)z->wgs * 2 * 4);
-        z->cw = align_up((size_t)z->P * nW * 8);
+        z->cw = align_up((size_t)z->P * (N / 2 + 16) * N * 8);
         z->nbar = align_up((size_t)z->P * 2 * 4);
     }
 }
@@ -307,8 +306,6 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
         (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
         (s = upload(dp.get(), h.phase_slot_code, &dp->code, &msg)) ||
         (s = upload(dp.get(), h.phase_code, &dp->wcode, &msg)) ||
-        (s = upload(dp.get(), h.side_off, &dp->side_off, &msg)) ||
-        (s = upload(dp.get(), h.side_ent, &dp->side_ent, &msg)) ||
         (s = upload(dp.get(), h.items, &dp->items, &msg)) ||
         (s = upload(dp.get(), h.group_xy, &dp->group_xy, &msg)) ||
         (s = upload(dp.get(), h.slot_v, &dp->slot, &msg)) ||
@@ -387,10 +384,8 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
         na.inv_gain = (float)(1.0 / p->photons_per_adu);
         na.cpart = (float2 *)q; q += z.cpart;
         na.spart = (float *)q; q += z.spart;
-        na.cw = (float2 *)q; q += z.cw;
+        na.cgrid = (float2 *)q; q += z.cw;
         na.nbar = (float *)q;
-        na.nW = (int)z.nW; na.Wxy = dp->W; na.woff = dp->woff; na.wcode = dp->wcode;
-        na.bispec = (float2 *)bispec; na.s_count = z.S;
     }
     {
         StageTimer t(ctx, ST_INGEST, st);
@@ -404,10 +399,9 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
     b.slot_v = dp->slot; b.out_idx = dp->out_idx;
     b.bispec = (float2 *)bispec; b.s_count = z.S;
     b.form = choice_of(ctx, p).second; b.queue = ctx->queue;
+    if (p->noise_bias == 2) { b.acc.noise_c = na.cgrid; b.acc.noise_t = na.nbar; }
     StageTimer t(ctx, ST_BISPEC, st);
-    e = launch_bispec(b, st);
-    if (e == hipSuccess && p->noise_bias == 2) e = launch_debias(na, st);
-    return e;
+    return launch_bispec(b, st);
 }
 
 hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
@@ -421,7 +415,7 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, co
     a.floor = p->stf_floor; a.noise_bias = p->noise_bias == 1; a.amp = amp;
     a.phasor = (double2 *)phasor;
     a.phase_method = p->phase_method; a.lsq_iters = p->lsq_iters;
-    a.wcode = dp->wcode; a.side_off = dp->side_off; a.side_ent = (const uint2 *)dp->side_ent;
+    a.wcode = dp->wcode;
     StageTimer t(ctx, ST_SOLVE, st);
     return launch_solve(a, st);
 }

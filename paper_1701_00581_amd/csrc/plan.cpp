@@ -124,28 +124,8 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     pl->shell_wb.push_back(nW);
     pl->s_count = pl->woff[nW];
 
-    // sides of every sample, grouped by frequency
+    // sample indices are kept in 30 bits by the kernels' tables
     if (pl->s_count >= (int64_t)1 << 30) { *err = "bispectrum set too large"; return false; }
-    {
-        pl->side_off.assign(nW + 1, 0);
-        for (int i = 0; i < nW; ++i)
-            for (int32_t t = pl->woff[i]; t < pl->woff[i + 1]; ++t) {
-                ++pl->side_off[((pl->phase_code[t] >> 16) & 0x7fffu) + 1];
-                ++pl->side_off[(pl->phase_code[t] & 0x7fffu) + 1];
-            }
-        for (int i = 0; i < nW; ++i) pl->side_off[i + 1] += pl->side_off[i];
-        pl->side_ent.assign((size_t)pl->side_off[nW] * 2, 0);
-        std::vector<int32_t> fill(pl->side_off.begin(), pl->side_off.end() - 1);
-        for (int i = 0; i < nW; ++i)
-            for (int32_t t = pl->woff[i]; t < pl->woff[i + 1]; ++t)
-                for (int role = 0; role < 2; ++role) {
-                    const uint32_t c = role == 0 ? (pl->phase_code[t] >> 16) : (pl->phase_code[t] & 0xffffu);
-                    const int u = (int)(c & 0x7fffu);
-                    const int32_t k = fill[u]++;
-                    pl->side_ent[2 * (size_t)k] = (uint32_t)t | ((uint32_t)role << 30) | ((c >> 15) << 31);
-                    pl->side_ent[2 * (size_t)k + 1] = (uint32_t)i;
-                }
-    }
 
     // phasor window: inner entries |w| <= R, the rest in a ring; each
     // shell's lowest ring entry read comes from its sample codes

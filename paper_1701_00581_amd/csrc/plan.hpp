@@ -47,13 +47,6 @@ struct HostPlan {
     // (bits 0..14 index into W, bit 15 set = use the conjugate).
     std::vector<uint32_t> phase_code;
     int64_t s_count = 0;
-    // For the least-squares refinement: the samples in which each w is a
-    // side (w - v or v, either sign), side_off[w] .. side_off[w+1] into
-    // side_ent, two words per entry: sample index t | role << 30 (0: the
-    // side w - v, 1: the side v) | conj << 31 (the sample holds -w), then
-    // the W index of the sample's w.
-    std::vector<int32_t> side_off;
-    std::vector<uint32_t> side_ent;
     // Bispectrum work items.  items[g*12 + 0..11] = w group, region x0,
     // region y0, region width, region height, region points (width x
     // height), region row pitch in LDS, 0, then the slot count ns of each of
