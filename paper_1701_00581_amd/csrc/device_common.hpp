@@ -163,6 +163,18 @@ __device__ __forceinline__ float2 load_global_f2(gptr_c base, unsigned byte_off)
     const unsigned long long v = *(const __attribute__((address_space(1))) unsigned long long *)(base + byte_off);
     return make_float2(__uint_as_float((unsigned)v), __uint_as_float((unsigned)(v >> 32)));
 }
+// The same for stores.
+typedef __attribute__((address_space(1))) char *gptr_m;
+__device__ __forceinline__ gptr_m uniform_ptr_m(void *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (gptr_m)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ void store_global_f2(gptr_m base, unsigned byte_off, float2 v) {
+    *(__attribute__((address_space(1))) unsigned long long *)(base + byte_off) =
+        (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
+}
 
 // Workgroup id remapped so that consecutive logical ids stay on one XCD:
 // hardware dispatches workgroup b to XCD b % 8.

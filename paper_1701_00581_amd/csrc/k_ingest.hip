@@ -15,6 +15,9 @@ namespace nvsm {
 namespace {
 
 constexpr int NT = 256;
+// The transform kernels hold one workgroup per CU (the tile fills most of
+// LDS), so they run 8 waves to hide latency.
+constexpr int FT = 512;
 
 // Four consecutive pixels of a row, loaded as one vector when the layout
 // allows it (VEC), else one by one.
@@ -22,11 +25,21 @@ template <typename T, bool VEC> struct Quad;
 template <> struct Quad<uint16_t, true> {
     ushort4 v;
     __device__ void load(const uint16_t *p) { v = *(const ushort4 *)p; }
+    __device__ void load(gptr_c base, unsigned off) {
+        const unsigned long long u = *(const __attribute__((address_space(1))) unsigned long long *)(base + off);
+        v = make_ushort4((unsigned short)u, (unsigned short)(u >> 16), (unsigned short)(u >> 32),
+                         (unsigned short)(u >> 48));
+    }
     __device__ float operator[](int i) const { return (float)(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w); }
 };
 template <> struct Quad<float, true> {
     float4 v;
     __device__ void load(const float *p) { v = *(const float4 *)p; }
+    __device__ void load(gptr_c base, unsigned off) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 u = *(const __attribute__((address_space(1))) f4 *)(base + off);
+        v = make_float4(u.x, u.y, u.z, u.w);
+    }
     __device__ float operator[](int i) const { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 };
 template <typename T> struct Quad<T, false> {
@@ -35,11 +48,16 @@ template <typename T> struct Quad<T, false> {
 #pragma unroll
         for (int i = 0; i < 4; ++i) e[i] = (float)p[i];
     }
+    __device__ void load(gptr_c base, unsigned off) {
+        const __attribute__((address_space(1))) T *p = (const __attribute__((address_space(1))) T *)(base + off);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = (float)p[i];
+    }
     __device__ float operator[](int i) const { return e[i]; }
 };
 
 template <int N, typename T, bool VEC>
-__global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, int chunk_frames, int window,
+__global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, int chunk_frames, int window,
                                                float inv_wsum, const float2 *__restrict__ twiddle,
                                                const float *__restrict__ hann,
                                                float2 *__restrict__ spectra, float *__restrict__ ppart,
@@ -47,12 +65,12 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
     constexpr int P = LdsPitch<N>::v;
     constexpr int HALF = N / 2;
     constexpr int NP = (HALF + 1) * N;           // power rows 0..N/2
-    constexpr int NPT = (NP + NT - 1) / NT;
-    constexpr int QPT = N * N / 4 / NT;          // pixel quads per thread and frame
+    constexpr int NPT = (NP + FT - 1) / FT;
+    constexpr int QPT = N * N / 4 / FT;          // pixel quads per thread and frame
     __shared__ float2 z[N * P];
     __shared__ float2 tw[N];
     __shared__ float hw[N];
-    __shared__ float red[2][NT / 64];
+    __shared__ float red[2][FT / 64];
 
     const int L = xcd_remap(blockIdx.x, bt.ingest_wgs);
     const int b = burst_of(bt, L, [](const BurstDesc &d) { return (int64_t)d.ingest0; });
@@ -67,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
     const int y0 = min(py * stride, H - N), x0 = min(px * stride, W - N);
     const int f0 = chunk * chunk_frames, f1 = min(F, f0 + chunk_frames);
     const int tid = threadIdx.x;
-    for (int i = tid; i < N; i += NT) {
+    for (int i = tid; i < N; i += FT) {
         tw[i] = twiddle[i];
         hw[i] = window ? hann[i] : 1.0f;
     }
@@ -81,33 +99,33 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
     constexpr int FS = SpecRows<N>::FS;          // float2 per stored frame spectrum
     const size_t spec_patch = (size_t)(bd.spec0 + (int64_t)lpatch * F) * FS;
 
-    // raw pixels of the current frame pair, loaded one pair ahead (not for
-    // 4-byte pixels at N = 128, which would not fit in registers)
-    constexpr bool AHEAD = !(sizeof(T) == 4 && N == 128);
+    // raw pixels of the current frame pair (wave-uniform frame bases, 32-bit
+    // lane offsets).  Loading the next pair during the transform measured no
+    // faster at 8 waves per CU and made the registers spill.
     Quad<T, VEC> qa[QPT], qb[QPT];
     auto load_pair = [&](int fa) __attribute__((always_inline)) {
         const int fb = min(fa + 1, f1 - 1);
-        const T *pa = frames + (size_t)fa * H * pitch + (size_t)y0 * pitch + x0;
-        const T *pb = frames + (size_t)fb * H * pitch + (size_t)y0 * pitch + x0;
+        const gptr_c pa = uniform_ptr(frames + (size_t)fa * H * pitch + (size_t)y0 * pitch + x0);
+        const gptr_c pb = uniform_ptr(frames + (size_t)fb * H * pitch + (size_t)y0 * pitch + x0);
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
-            qa[j].load(pa + (size_t)y * pitch + x);
-            qb[j].load(pb + (size_t)y * pitch + x);
+            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(T);
+            qa[j].load(pa, off);
+            qb[j].load(pb, off);
         }
     };
-    if (AHEAD) load_pair(f0);
     __syncthreads();
 
     for (int fa = f0; fa < f1; fa += 2) {
         const int fb = fa + 1;
         const bool hasb = fb < f1;
-        if (!AHEAD) load_pair(fa);
+        load_pair(fa);
         // weighted sums (compensated), raw pixels to LDS
         float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float va = qa[j][e], vb = hasb ? qb[j][e] : 0.f;
@@ -117,13 +135,12 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
                 z[y * P + x + e] = make_float2(va, vb);
             }
         }
-        if (AHEAD && fa + 2 < f1) load_pair(fa + 2);      // in flight during the FFT
         float ra = wave_sum(sa - ca), rb = wave_sum(sb - cb);
         if ((tid & 63) == 0) { red[0][tid >> 6] = ra; red[1][tid >> 6] = rb; }
         __syncthreads();
         float mua = 0.f, mub = 0.f;
 #pragma unroll
-        for (int k = 0; k < NT / 64; ++k) { mua += red[0][k]; mub += red[1][k]; }
+        for (int k = 0; k < FT / 64; ++k) { mua += red[0][k]; mub += red[1][k]; }
         mua *= inv_wsum;
         mub *= inv_wsum;
         if (tid == 0) {
@@ -133,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
         // taper the mean-removed pixels
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
@@ -142,11 +159,15 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
             }
         }
         __syncthreads();
-        fft2d_lds<N, NT>(z, tw);
+        fft2d_lds<N, FT>(z, tw);
+        // records of the two frames: wave-uniform bases, 32-bit lane offsets
+        // (fb = F when the group has no second frame: never stored to)
+        const gptr_m rec_a = uniform_ptr_m(spectra + spec_patch + (size_t)fa * FS);
+        const gptr_m rec_b = uniform_ptr_m(spectra + spec_patch + (size_t)fb * FS);
         // split the two spectra, write rows 0..N/2-1, accumulate |I|^2
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int j = k * NT + tid;
+            const int j = k * FT + tid;
             if (j < NP) {
                 const int uy = j / N, ux = j % N;
                 const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
@@ -158,15 +179,13 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
                 if (uy < HALF) {
                     // row uy of the stored record, and its conjugate mirror
                     // I(-u) = conj I(u) in row -uy for the rows below 0
-                    float2 *ra = spectra + spec_patch + (size_t)fa * FS;
-                    float2 *rb = spectra + spec_patch + (size_t)fb * FS;
-                    const int o = (uy + SPEC_NEG_ROWS) * N + ux;
-                    ra[o] = Ia;
-                    if (hasb) rb[o] = Ib;
+                    const unsigned o = ((uy + SPEC_NEG_ROWS) * N + ux) * (unsigned)sizeof(float2);
+                    store_global_f2(rec_a, o, Ia);
+                    if (hasb) store_global_f2(rec_b, o, Ib);
                     if (uy >= 1 && uy <= SPEC_NEG_ROWS) {
-                        const int om = (SPEC_NEG_ROWS - uy) * N + ((N - ux) & (N - 1));
-                        ra[om] = conjf2(Ia);
-                        if (hasb) rb[om] = conjf2(Ib);
+                        const unsigned om = ((SPEC_NEG_ROWS - uy) * N + ((N - ux) & (N - 1))) * (unsigned)sizeof(float2);
+                        store_global_f2(rec_a, om, conjf2(Ia));
+                        if (hasb) store_global_f2(rec_b, om, conjf2(Ib));
                     }
                 }
                 if (j == 1) {          // u = (1, 0)
@@ -185,12 +204,12 @@ __global__ __launch_bounds__(NT) void k_ingest(const BurstTable bt, int stride, 
     float *pp = ppart + (size_t)L * NP;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int j = k * NT + tid;
+        const int j = k * FT + tid;
         if (j < NP) pp[j] = ps[k];
     }
     float *mp = mpart + (size_t)L * 4;
-    if (tid == 1 % NT) { mp[0] = m10s[0] - m10c[0]; mp[1] = m10s[1] - m10c[1]; }
-    if (tid == N % NT) { mp[2] = m01s[0] - m01c[0]; mp[3] = m01s[1] - m01c[1]; }
+    if (tid == 1 % FT) { mp[0] = m10s[0] - m10c[0]; mp[1] = m10s[1] - m10c[1]; }
+    if (tid == N % FT) { mp[2] = m01s[0] - m01c[0]; mp[3] = m01s[1] - m01c[1]; }
     if (tid == 0) mupart[L] = mus - muc;
 }
 
@@ -277,11 +296,11 @@ __global__ __launch_bounds__(NT) void k_acc_stream(int nchunks, const float *__r
 template <int N, typename T>
 hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
     if (a.vec)
-        hipLaunchKernelGGL((k_ingest<N, T, true>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+        hipLaunchKernelGGL((k_ingest<N, T, true>), dim3(a.bt.ingest_wgs), dim3(FT), 0, st, a.bt, a.stride,
                            a.chunk_frames, a.window, a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart,
                            a.mupart);
     else
-        hipLaunchKernelGGL((k_ingest<N, T, false>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+        hipLaunchKernelGGL((k_ingest<N, T, false>), dim3(a.bt.ingest_wgs), dim3(FT), 0, st, a.bt, a.stride,
                            a.chunk_frames, a.window, a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart,
                            a.mupart);
     hipError_t e = hipGetLastError();
@@ -321,19 +340,19 @@ __device__ __forceinline__ float taper2_dft(int window, int ux, int uy) {
 }
 
 template <int N, typename T, bool VEC>
-__global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, int chunk_frames, int window,
+__global__ __launch_bounds__(FT) void k_noise(const BurstTable bt, int stride, int chunk_frames, int window,
                                               float inv_wsum, float inv_gain, const float2 *__restrict__ twiddle,
                                               const float *__restrict__ hann, float2 *__restrict__ cpart,
                                               float *__restrict__ spart) {
     constexpr int P = LdsPitch<N>::v;
     constexpr int HALF = N / 2;
     constexpr int NP = (HALF + 1) * N;
-    constexpr int NPT = (NP + NT - 1) / NT;
-    constexpr int QPT = N * N / 4 / NT;
+    constexpr int NPT = (NP + FT - 1) / FT;
+    constexpr int QPT = N * N / 4 / FT;
     __shared__ float2 z[N * P];
     __shared__ float2 tw[N];
     __shared__ float hw[N];
-    __shared__ float red[3][NT / 64];
+    __shared__ float red[3][FT / 64];
 
     const int L = xcd_remap(blockIdx.x, bt.ingest_wgs);
     const int b = burst_of(bt, L, [](const BurstDesc &d) { return (int64_t)d.ingest0; });
@@ -348,7 +367,7 @@ __global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, i
     const int y0 = min(py * stride, H - N), x0 = min(px * stride, W - N);
     const int f0 = chunk * chunk_frames, f1 = min(F, f0 + chunk_frames);
     const int tid = threadIdx.x;
-    for (int i = tid; i < N; i += NT) {
+    for (int i = tid; i < N; i += FT) {
         tw[i] = twiddle[i];
         hw[i] = window ? hann[i] : 1.0f;
     }
@@ -363,7 +382,7 @@ __global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, i
         float s1 = 0.f, c1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
             Quad<T, VEC> v;
             v.load(pf + (size_t)y * pitch + x);
 #pragma unroll
@@ -381,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, i
         __syncthreads();
         float mu = 0.f, q0 = 0.f, t3 = 0.f;
 #pragma unroll
-        for (int k = 0; k < NT / 64; ++k) { mu += red[0][k]; q0 += red[1][k]; t3 += red[2][k]; }
+        for (int k = 0; k < FT / 64; ++k) { mu += red[0][k]; q0 += red[1][k]; t3 += red[2][k]; }
         mu *= inv_wsum;
         if (tid == 0) {
             kahan_add(q0s, q0c, q0 * inv_gain);
@@ -389,7 +408,7 @@ __global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, i
         }
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * NT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
@@ -398,10 +417,10 @@ __global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, i
             }
         }
         __syncthreads();
-        fft2d_lds<N, NT>(z, tw);
+        fft2d_lds<N, FT>(z, tw);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int j = k * NT + tid;
+            const int j = k * FT + tid;
             if (j < NP) {
                 const int uy = j / N, ux = j % N;
                 const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
@@ -419,7 +438,7 @@ __global__ __launch_bounds__(NT) void k_noise(const BurstTable bt, int stride, i
     float2 *cp = cpart + (size_t)L * NP;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int j = k * NT + tid;
+        const int j = k * FT + tid;
         if (j < NP) cp[j] = cs[k];
     }
     if (tid == 0) {
@@ -479,11 +498,11 @@ template <int N, typename T>
 hipError_t launch_noise_t(const NoiseArgs &na, hipStream_t st) {
     const IngestArgs &a = na.in;
     if (a.vec)
-        hipLaunchKernelGGL((k_noise<N, T, true>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+        hipLaunchKernelGGL((k_noise<N, T, true>), dim3(a.bt.ingest_wgs), dim3(FT), 0, st, a.bt, a.stride,
                            a.chunk_frames, a.window, a.inv_wsum, na.inv_gain, a.twiddle, a.hann, na.cpart,
                            na.spart);
     else
-        hipLaunchKernelGGL((k_noise<N, T, false>), dim3(a.bt.ingest_wgs), dim3(NT), 0, st, a.bt, a.stride,
+        hipLaunchKernelGGL((k_noise<N, T, false>), dim3(a.bt.ingest_wgs), dim3(FT), 0, st, a.bt, a.stride,
                            a.chunk_frames, a.window, a.inv_wsum, na.inv_gain, a.twiddle, a.hann, na.cpart,
                            na.spart);
     hipError_t e = hipGetLastError();

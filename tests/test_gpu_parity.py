@@ -431,15 +431,15 @@ def test_photon_noise_accumulate(torch_cuda):
 
 def test_photon_noise_whole_path(torch_cuda):
     """noise_bias 2 through nvsm_reconstruct on a 160x192 crop (N = 64,
-    R = 8, 20 patches, 24 frames at 400 photons per pixel) against the
+    R = 8, 20 patches, 24 frames at 1000 photons per pixel) against the
     oracle's reconstruction with the same model.  (Far fewer photons make
     the corrected power of most high frequencies a small difference of
     large numbers, which the division by the transfer function then
     magnifies: the mosaic is no longer a stable function of the inputs.)"""
     import paper_1701_00581_amd as nv
     torch = torch_cuda
-    say("case photon noise whole path: 160x192 F=24, N=64, R=8, 400 photons/px")
-    fr, gain = _photon_burst(400, 24, 160, 192)
+    say("case photon noise whole path: 160x192 F=24, N=64, R=8, 1000 photons/px")
+    fr, gain = _photon_burst(1000, 24, 160, 192)
     p = nv.default_params(64, v_radius=8, noise_bias=2, photons_per_adu=gain, filter=1)
     import synth
     st = synth.stf_table(synth.CONFIGS["burst1024"], screens=60, patch=64)
