@@ -117,6 +117,24 @@ def test_batch_photon_noise_equals_alone(torch_cuda, bursts):
         assert same
 
 
+def test_batch_least_squares_equals_alone(torch_cuda, bursts):
+    """With least-squares phase steps (phase_method 1): their fixed-point
+    sums make the batched result bit-identical as well."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    p = _params()
+    p.phase_method = 1
+    p.lsq_iters = 5
+    ref = _alone(torch, p, bursts)
+    _, ws_all = nv.nvsm_batch_plan(p, [tuple(d.shape) for d, _ in bursts])
+    got = _batch(torch, p, bursts, ws_all)
+    for i, (g, r) in enumerate(zip(got, ref)):
+        same = torch.equal(g, r)
+        say(f"[batch lsq] burst {i} identical={same}")
+        assert torch.isfinite(g).all()
+        assert same
+
+
 def test_batch_workspace_errors(torch_cuda, bursts):
     import paper_1701_00581_amd as nv
     torch = torch_cuda

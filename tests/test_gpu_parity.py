@@ -460,3 +460,34 @@ def test_photon_noise_whole_path(torch_cuda):
     say(f"[photon path] mosaic vs oracle {err:.2e} (the correction moved the image by {moved:.2e})")
     assert err <= MOSAIC_TOL
     assert moved > 10 * MOSAIC_TOL
+
+
+def test_single64_photon_noise_no_taper(torch_cuda):
+    """noise_bias 2 without a taper (single 64x64 subimage, float32 photon
+    counts, one photon per unit): whole path against the oracle."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say("case single64 photon noise: no taper, F=100, N=64, R=8, gain 1")
+    fr = burst("single64")
+    p = nv.default_params(64, v_radius=8, window=0, noise_bias=2, photons_per_adu=1.0)
+    s = _session(p, 64, 64, 100)
+    s.accumulate(to_device(fr))
+    st = stf("single64")
+    s.solve(torch.from_numpy(st).cuda())
+    s.synthesize()
+    torch.cuda.synchronize()
+    op = oparams(p)
+    S = oracle.bispectrum_set(p.u_cut, p.v_radius)[1]
+    acc = oracle.accumulate_patch(fr.astype(np.float64), op, S)
+    I, _ = oracle.patch_spectra(fr.astype(np.float64), 0)
+    nerr, aerr = bispec_errors(as_complex(s.bispec)[0], acc["B"], abs_bispectrum(I, S))
+    perr = np.linalg.norm(s.power.cpu().numpy()[0] - acc["P"]) / np.linalg.norm(acc["P"])
+    ref = oracle.reconstruct(fr, op, st)
+    rms, mx = phase_rms(as_complex(s.phasor)[0], ref["tiles"][(0, 0)]["phasor"])
+    img = s.image.cpu().numpy()
+    merr = np.linalg.norm(img - ref["image"]) / np.linalg.norm(ref["image"] - ref["image"].mean())
+    say(f"[single64 photon] P {perr:.2e} B norm {nerr:.2e} B/A max {aerr:.2e} phase rms {rms:.2e} mosaic {merr:.2e}")
+    assert perr <= POWER_TOL
+    assert nerr <= BISPEC_TOL and aerr <= BISPEC_TOL
+    assert rms <= PHASE_RMS_TOL
+    assert merr <= MOSAIC_TOL
