@@ -18,3 +18,4 @@ object, which the paper prints no values for (parity unpinned against the
 truth; pinned only GPU-versus-oracle).
 """
 from .speckle import *  # noqa: F401,F403
+from .seeing import *  # noqa: F401,F403

@@ -1,0 +1,105 @@
+"""Pins of the model speckle transfer function (oracle/seeing.py) against
+facts outside it: the random generator's published known answers, normal
+moments, the Kolmogorov structure function, the diffraction limit, the
+band limit of the pupil, and the speckle-regime asymptote of the STF."""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def test_philox_known_answers():
+    """Philox4x32-10 known-answer vectors of its published definition
+    (counter, key -> output)."""
+    cases = [
+        ((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+        ((0xffffffff,) * 4, (0xffffffff,) * 2, (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+        ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+         (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+    ]
+    for ctr, key, want in cases:
+        got = oracle.philox4x32(*[np.array([c], np.uint32) for c in ctr], key[0], key[1])
+        assert tuple(int(g[0]) for g in got) == want
+
+
+def test_normals_moments():
+    g = oracle.normals(2024, 3, 1, 400000)
+    n = g.size
+    assert abs(g.mean()) < 4 / np.sqrt(n)
+    assert abs(g.var() - 1.0) < 4 * np.sqrt(2.0 / n)
+    assert abs(np.mean(g ** 4) - 3.0) < 0.05
+    # the two members of a Box-Muller pair are uncorrelated
+    assert abs(np.mean(g[0::2] * g[1::2])) < 4 / np.sqrt(n / 2)
+
+
+def test_screens_follow_the_kolmogorov_structure_function():
+    """<(phi(x + r) - phi(x))^2> = 6.88 (r / r0)^(5/3) for separations well
+    inside the grid, for both screens of a pair, which are uncorrelated.  FFT
+    screens with three subharmonic levels reach 0.8-0.9 of it there (the
+    grid's Nyquist limit and finite size remove some power); a wrong
+    normalisation would miss by far more."""
+    N, r0 = 128, 8.0
+    d = {r: [] for r in (2, 4, 8)}
+    cross = []
+    for j in range(24):
+        a, b = oracle.screen_pair(N, r0, 77, j, 0)
+        cross.append(np.mean((a - a.mean()) * (b - b.mean())) / np.sqrt(a.var() * b.var()))
+        for s in (a, b):
+            for r in d:
+                # differences inside the grid (the subharmonics are not periodic on it)
+                d[r].append(0.5 * (np.mean((s[:, r:] - s[:, :-r]) ** 2) + np.mean((s[r:, :] - s[:-r, :]) ** 2)))
+    for r, v in d.items():
+        ratio = np.mean(v) / (6.88 * (r / r0) ** (5.0 / 3.0))
+        assert 0.75 < ratio < 1.05, (r, ratio)
+    assert abs(np.mean(cross)) < 0.15
+
+
+def test_no_turbulence_gives_the_pupil_otf():
+    """D/r0 -> 0: every OTF is the bare pupil's, so <OTF> = T and the STF is
+    T^2 (T computed from the pupil by an explicit autocorrelation)."""
+    N = 32
+    P = oracle.pupil(N)
+    # autocorrelation of the pupil, brute force over all lags
+    T = np.zeros((N, N))
+    for dy in range(N):
+        for dx in range(N):
+            T[dy, dx] = np.sum(P * np.roll(np.roll(P, -dy, 0), -dx, 1))
+    T /= T[0, 0]
+    A, S = oracle.model(N, 1e-9, 4, 5)
+    assert np.max(np.abs(A - T)) < 1e-6
+    assert np.max(np.abs(S - T * T)) < 1e-6
+
+
+@pytest.mark.parametrize("x", [4.0, 16.0])
+def test_stf_is_normalised_symmetric_and_band_limited(x):
+    N = 64
+    A, S = oracle.model(N, x, 8, 11)
+    assert S[0, 0] == pytest.approx(1.0, abs=1e-12)
+    assert np.all(S <= 1.0 + 1e-12) and np.all(S >= 0.0)
+    Sm = S[(-np.arange(N)) % N][:, (-np.arange(N)) % N]
+    assert np.max(np.abs(S - Sm)) < 1e-12 * S.max()
+    # nothing beyond the diffraction cut-off |u| = D = N/2 px (+1 px for the
+    # discrete pupil's extent)
+    k = np.fft.fftfreq(N) * N
+    r = np.hypot(k[None, :], k[:, None])
+    assert np.max(S[r > N / 2 + 1.5]) < 1e-12
+
+
+def test_stf_speckle_regime_plateau():
+    """Between the seeing and diffraction limits the STF is the pupil OTF
+    times the coherence area of the wave over the pupil area:
+    int exp(-6.88 (r/r0)^(5/3)) d^2r / (pi D^2 / 4) = 0.4356 (r0/D)^2 for
+    Kolmogorov phase.  The screens carry 0.8-0.9 of that structure function
+    and resolve r0 by only 4-5 px here, both of which enlarge the coherence
+    area, so the plateau lies above 0.4356 but well within a factor of 2.5."""
+    from scipy.integrate import quad
+    area = 2 * np.pi * quad(lambda s: np.exp(-6.88 * s ** (5 / 3)) * s, 0, np.inf)[0]
+    assert area / (np.pi / 4) == pytest.approx(0.4356, abs=2e-4)
+    N, x = 128, 14.0
+    _, S = oracle.model(N, x, 80, 13)
+    T = oracle.otf(np.zeros((N, N)), oracle.pupil(N)).real
+    k = np.fft.fftfreq(N) * N
+    r = np.hypot(k[None, :], k[:, None])
+    band = (r > 0.35 * N / 2) & (r < 0.7 * N / 2)
+    ratio = np.mean(S[band] / (T[band] * (1.0 / x) ** 2))
+    assert 0.4356 < ratio < 2.5 * 0.4356, ratio
