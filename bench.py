@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import multiprocessing as mp
 import os
 import sys
@@ -43,6 +44,7 @@ WORKLOADS = {
     "single64": dict(v_radius=8, patch=64, window=0, noise_bias=1, filter=1),
     "batch16": None,
     "serve3": None,
+    "model_stf": None,
 }
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_bispec_burst2560_traffic.md")
@@ -289,6 +291,53 @@ def serve3(args):
     print(json.dumps(out), flush=True)
 
 
+def model_stf(args):
+    """Model STF tables: 128 x 128 patch grid, D/r0 = 20, --model-screens
+    Kolmogorov screens per table (Monte Carlo; a reading of the model STF the
+    paper chooses by r0)."""
+    import oracle
+    N, x, K = 128, 20.0, args.model_screens
+    cpu = None
+    if not args.no_cpu_baseline:
+        ks = 20
+        t = time.perf_counter()
+        oracle.model(N, x, ks, 99)
+        dt = time.perf_counter() - t
+        cpu = {"value": ks / K / dt, "unit": "tables/s", "cores": 1, "kind": "oracle",
+               "sample": f"{ks} of {K} screens of one table (FP64 NumPy oracle, one process), scaled to {K}"}
+    import torch
+    import paper_1701_00581_amd as nv
+    p = nv.default_params(N)
+    ctx = nv.nvsm_create(0)
+    ws = torch.empty(nv.nvsm_model_stf_plan(p, K), dtype=torch.uint8, device="cuda")
+    stf = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        nv.nvsm_model_stf(ctx, p, x, K, 1, stf, ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(args.steps):
+        nv.nvsm_model_stf(ctx, p, x, K, 1 + k, stf, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nv.nvsm_destroy(ctx)
+    # per screen: the pair's transform (made once per screen) and two
+    # transforms of the field and the PSF, 5 N^2 log2(N^2) flop each
+    flop = K * 3 * 5 * N * N * math.log2(N * N)
+    out = {
+        "metric": f"model STF tables/s ({N}x{N} patch grid, D/r0 {x:g}, {K} screens)",
+        "value": 1e3 / ms, "unit": "tables/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": f"model_stf: N {N}, D/r0 {x:g}, {K} screens per table"},
+        "screens_per_s": K * 1e3 / ms,
+        "fft_tflops": flop / (ms * 1e-3) / 1e12,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +352,7 @@ def main():
     ap.add_argument("--lsq-iters", type=int, default=10, help="least-squares steps with --phase-method 1")
     ap.add_argument("--noise-bias", type=int, default=None, choices=(0, 1, 2),
                     help="override the workload's noise term: 0 none, 1 corner level, 2 photon-noise model")
+    ap.add_argument("--model-screens", type=int, default=1000, help="model_stf: screens per table")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for traffic counters)")
@@ -323,6 +373,9 @@ def main():
         return
     if args.workload == "serve3":
         serve3(args)
+        return
+    if args.workload == "model_stf":
+        model_stf(args)
         return
 
     import oracle

@@ -288,6 +288,27 @@ nvsm_status nvsm_autotune(nvsm_context *ctx, const nvsm_params *p,
                           int32_t *slots_out, int32_t *form_out);
 nvsm_status nvsm_set_launch(nvsm_context *ctx, const nvsm_params *p, int32_t slots, int32_t form);
 
+/* Model speckle transfer function (the STF of Eq. 1 chosen by the seeing
+ * D/r0, Sections 2 and 3.2; the paper gives no model, so this is a reading):
+ * a Monte Carlo mean over `screens` Kolmogorov phase screens (phase spectrum
+ * 0.023 r0^(-5/3) f^(-11/3), FFT method plus three subharmonic levels of Lane,
+ * Glindemann and Dainty 1992) across a circular pupil of diameter N/2 px in
+ * the N x N patch grid (r0 = (N/2) / d_over_r0 px), so the PSF
+ * |FFT2(pupil exp(i phi))|^2 is Nyquist sampled on the patch grid; per screen
+ * OTF = FFT2(PSF) / OTF(0).
+ *   stf      device double [N][N], DFT order: <|OTF|^2> (1 at u = 0); the
+ *            table nvsm_solve and nvsm_reconstruct take.
+ *   mean_otf device double [N][N][2] (re, im) <OTF>, or NULL.
+ * Random numbers: Philox4x32-10 with key (seed mod 2^32, seed div 2^32) and
+ * counter (screen pair, word, 0, 0); the same seed gives the same table.
+ * screens: even, 2 .. 2^24 (two screens per transform); d_over_r0 in
+ * (0, 1000].  workspace: nvsm_model_stf_plan bytes of partial sums, owned by
+ * the caller; asynchronous on `stream`. */
+nvsm_status nvsm_model_stf_plan(const nvsm_params *p, int32_t screens, size_t *ws_bytes);
+nvsm_status nvsm_model_stf(nvsm_context *ctx, const nvsm_params *p, double d_over_r0, int32_t screens,
+                           uint64_t seed, double *stf, double *mean_otf, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
 /* Stage timing with HIP events recorded on the call's stream around each
  * stage's kernels (off by default; recording adds no synchronisation).
  * Stages: 0 ingest (tile cut, taper, FFT, power and mean sums),

@@ -29,6 +29,7 @@ EXPORTS = [
     "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
     "nvsm_profile_enable", "nvsm_profile_read", "nvsm_batch_plan", "nvsm_reconstruct_batch",
     "nvsm_autotune", "nvsm_set_launch", "nvsm_stream_plan", "nvsm_stream_add", "nvsm_stream_finish",
+    "nvsm_model_stf_plan", "nvsm_model_stf",
 ]
 STAGES = ["ingest", "bispectrum", "solve", "synthesize"]
 
@@ -105,6 +106,8 @@ def lib():
         L.nvsm_stream_add.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_i32, c_i32, c_p,
                                       c_sz, c_p, c_sz, c_p]
         L.nvsm_stream_finish.argtypes = [c_p, P, c_i32, c_i32, c_p, c_p, c_p, c_sz, c_p]
+        L.nvsm_model_stf_plan.argtypes = [P, c_i32, ctypes.POINTER(c_sz)]
+        L.nvsm_model_stf.argtypes = [c_p, P, ctypes.c_double, c_i32, ctypes.c_uint64, c_p, c_p, c_p, c_sz, c_p]
         L.nvsm_profile_enable.argtypes = [c_p, c_i32]
         L.nvsm_profile_read.argtypes = [c_p, c_p, c_p, c_i32]
         for name in EXPORTS:
@@ -309,6 +312,20 @@ def nvsm_stream_add(ctx, params, frames, frames_before, total_frames, state, ws,
 def nvsm_stream_finish(ctx, params, H, W, stf, out, ws, stream=None):
     _check(lib().nvsm_stream_finish(ctx, ctypes.byref(params), int(H), int(W), _ptr(stf), _ptr(out), _ptr(ws),
                                     _nbytes(ws), _stream(stream)), "nvsm_stream_finish", ctx)
+
+
+def nvsm_model_stf_plan(params, screens):
+    """Workspace bytes of nvsm_model_stf."""
+    n = ctypes.c_size_t()
+    _check(lib().nvsm_model_stf_plan(ctypes.byref(params), int(screens), ctypes.byref(n)), "nvsm_model_stf_plan")
+    return n.value
+
+
+def nvsm_model_stf(ctx, params, d_over_r0, screens, seed, stf, ws, mean_otf=None, stream=None):
+    """Model STF (device float64 [N][N]) by Monte Carlo at D/r0; mean_otf:
+    optional device float64 [N][N][2]."""
+    _check(lib().nvsm_model_stf(ctx, ctypes.byref(params), float(d_over_r0), int(screens), int(seed), _ptr(stf),
+                                _ptr(mean_otf), _ptr(ws), _nbytes(ws), _stream(stream)), "nvsm_model_stf", ctx)
 
 
 def nvsm_profile_enable(ctx, enable=True):

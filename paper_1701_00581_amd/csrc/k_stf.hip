@@ -1,0 +1,270 @@
+// Model speckle transfer function by Monte Carlo: <|OTF|^2> (and <OTF>) over
+// Kolmogorov phase screens across a circular pupil of diameter N/2 px in the
+// N x N patch grid (the PSF is then Nyquist sampled on the patch grid).
+//
+// Screens: phase spectrum 0.023 r0^(-5/3) f^(-11/3) on the DFT frequencies
+// (FFT method; a screen pair is the real and imaginary part of one complex
+// transform) plus three subharmonic levels (Lane, Glindemann and Dainty
+// 1992).  Random numbers: Philox4x32-10 (Salmon et al. 2011), key = the
+// seed's two halves, counter (pair j, word w, stream m, 0); each word gives
+// two normal pairs by Box-Muller with u = (x + 1/2) 2^-32.  Normals 2e and
+// 2e + 1 weight element e = y N + x; normals 2 N^2 + 2s, + 1 weight
+// subharmonic s = 8 (level - 1) + k, k over the 8 neighbours (iy, ix) of the
+// origin in the order iy, ix = -1, 0, 1.
+//
+// One workgroup takes screen pairs j = blockIdx.x, + gridDim.x, ...; per
+// screen: field = pupil exp(i phi) -> FFT -> |.|^2 (PSF) -> FFT (OTF) ->
+// normalised by OTF(0), accumulated over the half plane of frequencies.
+// The transforms leave their output in the storage order of fft2d_lds;
+// element-wise steps work there, and each thread moves its pixels back to
+// natural order through registers before the next transform.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace nvsm {
+
+namespace {
+
+constexpr int ST = 512;
+
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// The four normals of counter (j, w, m, 0).
+__device__ __forceinline__ void normals4(uint32_t j, uint32_t w, uint32_t m, uint32_t k0, uint32_t k1,
+                                         float (&g)[4]) {
+    uint32_t c[4] = {j, w, m, 0u};
+    philox4x32_10(c, k0, k1);
+#pragma unroll
+    for (int a = 0; a < 4; a += 2) {
+        const float u1 = (float)(((double)c[a] + 0.5) * 0x1p-32);
+        const float u2 = (float)(((double)c[a + 1] + 0.5) * 0x1p-32);
+        const float r = sqrtf(-2.0f * logf(u1));
+        float s, co;
+        sincospif(2.0f * u2, &s, &co);
+        g[a] = r * co;
+        g[a + 1] = r * s;
+    }
+}
+
+// Subharmonic s: level p = s / 8 + 1, neighbour k = s % 8 -> (iy, ix).
+__device__ __forceinline__ void sub_offset(int k, int &iy, int &ix) {
+    const int q = k < 4 ? k : k + 1;        // skip the centre of the 3 x 3 block
+    iy = q / 3 - 1;
+    ix = q % 3 - 1;
+}
+
+template <int N>
+__global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, uint32_t k0, uint32_t k1, uint32_t stream,
+                                            const float2 *__restrict__ twiddle, float2 *__restrict__ part_a,
+                                            float *__restrict__ part_s) {
+    constexpr int P = LdsPitch<N>::v;
+    constexpr int NP = (N / 2 + 1) * N;           // half plane: rows 0..N/2
+    constexpr int PX = N * N / ST;                // pixels per thread
+    constexpr int WD = N * N / 2 / ST;            // grid words per thread
+    __shared__ float2 z[N * P];
+    __shared__ float2 tw[N];
+    __shared__ float2 sh[24];                     // subharmonic coefficients
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += ST) tw[i] = twiddle[i];
+
+    // this workgroup's sums, kept in its own slice of the partials (each
+    // thread always adds to the same entries, so no other thread touches them)
+    float2 *pa = part_a + (size_t)blockIdx.x * NP;
+    float *ps = part_s + (size_t)blockIdx.x * NP;
+    for (int q = tid; q < NP; q += ST) {
+        pa[q] = make_float2(0.f, 0.f);
+        ps[q] = 0.f;
+    }
+    constexpr int PUPIL_R2 = (N / 2) * (N / 2);   // (2x - (N-1))^2 + (2y - (N-1))^2 <= (N/2)^2
+    auto in_pupil = [](int y, int x) {
+        const int dx = 2 * x - (N - 1), dy = 2 * y - (N - 1);
+        return dx * dx + dy * dy <= PUPIL_R2;
+    };
+
+    // storage position -> natural index along one axis of the transform
+    auto nat = [](int p) { return (p % FftGeom<N>::R1) * FftGeom<N>::R2 + p / FftGeom<N>::R1; };
+    // A pair's screens are the real and imaginary parts of one transform;
+    // the transform is made again for the second screen, so that neither
+    // screen has to be held while the other one is used.
+    for (int j = blockIdx.x; j < pairs; j += gridDim.x) {
+#pragma unroll 1
+        for (int scr = 0; scr < 2; ++scr) {
+            __syncthreads();                       // previous use of z and sh done
+            // spectrum of the screen pair, natural order
+#pragma unroll 1
+            for (int q = 0; q < WD; ++q) {
+                const int w = q * ST + tid;        // elements 2w, 2w + 1 (same row)
+                float g[4];
+                normals4((uint32_t)j, (uint32_t)w, stream, k0, k1, g);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = 2 * w + h, y = e / N, x = e % N;
+                    const int kx = x < N / 2 ? x : x - N, ky = y < N / 2 ? y : y - N;
+                    const float f2 = (float)(kx * kx + ky * ky);
+                    // sqrt(PSD(|k| / N)) / N = amp |k|^(-11/6), amp = sqrt(0.023) r0^(-5/6) N^(5/6)
+                    const float sig = f2 > 0.f ? amp * exp2f((-11.0f / 12.0f) * log2f(f2)) : 0.f;
+                    z[y * P + x] = make_float2(sig * g[2 * h], sig * g[2 * h + 1]);
+                }
+            }
+            if (tid < 12) {
+                float g[4];
+                normals4((uint32_t)j, (uint32_t)(N * N / 2 + tid), stream, k0, k1, g);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int s = 2 * tid + h, p = s / 8 + 1;
+                    const float t3 = p == 1 ? 3.f : p == 2 ? 9.f : 27.f;
+                    int iy, ix;
+                    sub_offset(s % 8, iy, ix);
+                    // |f| = kk / N with kk = |(ix, iy)| / 3^p; sqrt(PSD) df / 3^p = amp kk^(-11/6) / 3^p
+                    const float kk = sqrtf((float)(ix * ix + iy * iy)) / t3;
+                    const float sig = amp * exp2f((-11.0f / 6.0f) * log2f(kk)) / t3;
+                    sh[s] = make_float2(sig * g[2 * h], sig * g[2 * h + 1]);
+                }
+            }
+            __syncthreads();
+            fft2d_lds<N, ST>(z, tw);
+            // subharmonics, in place at each stored position
+#pragma unroll 1
+            for (int i = tid; i < N * N; i += ST) {
+                const int row = i / N, col = i % N;
+                const int y = nat(row), x = nat(col);
+                float2 v = z[row * P + col];
+#pragma unroll
+                for (int p = 1; p <= 3; ++p) {
+                    // exp(2 pi i x / (N 3^p)) and the same for y
+                    const float inv = 1.0f / ((float)N * (p == 1 ? 3.f : p == 2 ? 9.f : 27.f));
+                    float sx, cx, sy, cy;
+                    sincospif(2.0f * (float)x * inv, &sx, &cx);
+                    sincospif(2.0f * (float)y * inv, &sy, &cy);
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk) {
+                        int iy, ix;
+                        sub_offset(kk, iy, ix);
+                        const float exr = ix ? cx : 1.f, exi = (float)ix * sx;     // exp(i ix a), ix in -1, 0, 1
+                        const float eyr = iy ? cy : 1.f, eyi = (float)iy * sy;
+                        const float er = exr * eyr - exi * eyi, ei = exr * eyi + exi * eyr;
+                        const float2 c = sh[8 * (p - 1) + kk];
+                        v.x += c.x * er - c.y * ei;
+                        v.y += c.x * ei + c.y * er;
+                    }
+                }
+                z[row * P + col] = v;
+            }
+            __syncthreads();
+            // field = pupil exp(i phi) of this screen, to natural order
+            float2 t[PX];
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int e = k * ST + tid, y = e / N, x = e % N;
+                float s = 0.f, c = 0.f;
+                if (in_pupil(y, x)) {
+                    const float2 v = z[fft_pos<N>(y) * P + fft_pos<N>(x)];
+                    sincosf(scr ? v.y : v.x, &s, &c);
+                }
+                t[k] = make_float2(c, s);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int e = k * ST + tid;
+                z[(e / N) * P + e % N] = t[k];
+            }
+            __syncthreads();
+            fft2d_lds<N, ST>(z, tw);
+            // PSF = |.|^2, to natural order for the next transform
+            float psf[PX];
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int e = k * ST + tid, y = e / N, x = e % N;
+                const float2 v = z[fft_pos<N>(y) * P + fft_pos<N>(x)];
+                psf[k] = v.x * v.x + v.y * v.y;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int e = k * ST + tid;
+                z[(e / N) * P + e % N] = make_float2(psf[k], 0.f);
+            }
+            __syncthreads();
+            fft2d_lds<N, ST>(z, tw);
+            const float o0 = z[0].x;               // OTF(0) = sum of the PSF
+#pragma unroll 4
+            for (int q = tid; q < NP; q += ST) {
+                const int uy = q / N, ux = q % N;
+                const float2 o = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
+                const float ox = o.x / o0, oy = o.y / o0;    // (a division: exactly 1 at u = 0)
+                const float2 a = pa[q];
+                pa[q] = make_float2(a.x + ox, a.y + oy);
+                ps[q] += ox * ox + oy * oy;
+            }
+        }
+    }
+}
+
+// Sums the workgroups' partials in FP64 and writes <|OTF|^2> (and <OTF>)
+// over the full grid: the half plane directly, the other half from
+// S(-u) = S(u) and <OTF>(-u) = conj <OTF>(u).
+template <int N>
+__global__ __launch_bounds__(256) void k_stf_finalize(int nwg, double inv_screens, const float2 *__restrict__ part_a,
+                                                      const float *__restrict__ part_s, double *__restrict__ stf,
+                                                      double2 *__restrict__ mean_otf) {
+    constexpr int NP = (N / 2 + 1) * N;
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= NP) return;
+    double ax = 0.0, ay = 0.0, s = 0.0;
+    for (int b = 0; b < nwg; ++b) {
+        const float2 a = part_a[(size_t)b * NP + q];
+        ax += (double)a.x;
+        ay += (double)a.y;
+        s += (double)part_s[(size_t)b * NP + q];
+    }
+    ax *= inv_screens;
+    ay *= inv_screens;
+    s *= inv_screens;
+    const int uy = q / N, ux = q % N;
+    stf[uy * N + ux] = s;
+    if (mean_otf) mean_otf[uy * N + ux] = make_double2(ax, ay);
+    if (uy >= 1 && uy < N / 2) {
+        const int my = N - uy, mx = (N - ux) & (N - 1);
+        stf[my * N + mx] = s;
+        if (mean_otf) mean_otf[my * N + mx] = make_double2(ax, -ay);
+    }
+}
+
+template <int N>
+hipError_t launch_stf_t(const StfArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL((k_stf<N>), dim3(a.nwg), dim3(ST), 0, st, a.pairs, a.amp, a.k0, a.k1, a.stream, a.twiddle,
+                       a.part_a, a.part_s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    constexpr int NP = (N / 2 + 1) * N;
+    hipLaunchKernelGGL((k_stf_finalize<N>), dim3((NP + 255) / 256), dim3(256), 0, st, a.nwg, 1.0 / (2.0 * a.pairs),
+                       a.part_a, a.part_s, a.stf, a.mean_otf);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stf(const StfArgs &a, hipStream_t st) {
+    if (a.pairs < 1 || a.nwg < 1) return hipErrorInvalidValue;
+    return a.N == 128 ? launch_stf_t<128>(a, st) : launch_stf_t<64>(a, st);
+}
+
+}  // namespace nvsm

@@ -70,6 +70,23 @@ struct NoiseArgs {
 };
 hipError_t launch_noise(const NoiseArgs &a, hipStream_t st);
 
+// Model speckle transfer function by Monte Carlo over Kolmogorov screens
+// (see k_stf.hip): screens = 2 pairs; nwg workgroups each sum their pairs'
+// <OTF> and <|OTF|^2> over the half plane into part_a / part_s; stf (and
+// mean_otf if not null) receive the means over the full N x N grid (DFT
+// order, FP64).
+struct StfArgs {
+    int N = 0, pairs = 0, nwg = 0;
+    float amp = 0.f;                      // sqrt(0.023) r0^(-5/6) N^(5/6), r0 in px
+    uint32_t k0 = 0, k1 = 0, stream = 0;  // Philox key and counter word 2
+    const float2 *twiddle = nullptr;
+    float2 *part_a = nullptr;             // [nwg][N/2 + 1][N]
+    float *part_s = nullptr;              // [nwg][N/2 + 1][N]
+    double *stf = nullptr;                // [N][N]
+    double2 *mean_otf = nullptr;          // [N][N] or null
+};
+hipError_t launch_stf(const StfArgs &a, hipStream_t st);
+
 // Zeroes bytes (a multiple of 16, 16-byte aligned) with a fill kernel.
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -993,6 +994,63 @@ nvsm_status nvsm_stream_finish(nvsm_context *ctx, const nvsm_params *p, int32_t 
     if (e != hipSuccess) return hip_fail(ctx, e, "stream solve");
     e = run_synth(ctx, dp, p, bt, v.amp, v.phasor, v.mu, v.patches, true, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "stream synthesize");
+    return NVSM_OK;
+}
+
+static nvsm_status stf_sizes(const nvsm_params *p, int32_t screens, int *pairs, int *nwg, size_t *part_a,
+                             size_t *part_s, std::string *msg) {
+    nvsm_status s = check_params(p, msg);
+    if (s != NVSM_OK) return s;
+    if (screens < 2 || screens > (1 << 24) || screens % 2) {
+        *msg = "screens must be even and in [2, 2^24]";
+        return NVSM_ERR_INVALID_ARG;
+    }
+    *pairs = screens / 2;
+    *nwg = std::min(*pairs, 256);                // one workgroup per CU (the tile fills LDS)
+    const size_t np = (size_t)(p->patch / 2 + 1) * p->patch;
+    *part_a = align_up((size_t)*nwg * np * 8);
+    *part_s = align_up((size_t)*nwg * np * 4);
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_model_stf_plan(const nvsm_params *p, int32_t screens, size_t *ws_bytes) {
+    if (!ws_bytes) return NVSM_ERR_INVALID_ARG;
+    std::string msg;
+    int pairs, nwg;
+    size_t pa, ps;
+    nvsm_status s = stf_sizes(p, screens, &pairs, &nwg, &pa, &ps, &msg);
+    if (s != NVSM_OK) return s;
+    *ws_bytes = pa + ps;
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_model_stf(nvsm_context *ctx, const nvsm_params *p, double d_over_r0, int32_t screens,
+                           uint64_t seed, double *stf, double *mean_otf, void *workspace, size_t workspace_bytes,
+                           void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!stf) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    std::string msg;
+    int pairs, nwg;
+    size_t pa, ps;
+    nvsm_status s = stf_sizes(p, screens, &pairs, &nwg, &pa, &ps, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    if (!(d_over_r0 > 0.0 && d_over_r0 <= 1000.0))
+        return fail(ctx, NVSM_ERR_INVALID_ARG, "d_over_r0 must be in (0, 1000]");
+    if (!workspace || workspace_bytes < pa + ps) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small");
+    DevicePlan *dp;
+    if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;
+    const int N = p->patch;
+    const double r0 = (N / 2.0) / d_over_r0;
+    StfArgs a;
+    a.N = N; a.pairs = pairs; a.nwg = nwg;
+    a.amp = (float)(std::sqrt(0.023) * std::pow(r0, -5.0 / 6.0) * std::pow((double)N, 5.0 / 6.0));
+    a.k0 = (uint32_t)(seed & 0xffffffffu); a.k1 = (uint32_t)(seed >> 32); a.stream = 0;
+    a.twiddle = dp->twiddle;
+    a.part_a = (float2 *)workspace;
+    a.part_s = (float *)((char *)workspace + pa);
+    a.stf = stf; a.mean_otf = (double2 *)mean_otf;
+    hipError_t e = launch_stf(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "model stf");
     return NVSM_OK;
 }
 

@@ -97,6 +97,14 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
     with pytest.raises(nv.NvsmError) as e:
         nv.nvsm_stream_plan(p, 1024, 1024, 10)
     assert e.value.status == _lib.NVSM_ERR_NOT_IMPLEMENTED
+    # model STF workspace: partial sums of min(pairs, 256) workgroups over the half plane
+    p = nv.default_params(128)
+    assert nv.nvsm_model_stf_plan(p, 1000) == 256 * 65 * 128 * 12
+    assert nv.nvsm_model_stf_plan(p, 8) == 4 * 65 * 128 * 12
+    for bad in (0, 7, -2, (1 << 24) + 2):
+        n = ctypes.c_size_t()
+        assert L.nvsm_model_stf_plan(ctypes.byref(p), bad, ctypes.byref(n)) == _lib.NVSM_ERR_INVALID_ARG
+    assert L.nvsm_model_stf(None, ctypes.byref(p), 10.0, 8, 1, None, None, None, 0, None) == _lib.NVSM_ERR_INVALID_ARG
     p = nv.default_params(128)
     assert L.nvsm_plan(ctypes.byref(p), 100, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 0, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
