@@ -103,3 +103,70 @@ def test_stf_speckle_regime_plateau():
     band = (r > 0.35 * N / 2) & (r < 0.7 * N / 2)
     ratio = np.mean(S[band] / (T[band] * (1.0 / x) ** 2))
     assert 0.4356 < ratio < 2.5 * 0.4356, ratio
+
+
+# ---------------------------------------------------------------------------
+# Spectral ratio and the seeing fit.
+# ---------------------------------------------------------------------------
+def test_spectral_ratio_of_identical_frames_is_one():
+    """Frames that do not change have |<I>|^2 = <|I|^2>: the finite-burst
+    corrected ratio is 1 wherever there is power."""
+    rng = np.random.default_rng(3)
+    img = rng.random((32, 32))
+    eps, P = oracle.spectral_ratio(np.repeat(img[None], 7, axis=0), 1)
+    nz = P > 1e-12 * P.max()
+    assert np.max(np.abs(eps[nz] - 1.0)) < 1e-9
+
+
+def test_spectral_ratio_numerator_is_unbiased_for_random_frames():
+    """Frames = fixed image + independent white noise of power sigma^2 per
+    frequency: E|m|^2 = |S|^2 + sigma^2 / F and E P = |S|^2 + sigma^2, so
+    eps P = (|m|^2 - P / F) / (1 - 1/F) averages to |S|^2 (the uncorrected
+    |m|^2 sits sigma^2 / F above it)."""
+    N, F, B = 16, 8, 400
+    rng = np.random.default_rng(9)
+    base = rng.standard_normal((N, N))
+    S2 = np.abs(np.fft.fft2(base - base.mean())) ** 2
+    sigma2 = S2[1:, 1:].mean()
+    num, raw = [], []
+    for _ in range(B):
+        fr = base[None] + rng.standard_normal((F, N, N)) * np.sqrt(sigma2 / (N * N))
+        eps, P = oracle.spectral_ratio(fr, 0)
+        num.append(eps * P)
+        I = np.fft.fft2(fr - fr.mean(axis=(1, 2), keepdims=True), axes=(1, 2))
+        raw.append(np.abs(I.mean(axis=0)) ** 2)
+    m = np.ones((N, N), bool)
+    m[0, 0] = False
+    se = sigma2 * np.sqrt(4.0 / (F * B))              # rough standard error of the mean numerator
+    assert abs(np.mean(np.mean(num, axis=0)[m] - S2[m])) < 3 * se / np.sqrt(m.sum())
+    assert np.mean(np.mean(raw, axis=0)[m] - S2[m]) == pytest.approx(sigma2 / F, rel=0.1)
+
+
+def test_weighted_model_curve_without_taper_is_the_annular_mean():
+    rng = np.random.default_rng(4)
+    N, Q = 32, 6
+    rho = rng.random((N, N))
+    rho[0, 0] = 0.0
+    P = rng.random((N, N)) + 0.1
+    annuli = oracle.half_plane_annuli(Q)
+    got = oracle.weighted_model_curve(rho, P, 0, annuli)
+    want = np.array([np.mean([rho[uy % N, ux % N] for (uy, ux) in mem]) for mem in annuli])
+    assert np.allclose(got, want, rtol=0, atol=1e-15)
+    # the half-plane annuli hold one of each +-u: counts are half the full annuli
+    k = np.fft.fftfreq(N) * N
+    r = np.hypot(k[None, :], k[:, None])
+    for q, mem in enumerate(annuli, 1):
+        assert 2 * len(mem) == np.count_nonzero((r >= q - 0.5) & (r < q + 0.5))
+
+
+def test_seeing_recovers_the_generators_d_over_r0():
+    """A 384 x 384 burst of 60 frames made by the test generator at
+    D/r0 = 15 (its own Kolmogorov screens): the spectral-ratio estimate lies
+    within 10 % (measured 14.5)."""
+    import dataclasses
+    import synth
+    cfg = dataclasses.replace(synth.CONFIGS["burst1024"], index=300, H=384, W=384)
+    fr = synth.make_burst(cfg, frames=60).astype(np.float64)
+    r = oracle.seeing(fr, 128, 1, screens=200, seed=5, lo=6.0, hi=40.0, J=12, Q=12)
+    assert abs(r["d_over_r0"] / cfg.d_over_r0 - 1.0) < 0.10, r["d_over_r0"]
+    assert r["stf"][0, 0] == pytest.approx(1.0, abs=1e-12)
