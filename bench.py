@@ -45,6 +45,7 @@ WORKLOADS = {
     "batch16": None,
     "serve3": None,
     "model_stf": None,
+    "seeing2560": None,
 }
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_bispec_burst2560_traffic.md")
@@ -338,6 +339,63 @@ def model_stf(args):
     print(json.dumps(out), flush=True)
 
 
+def seeing2560(args):
+    """Seeing estimate by the spectral ratio of the 2560x2160x100 burst (320
+    cubes of 128^2) with the default settings: 40 model points of 1000
+    screens, 12 annuli; then its model STF."""
+    import oracle
+    import synth
+    cfg = synth.CONFIGS["burst2560"]
+    frames = synth.make_burst(cfg)
+    F, H, W = frames.shape
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's two parts on a sample: one model point of 20 screens,
+        # and the ratio of 2 cubes, scaled to 41 model points of 1000 screens
+        # and 320 cubes (the per-cube fit is left out of the sample)
+        t = time.perf_counter()
+        oracle.model(128, 20.0, 20, 1, 0)
+        t_model = (time.perf_counter() - t) * (1000 / 20) * 41
+        t = time.perf_counter()
+        for (y0, x0) in oracle.seeing_cubes(H, W, 128)[:2]:
+            oracle.spectral_ratio(frames[:, y0:y0 + 128, x0:x0 + 128].astype(np.float64), 1)
+        t_ratio = (time.perf_counter() - t) * 320 / 2
+        cpu = {"value": 1.0 / (t_model + t_ratio), "unit": "estimates/s", "cores": 1, "kind": "oracle",
+               "sample": "one model point of 20 screens and the ratio of 2 cubes, scaled to 41 x 1000 screens and "
+                         "320 cubes (FP64 NumPy oracle, one process; the fit is not included)"}
+    import torch
+    import paper_1701_00581_amd as nv
+    p = nv.default_params(128)
+    sp = nv.seeing_default_params()
+    ws_b, cubes = nv.nvsm_seeing_plan(p, sp, H, W, F)
+    ctx = nv.nvsm_create(0)
+    d = torch.from_numpy(frames.view(np.int16)).cuda()
+    x = torch.empty(1 + cubes, dtype=torch.float64, device="cuda")
+    stf = torch.empty((128, 128), dtype=torch.float64, device="cuda")
+    ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        nv.nvsm_seeing(ctx, p, sp, d, x, stf, ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        nv.nvsm_seeing(ctx, p, sp, d, x, stf, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    est = float(x[0].item())
+    nv.nvsm_destroy(ctx)
+    out = {
+        "metric": "seeing estimates/s (2560x2160x100, 320 cubes of 128^2, 40 model points x 1000 screens)",
+        "value": 1e3 / ms, "unit": "estimates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": "seeing2560: the 2560x2160x100 burst, D/r0 20 in the generator"},
+        "d_over_r0_estimate": est, "d_over_r0_generator": cfg.d_over_r0, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,6 +434,9 @@ def main():
         return
     if args.workload == "model_stf":
         model_stf(args)
+        return
+    if args.workload == "seeing2560":
+        seeing2560(args)
         return
 
     import oracle

@@ -309,6 +309,45 @@ nvsm_status nvsm_model_stf(nvsm_context *ctx, const nvsm_params *p, double d_ove
                            uint64_t seed, double *stf, double *mean_otf, void *workspace,
                            size_t workspace_bytes, void *stream);
 
+/* Seeing estimate by the spectral ratio (Sections 2 and 3.2: the paper
+ * finds r0 from the burst on non-overlapping subimage cubes, averages it and
+ * chooses the model STF by it; it gives no formulas, so this is a reading).
+ * Cubes: the full N x N tiles of the frame on a grid of step N.  Per cube,
+ * with the taper and mean removal of nvsm_accumulate, m = <I_f> and
+ * P = <|I_f|^2>: eps(u) = (|m|^2 - P/F) / (P (1 - 1/F)), averaged over the
+ * annuli q - 1/2 <= |u| < q + 1/2 (q = 1..bins).  Model curves, on the grid
+ * D/r0 = min (max/min)^(j/(points-1)): rho = |<OTF>|^2 / <|OTF|^2> of the
+ * nvsm_model_stf Monte Carlo (model point j is Philox counter word 2 = j),
+ * seen through the taper as sum_k |w(k)|^2 P(u-k) rho(u-k) / sum_k
+ * |w(k)|^2 P(u-k) (|w|^2 = 1/4, 1/16 per axis at offsets 0, +-1; only k = 0
+ * without a taper), averaged over the same annuli.  A cube's D/r0 minimises
+ * the squared distance of the curves (first minimum, then the vertex of the
+ * parabola through it and its neighbours, in grid index); the burst's is
+ * 1 / <1 / (D/r0)> over the cubes.
+ *   d_over_r0 device double [1 + cubes]: the burst's value, then each cube's.
+ *   stf       device double [N][N]: the model STF at the burst's value
+ *             (nvsm_model_stf with counter word 2 = points), ready for
+ *             nvsm_solve / nvsm_reconstruct.
+ *   curves    device double [cubes][bins] ratio curves, or NULL.
+ * F >= 2; H, W >= N.  workspace: nvsm_seeing_plan bytes.  Asynchronous on
+ * `stream` (nothing is read back to the host). */
+typedef struct {
+    int32_t screens;        /* Monte Carlo screens per model point, even, 2..2^24 (default 1000) */
+    int32_t points;         /* model points of the D/r0 grid, 3..256 (default 40) */
+    double  d_over_r0_min;  /* grid ends, 0 < min < max <= 1000 (default 2, 50) */
+    double  d_over_r0_max;
+    int32_t bins;           /* annuli of the fit, 2..min(24, N/4) (default 12) */
+    int32_t reserved;       /* 0 */
+    uint64_t seed;          /* Philox key (default 1) */
+} nvsm_seeing_params;
+nvsm_status nvsm_seeing_default_params(nvsm_seeing_params *out);
+nvsm_status nvsm_seeing_plan(const nvsm_params *p, const nvsm_seeing_params *sp, int32_t H, int32_t W, int32_t F,
+                             size_t *ws_bytes, int32_t *cubes);
+nvsm_status nvsm_seeing(nvsm_context *ctx, const nvsm_params *p, const nvsm_seeing_params *sp,
+                        const void *frames, nvsm_dtype dtype, int32_t F, int32_t H, int32_t W,
+                        int64_t row_pitch, double *d_over_r0, double *stf, double *curves,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
 /* Stage timing with HIP events recorded on the call's stream around each
  * stage's kernels (off by default; recording adds no synchronisation).
  * Stages: 0 ingest (tile cut, taper, FFT, power and mean sums),

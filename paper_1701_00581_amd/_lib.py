@@ -29,7 +29,7 @@ EXPORTS = [
     "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
     "nvsm_profile_enable", "nvsm_profile_read", "nvsm_batch_plan", "nvsm_reconstruct_batch",
     "nvsm_autotune", "nvsm_set_launch", "nvsm_stream_plan", "nvsm_stream_add", "nvsm_stream_finish",
-    "nvsm_model_stf_plan", "nvsm_model_stf",
+    "nvsm_model_stf_plan", "nvsm_model_stf", "nvsm_seeing_default_params", "nvsm_seeing_plan", "nvsm_seeing",
 ]
 STAGES = ["ingest", "bispectrum", "solve", "synthesize"]
 
@@ -46,6 +46,14 @@ class Params(ctypes.Structure):
         ("v_radius", ctypes.c_int32), ("window", ctypes.c_int32), ("phase_method", ctypes.c_int32),
         ("noise_bias", ctypes.c_int32), ("filter", ctypes.c_int32), ("stf_floor", ctypes.c_double),
         ("lsq_iters", ctypes.c_int32), ("reserved", ctypes.c_int32), ("photons_per_adu", ctypes.c_double),
+    ]
+
+
+class SeeingParams(ctypes.Structure):
+    _fields_ = [
+        ("screens", ctypes.c_int32), ("points", ctypes.c_int32), ("d_over_r0_min", ctypes.c_double),
+        ("d_over_r0_max", ctypes.c_double), ("bins", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -108,6 +116,11 @@ def lib():
         L.nvsm_stream_finish.argtypes = [c_p, P, c_i32, c_i32, c_p, c_p, c_p, c_sz, c_p]
         L.nvsm_model_stf_plan.argtypes = [P, c_i32, ctypes.POINTER(c_sz)]
         L.nvsm_model_stf.argtypes = [c_p, P, ctypes.c_double, c_i32, ctypes.c_uint64, c_p, c_p, c_p, c_sz, c_p]
+        SP = ctypes.POINTER(SeeingParams)
+        L.nvsm_seeing_default_params.argtypes = [SP]
+        L.nvsm_seeing_plan.argtypes = [P, SP, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz), ctypes.POINTER(c_i32)]
+        L.nvsm_seeing.argtypes = [c_p, P, SP, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_p, c_p, c_p, c_p, c_sz,
+                                  c_p]
         L.nvsm_profile_enable.argtypes = [c_p, c_i32]
         L.nvsm_profile_read.argtypes = [c_p, c_p, c_p, c_i32]
         for name in EXPORTS:
@@ -326,6 +339,33 @@ def nvsm_model_stf(ctx, params, d_over_r0, screens, seed, stf, ws, mean_otf=None
     optional device float64 [N][N][2]."""
     _check(lib().nvsm_model_stf(ctx, ctypes.byref(params), float(d_over_r0), int(screens), int(seed), _ptr(stf),
                                 _ptr(mean_otf), _ptr(ws), _nbytes(ws), _stream(stream)), "nvsm_model_stf", ctx)
+
+
+def seeing_default_params(**kw):
+    sp = SeeingParams()
+    _check(lib().nvsm_seeing_default_params(ctypes.byref(sp)), "nvsm_seeing_default_params")
+    for k, v in kw.items():
+        setattr(sp, k, v)
+    return sp
+
+
+def nvsm_seeing_plan(params, sp, H, W, F):
+    """(workspace bytes, cubes)."""
+    n, c = ctypes.c_size_t(), ctypes.c_int32()
+    _check(lib().nvsm_seeing_plan(ctypes.byref(params), ctypes.byref(sp), int(H), int(W), int(F), ctypes.byref(n),
+                                  ctypes.byref(c)), "nvsm_seeing_plan")
+    return n.value, c.value
+
+
+def nvsm_seeing(ctx, params, sp, frames, d_over_r0, stf, ws, curves=None, stream=None):
+    """Seeing by the spectral ratio.  frames: device [F][H][W] (view with a
+    row pitch allowed) of int16 (12-bit data) or float32; d_over_r0: device
+    float64 [1 + cubes]; stf: device float64 [N][N]; curves: optional device
+    float64 [cubes][bins]."""
+    F, H, W = frames.shape
+    _check(lib().nvsm_seeing(ctx, ctypes.byref(params), ctypes.byref(sp), _ptr(frames), frames_dtype(frames), F, H, W,
+                             frames.stride(1), _ptr(d_over_r0), _ptr(stf), _ptr(curves), _ptr(ws), _nbytes(ws),
+                             _stream(stream)), "nvsm_seeing", ctx)
 
 
 def nvsm_profile_enable(ctx, enable=True):

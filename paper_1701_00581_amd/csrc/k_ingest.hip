@@ -512,6 +512,125 @@ hipError_t launch_noise_t(const NoiseArgs &na, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Spectral-ratio sums of the seeing cubes: one workgroup per (cube, frame
+// group); cube c is the N x N tile at (c / nx, c % nx) * N of frames
+// [F][H][pitch].  Two frames per transform as in k_ingest (same taper and
+// weighted-mean removal).  Only the box 0 <= uy <= B, |ux| <= B is kept:
+// per entry e = uy (2B + 1) + ux + B the group's sums of I (re, im) and of
+// |I|^2 go to part[L][e][0..2].
+template <int N, typename T, bool VEC>
+__global__ __launch_bounds__(FT) void k_ratio(const RatioArgs a) {
+    constexpr int P = LdsPitch<N>::v;
+    constexpr int QPT = N * N / 4 / FT;
+    constexpr int MAXE = (RATIO_MAX_BINS + 3) * (2 * RATIO_MAX_BINS + 5);
+    constexpr int EPT = (MAXE + FT - 1) / FT;
+    __shared__ float2 z[N * P];
+    __shared__ float2 tw[N];
+    __shared__ float hw[N];
+    __shared__ float red[2][FT / 64];
+    const T *frames = (const T *)a.frames;
+    const int64_t pitch = a.pitch;
+    const int nchunks = (a.F + a.chunk_frames - 1) / a.chunk_frames;
+    const int L = blockIdx.x;
+    const int cube = L / nchunks, chunk = L % nchunks;
+    const int y0 = (cube / a.nx) * N, x0 = (cube % a.nx) * N;
+    const int f0 = chunk * a.chunk_frames, f1 = min(a.F, f0 + a.chunk_frames);
+    const int B = a.B, bw = 2 * B + 1, nbox = (B + 1) * bw;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += FT) {
+        tw[i] = a.twiddle[i];
+        hw[i] = a.window ? a.hann[i] : 1.0f;
+    }
+    float sm[EPT][3];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) sm[k][0] = sm[k][1] = sm[k][2] = 0.f;
+    Quad<T, VEC> qa[QPT], qb[QPT];
+    __syncthreads();
+    for (int fa = f0; fa < f1; fa += 2) {
+        const bool hasb = fa + 1 < f1;
+        const int fb = hasb ? fa + 1 : fa;
+        const gptr_c pa = uniform_ptr(frames + (size_t)fa * a.H * pitch + (size_t)y0 * pitch + x0);
+        const gptr_c pb = uniform_ptr(frames + (size_t)fb * a.H * pitch + (size_t)y0 * pitch + x0);
+        float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(T);
+            qa[j].load(pa, off);
+            qb[j].load(pb, off);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float va = qa[j][e], vb = hasb ? qb[j][e] : 0.f;
+                const float w = hw[y] * hw[x + e];
+                kahan_add(sa, ca, w * va);
+                kahan_add(sb, cb, w * vb);
+                z[y * P + x + e] = make_float2(va, vb);
+            }
+        }
+        const float r0 = wave_sum(sa - ca), r1 = wave_sum(sb - cb);
+        if ((tid & 63) == 0) { red[0][tid >> 6] = r0; red[1][tid >> 6] = r1; }
+        __syncthreads();
+        float mua = 0.f, mub = 0.f;
+#pragma unroll
+        for (int k = 0; k < FT / 64; ++k) { mua += red[0][k]; mub += red[1][k]; }
+        mua *= a.inv_wsum;
+        mub *= a.inv_wsum;
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float w = hw[y] * hw[x + e];
+                const float2 v = z[y * P + x + e];
+                z[y * P + x + e] = make_float2((v.x - mua) * w, hasb ? (v.y - mub) * w : 0.f);
+            }
+        }
+        __syncthreads();
+        fft2d_lds<N, FT>(z, tw);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = k * FT + tid;
+            if (e < nbox) {
+                const int uy = e / bw, ux = (e % bw - B) & (N - 1);
+                const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
+                const float2 Zm = z[fft_pos<N>((N - uy) & (N - 1)) * P + fft_pos<N>((N - ux) & (N - 1))];
+                const float2 Ia = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+                const float2 Ib = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+                sm[k][0] += Ia.x;
+                sm[k][1] += Ia.y;
+                sm[k][2] += Ia.x * Ia.x + Ia.y * Ia.y;
+                if (hasb) {
+                    sm[k][0] += Ib.x;
+                    sm[k][1] += Ib.y;
+                    sm[k][2] += Ib.x * Ib.x + Ib.y * Ib.y;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *pp = a.part + (size_t)L * nbox * 3;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = k * FT + tid;
+        if (e < nbox) {
+            pp[3 * e] = sm[k][0];
+            pp[3 * e + 1] = sm[k][1];
+            pp[3 * e + 2] = sm[k][2];
+        }
+    }
+}
+
+template <int N, typename T>
+hipError_t launch_ratio_t(const RatioArgs &a, hipStream_t st) {
+    const int nchunks = (a.F + a.chunk_frames - 1) / a.chunk_frames;
+    const int grid = a.cubes * nchunks;
+    if (a.vec)
+        hipLaunchKernelGGL((k_ratio<N, T, true>), dim3(grid), dim3(FT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_ratio<N, T, false>), dim3(grid), dim3(FT), 0, st, a);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(NT) void k_zero(float4 *__restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -532,6 +651,12 @@ hipError_t launch_noise(const NoiseArgs &na, hipStream_t st) {
     if (a.bt.patches == 0) return hipSuccess;
     if (a.N == 128) return a.f32 ? launch_noise_t<128, float>(na, st) : launch_noise_t<128, uint16_t>(na, st);
     return a.f32 ? launch_noise_t<64, float>(na, st) : launch_noise_t<64, uint16_t>(na, st);
+}
+
+hipError_t launch_ratio(const RatioArgs &a, hipStream_t st) {
+    if (a.cubes < 1 || a.F < 2 || a.B < 3 || a.B > RATIO_MAX_BINS + 2 || a.chunk_frames < 1) return hipErrorInvalidValue;
+    if (a.N == 128) return a.f32 ? launch_ratio_t<128, float>(a, st) : launch_ratio_t<128, uint16_t>(a, st);
+    return a.f32 ? launch_ratio_t<64, float>(a, st) : launch_ratio_t<64, uint16_t>(a, st);
 }
 
 hipError_t launch_ingest(const IngestArgs &a, hipStream_t st) {

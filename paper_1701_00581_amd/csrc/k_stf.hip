@@ -71,9 +71,9 @@ __device__ __forceinline__ void sub_offset(int k, int &iy, int &ix) {
 }
 
 template <int N>
-__global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, uint32_t k0, uint32_t k1, uint32_t stream,
-                                            const float2 *__restrict__ twiddle, float2 *__restrict__ part_a,
-                                            float *__restrict__ part_s) {
+__global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, const double *__restrict__ x_dev, uint32_t k0,
+                                            uint32_t k1, uint32_t stream, const float2 *__restrict__ twiddle,
+                                            float2 *__restrict__ part_a, float *__restrict__ part_s) {
     constexpr int P = LdsPitch<N>::v;
     constexpr int NP = (N / 2 + 1) * N;           // half plane: rows 0..N/2
     constexpr int PX = N * N / ST;                // pixels per thread
@@ -83,6 +83,10 @@ __global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, uint32_t k0, u
     __shared__ float2 sh[24];                     // subharmonic coefficients
     const int tid = threadIdx.x;
     for (int i = tid; i < N; i += ST) tw[i] = twiddle[i];
+    if (x_dev) {                                   // D/r0 from device memory: r0 = (N/2) / (D/r0) px
+        const double r0 = (N / 2.0) / *x_dev;
+        amp = (float)(0.15165750888103102 * pow(r0, -5.0 / 6.0) * pow((double)N, 5.0 / 6.0));   // sqrt(0.023)
+    }
 
     // this workgroup's sums, kept in its own slice of the partials (each
     // thread always adds to the same entries, so no other thread touches them)
@@ -250,8 +254,8 @@ __global__ __launch_bounds__(256) void k_stf_finalize(int nwg, double inv_screen
 
 template <int N>
 hipError_t launch_stf_t(const StfArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_stf<N>), dim3(a.nwg), dim3(ST), 0, st, a.pairs, a.amp, a.k0, a.k1, a.stream, a.twiddle,
-                       a.part_a, a.part_s);
+    hipLaunchKernelGGL((k_stf<N>), dim3(a.nwg), dim3(ST), 0, st, a.pairs, a.amp, a.x_dev, a.k0, a.k1, a.stream,
+                       a.twiddle, a.part_a, a.part_s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     constexpr int NP = (N / 2 + 1) * N;
@@ -260,7 +264,146 @@ hipError_t launch_stf_t(const StfArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Seeing fit of one cube per workgroup (FP64).  The frame-group sums of the
+// box (see k_ratio) give m = <I> and P = <|I|^2>; the ratio
+// eps = (|m|^2 - P/F) / (P (1 - 1/F)) is averaged over the annuli
+// q - 1/2 <= |u| < q + 1/2 of the half plane (uy > 0, or uy = 0 < ux).  For
+// each model point j the same annuli of
+//   sum_k |w(k)|^2 P(u - k) rho_j(u - k) / sum_k |w(k)|^2 P(u - k),
+// rho_j = |<OTF>|^2 / <|OTF|^2> (rho_j(0) left out; |w|^2 = 1/4, 1/16 per
+// axis at offsets 0, +-1 with the taper, only k = 0 without) give the model
+// curve; the cube's D/r0 minimises the squared distance (first minimum, then
+// the vertex of the parabola through it and its neighbours, in grid index).
+// Sums over annuli and candidates run in a fixed order.
+template <int N>
+__global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
+    constexpr int MAXE = (RATIO_MAX_BINS + 3) * (2 * RATIO_MAX_BINS + 5);
+    __shared__ double mre[MAXE], mim[MAXE], pw[MAXE], val[MAXE];
+    __shared__ double eq[RATIO_MAX_BINS], cq[RATIO_MAX_BINS];
+    __shared__ double err[RATIO_MAX_POINTS];
+    const int cube = blockIdx.x, tid = threadIdx.x;
+    const int B = a.B, bw = 2 * B + 1, nbox = (B + 1) * bw, Q = a.Q, F = a.F;
+    const double invF = 1.0 / F;
+    for (int e = tid; e < nbox; e += 256) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < a.nchunks; ++k) {
+            const float *pp = a.part + ((size_t)(cube * a.nchunks + k) * nbox + e) * 3;
+            s0 += (double)pp[0];
+            s1 += (double)pp[1];
+            s2 += (double)pp[2];
+        }
+        mre[e] = s0 * invF;
+        mim[e] = s1 * invF;
+        pw[e] = s2 * invF;
+    }
+    __syncthreads();
+    // annulus of a box entry of the half plane, 0 if none
+    auto bin_of = [&](int e) {
+        const int uy = e / bw, ux = e % bw - B;
+        if (uy == 0 && ux <= 0) return 0;
+        const int q = (int)floor(sqrt((double)(uy * uy + ux * ux)) + 0.5);
+        return q <= Q ? q : 0;
+    };
+    // P at (vy, vx), |vx| <= B, -1 <= vy <= B (P(-v) = P(v))
+    auto p_at = [&](int vy, int vx) {
+        if (vy < 0) { vy = -vy; vx = -vx; }
+        return pw[vy * bw + vx + B];
+    };
+    for (int e = tid; e < nbox; e += 256) {
+        double v = 0.0;
+        if (bin_of(e)) {
+            const double m2 = mre[e] * mre[e] + mim[e] * mim[e], P = pw[e];
+            v = P > 0.0 ? (m2 - P * invF) / (P * (1.0 - invF)) : 0.0;
+        }
+        val[e] = v;
+    }
+    __syncthreads();
+    if (tid < Q) {
+        double sum = 0.0;
+        int cnt = 0;
+        for (int e = 0; e < nbox; ++e)
+            if (bin_of(e) == tid + 1) { sum += val[e]; ++cnt; }
+        eq[tid] = sum / cnt;
+        if (a.curves) a.curves[(size_t)cube * Q + tid] = eq[tid];
+    }
+    __syncthreads();
+    const int kr = a.window ? 1 : 0;
+    for (int j = 0; j < a.J; ++j) {
+        const double *S = a.tab_s + (size_t)j * N * N;
+        const double2 *A = a.tab_a + (size_t)j * N * N;
+        for (int e = tid; e < nbox; e += 256) {
+            double v = 0.0;
+            if (bin_of(e)) {
+                const int uy = e / bw, ux = e % bw - B;
+                double num = 0.0, den = 0.0;
+                for (int ky = -kr; ky <= kr; ++ky)
+                    for (int kx = -kr; kx <= kr; ++kx) {
+                        const int vy = uy - ky, vx = ux - kx;
+                        if (vy == 0 && vx == 0) continue;
+                        const double wt = (kr ? (ky ? 0.0625 : 0.25) * (kx ? 0.0625 : 0.25) : 1.0) * p_at(vy, vx);
+                        const int g = (vy & (N - 1)) * N + (vx & (N - 1));
+                        const double sv = S[g];
+                        const double2 av = A[g];
+                        num += wt * (sv > 0.0 ? (av.x * av.x + av.y * av.y) / sv : 0.0);
+                        den += wt;
+                    }
+                v = den > 0.0 ? num / den : 0.0;
+            }
+            val[e] = v;
+        }
+        __syncthreads();
+        if (tid < Q) {
+            double sum = 0.0;
+            int cnt = 0;
+            for (int e = 0; e < nbox; ++e)
+                if (bin_of(e) == tid + 1) { sum += val[e]; ++cnt; }
+            cq[tid] = sum / cnt;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double e2 = 0.0;
+            for (int q = 0; q < Q; ++q) e2 += (eq[q] - cq[q]) * (eq[q] - cq[q]);
+            err[j] = e2;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int jm = 0;
+        for (int j = 1; j < a.J; ++j)
+            if (err[j] < err[jm]) jm = j;
+        double t = jm;
+        if (jm > 0 && jm < a.J - 1) {
+            const double den = err[jm - 1] - 2.0 * err[jm] + err[jm + 1];
+            if (den > 0.0) t = jm + 0.5 * (err[jm - 1] - err[jm + 1]) / den;
+        }
+        a.x[1 + cube] = a.lo * pow(a.hi / a.lo, t / (a.J - 1.0));
+    }
+}
+
+// D / <r0> = 1 / <1 / (D/r0)> over the cubes, into x[0].
+__global__ void k_seeing_mean(int cubes, double *x) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int c = 0; c < cubes; ++c) s += 1.0 / x[1 + c];
+        x[0] = cubes / s;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_seeing_fit(const SeeingFitArgs &a, hipStream_t st) {
+    if (a.cubes < 1 || a.Q < 2 || a.Q > RATIO_MAX_BINS || a.B != a.Q + 2 || a.J < 3 || a.J > RATIO_MAX_POINTS ||
+        a.F < 2 || a.nchunks < 1)
+        return hipErrorInvalidValue;
+    if (a.N == 128)
+        hipLaunchKernelGGL((k_seeing_fit<128>), dim3(a.cubes), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_seeing_fit<64>), dim3(a.cubes), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seeing_mean, dim3(1), dim3(64), 0, st, a.cubes, a.x);
+    return hipGetLastError();
+}
 
 hipError_t launch_stf(const StfArgs &a, hipStream_t st) {
     if (a.pairs < 1 || a.nwg < 1) return hipErrorInvalidValue;

@@ -70,6 +70,32 @@ struct NoiseArgs {
 };
 hipError_t launch_noise(const NoiseArgs &a, hipStream_t st);
 
+// Seeing by the spectral ratio (see k_ingest.hip, k_stf.hip).
+constexpr int RATIO_MAX_BINS = 24;        // annuli q = 1..bins
+constexpr int RATIO_MAX_POINTS = 256;     // model points of the D/r0 grid
+struct RatioArgs {
+    int N = 0;
+    bool f32 = false, vec = false;
+    const void *frames = nullptr;         // [F][H][pitch]
+    int F = 0, H = 0, cubes = 0, nx = 0, chunk_frames = 0, window = 0, B = 0;
+    int64_t pitch = 0;
+    float inv_wsum = 0.f;
+    const float2 *twiddle = nullptr;
+    const float *hann = nullptr;
+    float *part = nullptr;                // [cubes * chunks][(B + 1)(2B + 1)][3]
+};
+hipError_t launch_ratio(const RatioArgs &a, hipStream_t st);
+struct SeeingFitArgs {
+    int N = 0, cubes = 0, nchunks = 0, F = 0, B = 0, Q = 0, J = 0, window = 0;
+    double lo = 0.0, hi = 0.0;            // D/r0 grid lo (hi/lo)^(j/(J-1))
+    const float *part = nullptr;          // from launch_ratio
+    const double *tab_s = nullptr;        // [J][N][N] model <|OTF|^2>
+    const double2 *tab_a = nullptr;       // [J][N][N] model <OTF>
+    double *x = nullptr;                  // [1 + cubes]: burst, then per cube
+    double *curves = nullptr;             // [cubes][Q] ratio curves, or null
+};
+hipError_t launch_seeing_fit(const SeeingFitArgs &a, hipStream_t st);
+
 // Model speckle transfer function by Monte Carlo over Kolmogorov screens
 // (see k_stf.hip): screens = 2 pairs; nwg workgroups each sum their pairs'
 // <OTF> and <|OTF|^2> over the half plane into part_a / part_s; stf (and
@@ -84,6 +110,7 @@ struct StfArgs {
     float *part_s = nullptr;              // [nwg][N/2 + 1][N]
     double *stf = nullptr;                // [N][N]
     double2 *mean_otf = nullptr;          // [N][N] or null
+    const double *x_dev = nullptr;        // D/r0 in device memory (then amp is computed from it), or null
 };
 hipError_t launch_stf(const StfArgs &a, hipStream_t st);
 

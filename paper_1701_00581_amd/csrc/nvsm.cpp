@@ -997,6 +997,12 @@ nvsm_status nvsm_stream_finish(nvsm_context *ctx, const nvsm_params *p, int32_t 
     return NVSM_OK;
 }
 
+// sqrt(0.023) r0^(-5/6) N^(5/6) with r0 = (N/2) / (D/r0) px (see k_stf.hip)
+static float screen_amp(int N, double d_over_r0) {
+    const double r0 = (N / 2.0) / d_over_r0;
+    return (float)(std::sqrt(0.023) * std::pow(r0, -5.0 / 6.0) * std::pow((double)N, 5.0 / 6.0));
+}
+
 static nvsm_status stf_sizes(const nvsm_params *p, int32_t screens, int *pairs, int *nwg, size_t *part_a,
                              size_t *part_s, std::string *msg) {
     nvsm_status s = check_params(p, msg);
@@ -1040,10 +1046,9 @@ nvsm_status nvsm_model_stf(nvsm_context *ctx, const nvsm_params *p, double d_ove
     DevicePlan *dp;
     if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;
     const int N = p->patch;
-    const double r0 = (N / 2.0) / d_over_r0;
     StfArgs a;
     a.N = N; a.pairs = pairs; a.nwg = nwg;
-    a.amp = (float)(std::sqrt(0.023) * std::pow(r0, -5.0 / 6.0) * std::pow((double)N, 5.0 / 6.0));
+    a.amp = screen_amp(N, d_over_r0);
     a.k0 = (uint32_t)(seed & 0xffffffffu); a.k1 = (uint32_t)(seed >> 32); a.stream = 0;
     a.twiddle = dp->twiddle;
     a.part_a = (float2 *)workspace;
@@ -1051,6 +1056,126 @@ nvsm_status nvsm_model_stf(nvsm_context *ctx, const nvsm_params *p, double d_ove
     a.stf = stf; a.mean_otf = (double2 *)mean_otf;
     hipError_t e = launch_stf(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "model stf");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_seeing_default_params(nvsm_seeing_params *out) {
+    if (!out) return NVSM_ERR_INVALID_ARG;
+    out->screens = 1000;
+    out->points = 40;
+    out->d_over_r0_min = 2.0;
+    out->d_over_r0_max = 50.0;
+    out->bins = 12;
+    out->reserved = 0;
+    out->seed = 1;
+    return NVSM_OK;
+}
+
+namespace {
+
+struct SeeingSizes {
+    int cubes = 0, nx = 0, nchunks = 0, box = 0, pairs = 0, nwg = 0;
+    size_t part_a = 0, part_s = 0, tab_s = 0, tab_a = 0, ratio = 0;
+    size_t total() const { return part_a + part_s + tab_s + tab_a + ratio; }
+};
+
+nvsm_status seeing_sizes(const nvsm_params *p, const nvsm_seeing_params *sp, int32_t H, int32_t W, int32_t F,
+                         SeeingSizes *z, std::string *msg) {
+    if (!sp) { *msg = "seeing params is NULL"; return NVSM_ERR_INVALID_ARG; }
+    nvsm_status s = stf_sizes(p, sp->screens, &z->pairs, &z->nwg, &z->part_a, &z->part_s, msg);
+    if (s != NVSM_OK) return s;
+    const int N = p->patch;
+    if (sp->points < 3 || sp->points > RATIO_MAX_POINTS) { *msg = "points must be in [3, 256]"; return NVSM_ERR_INVALID_ARG; }
+    if (!(sp->d_over_r0_min > 0.0 && sp->d_over_r0_min < sp->d_over_r0_max && sp->d_over_r0_max <= 1000.0)) {
+        *msg = "need 0 < d_over_r0_min < d_over_r0_max <= 1000";
+        return NVSM_ERR_INVALID_ARG;
+    }
+    if (sp->bins < 2 || sp->bins > std::min(RATIO_MAX_BINS, N / 4)) {
+        *msg = "bins must be in [2, min(24, N/4)]";
+        return NVSM_ERR_INVALID_ARG;
+    }
+    if (F < 2) { *msg = "the spectral ratio needs F >= 2"; return NVSM_ERR_SHAPE; }
+    if (H < N || W < N) { *msg = "frames smaller than one cube"; return NVSM_ERR_SHAPE; }
+    if ((int64_t)H * W > ((int64_t)1 << 31) - 1) { *msg = "frame too large"; return NVSM_ERR_SHAPE; }
+    z->nx = W / N;
+    z->cubes = (H / N) * z->nx;
+    z->nchunks = (F + CHUNK_FRAMES - 1) / CHUNK_FRAMES;
+    const int B = sp->bins + 2;
+    z->box = (B + 1) * (2 * B + 1);
+    z->tab_s = align_up((size_t)sp->points * N * N * 8);
+    z->tab_a = align_up((size_t)sp->points * N * N * 16);
+    z->ratio = align_up((size_t)z->cubes * z->nchunks * z->box * 3 * 4);
+    return NVSM_OK;
+}
+
+}  // namespace
+
+nvsm_status nvsm_seeing_plan(const nvsm_params *p, const nvsm_seeing_params *sp, int32_t H, int32_t W, int32_t F,
+                             size_t *ws_bytes, int32_t *cubes) {
+    if (!ws_bytes || !cubes) return NVSM_ERR_INVALID_ARG;
+    std::string msg;
+    SeeingSizes z;
+    nvsm_status s = seeing_sizes(p, sp, H, W, F, &z, &msg);
+    if (s != NVSM_OK) return s;
+    *ws_bytes = z.total();
+    *cubes = z.cubes;
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_seeing(nvsm_context *ctx, const nvsm_params *p, const nvsm_seeing_params *sp, const void *frames,
+                        nvsm_dtype dtype, int32_t F, int32_t H, int32_t W, int64_t row_pitch, double *d_over_r0,
+                        double *stf, double *curves, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!frames || !d_over_r0 || !stf) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    std::string msg;
+    SeeingSizes z;
+    nvsm_status s = seeing_sizes(p, sp, H, W, F, &z, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    if (row_pitch < W) return fail(ctx, NVSM_ERR_SHAPE, "row_pitch < W");
+    if (!workspace || workspace_bytes < z.total()) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small");
+    DevicePlan *dp;
+    if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;
+    const int N = p->patch, J = sp->points;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)workspace;
+    float2 *part_a = (float2 *)w; w += z.part_a;
+    float *part_s = (float *)w; w += z.part_s;
+    double *tab_s = (double *)w; w += z.tab_s;
+    double2 *tab_a = (double2 *)w; w += z.tab_a;
+    float *ratio = (float *)w;
+    // model curves' tables, model points m = 0..J-1
+    StfArgs ma;
+    ma.N = N; ma.pairs = z.pairs; ma.nwg = z.nwg;
+    ma.k0 = (uint32_t)(sp->seed & 0xffffffffu); ma.k1 = (uint32_t)(sp->seed >> 32);
+    ma.twiddle = dp->twiddle; ma.part_a = part_a; ma.part_s = part_s;
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < J && e == hipSuccess; ++j) {
+        const double x = sp->d_over_r0_min * std::pow(sp->d_over_r0_max / sp->d_over_r0_min, j / (J - 1.0));
+        ma.amp = screen_amp(N, x);
+        ma.stream = (uint32_t)j;
+        ma.stf = tab_s + (size_t)j * N * N;
+        ma.mean_otf = tab_a + (size_t)j * N * N;
+        e = launch_stf(ma, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "seeing model");
+    RatioArgs ra;
+    ra.N = N; ra.f32 = dtype == NVSM_F32;
+    const size_t px = ra.f32 ? 4 : 2;
+    ra.vec = row_pitch % 4 == 0 && (uintptr_t)frames % (4 * px) == 0;
+    ra.frames = frames; ra.F = F; ra.H = H; ra.cubes = z.cubes; ra.nx = z.nx; ra.chunk_frames = CHUNK_FRAMES;
+    ra.window = p->window; ra.B = sp->bins + 2; ra.pitch = row_pitch;
+    ra.inv_wsum = (float)(1.0 / (p->window ? dp->h.hann_sum2 : (double)N * N));
+    ra.twiddle = dp->twiddle; ra.hann = dp->hann; ra.part = ratio;
+    if ((e = launch_ratio(ra, st)) != hipSuccess) return hip_fail(ctx, e, "seeing ratio");
+    SeeingFitArgs fa;
+    fa.N = N; fa.cubes = z.cubes; fa.nchunks = z.nchunks; fa.F = F; fa.B = sp->bins + 2; fa.Q = sp->bins; fa.J = J;
+    fa.window = p->window; fa.lo = sp->d_over_r0_min; fa.hi = sp->d_over_r0_max;
+    fa.part = ratio; fa.tab_s = tab_s; fa.tab_a = tab_a; fa.x = d_over_r0; fa.curves = curves;
+    if ((e = launch_seeing_fit(fa, st)) != hipSuccess) return hip_fail(ctx, e, "seeing fit");
+    // the burst's model STF at the estimate (read on the device), model point m = J
+    ma.amp = 0.f; ma.x_dev = d_over_r0; ma.stream = (uint32_t)J; ma.stf = stf; ma.mean_otf = nullptr;
+    if ((e = launch_stf(ma, st)) != hipSuccess) return hip_fail(ctx, e, "seeing stf");
     return NVSM_OK;
 }
 

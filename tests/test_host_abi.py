@@ -105,6 +105,24 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
         n = ctypes.c_size_t()
         assert L.nvsm_model_stf_plan(ctypes.byref(p), bad, ctypes.byref(n)) == _lib.NVSM_ERR_INVALID_ARG
     assert L.nvsm_model_stf(None, ctypes.byref(p), 10.0, 8, 1, None, None, None, 0, None) == _lib.NVSM_ERR_INVALID_ARG
+    # seeing: defaults, sizes and validation
+    sp = nv.seeing_default_params()
+    assert (sp.screens, sp.points, sp.bins) == (1000, 40, 12)
+    ws, cubes = nv.nvsm_seeing_plan(p, sp, 2160, 2560, 100)
+    assert cubes == 16 * 20
+    box = (12 + 3) * (2 * 12 + 5)
+    assert ws == (256 * 65 * 128 * 12 + 40 * 128 * 128 * 24 + 320 * 5 * box * 12)   # 5 frame groups of 20
+    n, c = ctypes.c_size_t(), ctypes.c_int32()
+    for field, bad in [("points", 2), ("points", 257), ("bins", 1), ("bins", 33), ("d_over_r0_min", 0.0),
+                       ("d_over_r0_max", 1.0), ("screens", 3)]:
+        spb = nv.seeing_default_params()
+        setattr(spb, field, bad)
+        assert L.nvsm_seeing_plan(ctypes.byref(p), ctypes.byref(spb), 2160, 2560, 100, ctypes.byref(n),
+                                  ctypes.byref(c)) == _lib.NVSM_ERR_INVALID_ARG, field
+    assert L.nvsm_seeing_plan(ctypes.byref(p), ctypes.byref(sp), 2160, 2560, 1, ctypes.byref(n),
+                              ctypes.byref(c)) == _lib.NVSM_ERR_SHAPE
+    assert L.nvsm_seeing_plan(ctypes.byref(p), ctypes.byref(sp), 100, 2560, 10, ctypes.byref(n),
+                              ctypes.byref(c)) == _lib.NVSM_ERR_SHAPE
     p = nv.default_params(128)
     assert L.nvsm_plan(ctypes.byref(p), 100, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 0, ctypes.byref(info)) == _lib.NVSM_ERR_SHAPE
