@@ -164,12 +164,19 @@ def _check(status, where, ctx=None):
         raise NvsmError(status, where, detail)
 
 
+def _set_fields(struct, kw):
+    names = {f[0] for f in type(struct)._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"{type(struct).__name__} has no field {k!r}")
+        setattr(struct, k, v)
+    return struct
+
+
 def default_params(patch, **kw):
     p = Params()
     _check(lib().nvsm_default_params(int(patch), ctypes.byref(p)), "nvsm_default_params")
-    for k, v in kw.items():
-        setattr(p, k, v)
-    return p
+    return _set_fields(p, kw)
 
 
 def nvsm_create(device=0):
@@ -344,9 +351,7 @@ def nvsm_model_stf(ctx, params, d_over_r0, screens, seed, stf, ws, mean_otf=None
 def seeing_default_params(**kw):
     sp = SeeingParams()
     _check(lib().nvsm_seeing_default_params(ctypes.byref(sp)), "nvsm_seeing_default_params")
-    for k, v in kw.items():
-        setattr(sp, k, v)
-    return sp
+    return _set_fields(sp, kw)
 
 
 def nvsm_seeing_plan(params, sp, H, W, F):

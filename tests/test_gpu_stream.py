@@ -109,6 +109,24 @@ def test_stream_groups_within_tolerance(torch_cuda, setup):
         assert nrm < BISPEC_TOL and mx < BISPEC_TOL
 
 
+def test_stream_least_squares_one_group_is_exact(torch_cuda, setup):
+    """With least-squares phase steps (phase_method 1) the stream's finish
+    runs the same solve: one group gives nvsm_reconstruct's image bit for bit."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    p = nv.default_params(128, v_radius=10, noise_bias=1, filter=1, phase_method=1, lsq_iters=4)
+    s = dict(setup, p=p)
+    img, _ = _stream(nv, torch, s, [F])
+    ref = torch.empty((H, W), device="cuda")
+    info = nv.nvsm_plan(p, H, W, F)
+    nv.nvsm_reconstruct(setup["ctx"], p, setup["d"], setup["stf"], ref,
+                        torch.empty(info.ws_reconstruct, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    same = torch.equal(img, ref)
+    say(f"[stream] least squares, one group: image identical={same}")
+    assert torch.isfinite(img).all() and same
+
+
 def test_stream_errors(torch_cuda, setup):
     import paper_1701_00581_amd as nv
     torch = torch_cuda

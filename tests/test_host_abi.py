@@ -137,6 +137,14 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
                              None, 0, None) == _lib.NVSM_ERR_INVALID_ARG
 
 
+def test_parameter_helpers_reject_unknown_fields():
+    with pytest.raises(TypeError):
+        nv.default_params(128, phase_methd=1)
+    with pytest.raises(TypeError):
+        nv.seeing_default_params(screen=10)
+    assert nv.default_params(128, lsq_iters=3).lsq_iters == 3
+
+
 def test_status_strings():
     for s in range(-6, 1):
         assert nv.status_string(s)
