@@ -287,7 +287,10 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int iters, const int *__
             const int lo = pass ? half : 0, n = pass ? nW - half : half;     // targets [lo, lo + n)
             for (int i = tid; i < 2 * n; i += LSQ_NT) acc[i] = 0ull;
             __syncthreads();
-            for (int w = wave; w < nW; w += LSQ_NWAVE) {
+            // W is ordered by |w|^2 and both sides of a sample are shorter than
+            // its w, so every target of segment w lies below w: the upper
+            // targets' pass needs only the segments from lo on (~52 % of S)
+            for (int w = (pass ? lo : 0) + wave; w < nW; w += LSQ_NWAVE) {
                 const int t0 = woff[w], t1 = woff[w + 1];
                 const double2 cw = e[w];
                 const bool own = (unsigned)(w - lo) < (unsigned)n;
