@@ -15,7 +15,7 @@
 // lanes per clock), so I(v) and I(w) stay out of LDS and the lanes of a
 // group are laid out for conflict-free gathers (see plan.cpp).
 // Accumulators stay in registers for the whole burst: a plain FP32 sum over
-// KB frames, folded into a Kahan (sum, compensation) pair every KB frames.
+// KB frames, folded into a compensated sum every KB frames (fold_carry).
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -66,6 +66,17 @@ __device__ __forceinline__ float fmac_bc(float acc, float b, float a) {
     asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
         : "+v"(acc) : "v"(b), "v"(a), "i"(K));
     return acc;
+}
+
+// Compensated (Kahan) fold of the block sum t into s.  The rounding error
+// of s + t, negated, is where the next block's sum starts: Kahan's
+// correction travels in the next addend instead of a register of its own,
+// so a slot holds two accumulators (s, t) rather than three.  The
+// compensated total at any fold is s + t.
+__device__ __forceinline__ void fold_carry(float &s, float &t) {
+    const float u = s + t;
+    t = t - (u - s);
+    s = u;
 }
 
 // Waits until at most n vector-memory loads of this wave are in flight
@@ -163,18 +174,19 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     // (((patch * n_items + g) * 4 + j) * K + k) * 64 + l
     // (wave-uniform base, so that only the lane offset needs a vector register)
     const size_t ls0 = (((size_t)patch * acc.n_items + g) * BS_WAVES + wave) * K * 64;
-    float2 t[NS], s[NS], c[NS];
+    // t: this block's sum (starting from the carried correction); s: the folded sum
+    float2 t[NS], s[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         t[k] = make_float2(0.f, 0.f);
         s[k] = make_float2(0.f, 0.f);
-        c[k] = make_float2(0.f, 0.f);
     }
     if (MODE == 1 && !acc.first) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             s[k] = acc.sum[ls0 + k * 64 + lane];
-            c[k] = acc.comp[ls0 + k * 64 + lane];
+            const float2 c = acc.comp[ls0 + k * 64 + lane];
+            t[k] = make_float2(-c.x, -c.y);
         }
     }
 
@@ -208,9 +220,8 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         if ((f + 1) % KB == 0 || f + 1 == F) {
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                kahan_add(s[k].x, c[k].x, t[k].x);
-                kahan_add(s[k].y, c[k].y, t[k].y);
-                t[k] = make_float2(0.f, 0.f);
+                fold_carry(s[k].x, t[k].x);
+                fold_carry(s[k].y, t[k].y);
             }
         }
         load_vals(fn, cw, bv);
@@ -230,7 +241,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             acc.sum[ls0 + k * 64 + lane] = s[k];
-            acc.comp[ls0 + k * 64 + lane] = c[k];
+            acc.comp[ls0 + k * 64 + lane] = make_float2(-t[k].x, -t[k].y);
         }
         return;
     }
@@ -245,9 +256,9 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         const float2 *Cp = acc.noise_c + (size_t)patch * FS;
         const float t2 = 2.0f * acc.noise_t[(size_t)patch * 2 + 1];
         const int wi = wo / (int)sizeof(float2);
-        // the means first, so the compensation registers are free for the loads
+        // the means first, so the block-sum registers are free for the loads
 #pragma unroll
-        for (int k = 0; k < NS; ++k) s[k] = make_float2((s[k].x - c[k].x) * inv, (s[k].y - c[k].y) * inv);
+        for (int k = 0; k < NS; ++k) s[k] = make_float2((s[k].x + t[k].x) * inv, (s[k].y + t[k].y) * inv);
         const float2 c_w = Cp[wi];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -262,7 +273,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const int o = oi[k * 64];
-            if (o >= 0) bo[o] = make_float2((s[k].x - c[k].x) * inv, (s[k].y - c[k].y) * inv);
+            if (o >= 0) bo[o] = make_float2((s[k].x + t[k].x) * inv, (s[k].y + t[k].y) * inv);
         }
     }
 }
@@ -319,13 +330,23 @@ __device__ __forceinline__ int item_at(const BurstTable &bt, int o, int n_items)
     return o;                                  // not reached: o < patches * n_items
 }
 
+// Waves per SIMD the kernel is built for.  With 16 slots it fits 96 VGPRs
+// (two accumulators per slot value, 16 LDS offsets), i.e. 5 waves per
+// SIMD; more waves hide more of the latency of the one LDS gather each slot
+// waits for (measured: 51.7 ms at 5 waves against 53.6 ms at 4 with 97
+// VGPRs, and 52.5 ms at 4 with all 16 gathers of a frame issued ahead).
+// The photon form then keeps one 8-byte value in scratch across the frame
+// loop (stored before it, reloaded after).  The persistent form
+// (k_bispec_queue) needs about 100 VGPRs and runs at 4.
+constexpr int bs_waves_per_eu(int K) { return K <= 16 ? 5 : 2; }
+
 // One workgroup per item.  MODE 0 writes the mean of all frames; MODE 1
 // adds a frame group to the running sums of acc (acc.mode 1 and 2); MODE 2
 // writes the mean less the photon-noise terms of acc.noise_c/noise_t.  Each
 // is a separate instantiation, so that the plain form carries none of the
 // others' registers.
 template <int N, int K, int MODE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? (MODE == 2 ? 4 : 3) : 2))) void k_bispec(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(bs_waves_per_eu(K)))) void k_bispec(
     const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
     const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
     float2 *__restrict__ bispec, int64_t s_count, const AccState acc) {
@@ -346,7 +367,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? (M
 // range and must be zero at launch.  Every workgroup ends after finding all
 // 8 ranges exhausted.
 template <int N, int K, int MODE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 3 : 2))) void k_bispec_queue(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : 2))) void k_bispec_queue(
     const BurstTable bt, const float2 *__restrict__ spec, int n_items, int total, const int *__restrict__ items,
     const int *__restrict__ group_xy, const int *__restrict__ slot, const int *__restrict__ out_idx,
     float2 *__restrict__ bispec, int64_t s_count, const AccState acc, int *__restrict__ queue) {
