@@ -79,6 +79,9 @@ __device__ __forceinline__ void fold_carry(float &s, float &t) {
     s = u;
 }
 
+// This lane's index in the wave.
+__device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
 // Waits until at most n vector-memory loads of this wave are in flight
 // (they complete in order).
 template <int n>
@@ -108,7 +111,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
                                             int64_t rec0, int F, int patch, int g, const int *__restrict__ it,
                                             const int *__restrict__ group_xy, const int *__restrict__ slot,
                                             const int *__restrict__ out_idx, float2 *__restrict__ bispec,
-                                            int64_t s_count, float invF, const AccState acc) {
+                                            int64_t s_count, const AccState acc) {
     constexpr int HALF = N / 2;
     constexpr int FS = SpecRows<N>::FS;
     constexpr int FB = FS * (int)sizeof(float2);               // bytes per stored frame
@@ -238,16 +241,20 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
 
     if (MODE == 1 && acc.mode == 1) {
         // keep the running (sum, compensation) for the next frame group
+        const int lane_e = lane_id();
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            acc.sum[ls0 + k * 64 + lane] = s[k];
-            acc.comp[ls0 + k * 64 + lane] = make_float2(-t[k].x, -t[k].y);
+            acc.sum[ls0 + k * 64 + lane_e] = s[k];
+            acc.comp[ls0 + k * 64 + lane_e] = make_float2(-t[k].x, -t[k].y);
         }
         return;
     }
-    const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane;
+    // (the lane index and 1/F are formed again here, so that neither keeps
+    // a register through the frame loop)
+    const int lane_e = lane_id();
+    const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane_e;
     float2 *bo = bispec + (size_t)patch * s_count;
-    const float inv = MODE == 1 ? acc.inv_total : invF;
+    const float inv = MODE == 1 ? acc.inv_total : 1.0f / (float)F;
     if constexpr (MODE == 2) {
         // photon-noise terms: B -= C(w) + conj C(v) + conj C(w - v) - 2T,
         // C of the patch in the record layout of the spectra (the slot
@@ -283,14 +290,14 @@ template <int N, int K, int Q, int MODE>
 __device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *lds1, const float2 *spec,
                                                 int64_t rec0, int F, int patch, int g, const int *it, const int *group_xy,
                                                 const int *slot, const int *out_idx, float2 *bispec,
-                                                int64_t s_count, float invF, const AccState &acc) {
+                                                int64_t s_count, const AccState &acc) {
     if constexpr (Q > 0) {
         if (nq == Q)
             bispec_item<N, K, 4 * Q, MODE>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
-                                     invF, acc);
+                                     acc);
         else
             bispec_dispatch<N, K, Q - 1, MODE>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
-                                         s_count, invF, acc);
+                                         s_count, acc);
     }
 }
 
@@ -304,11 +311,10 @@ __device__ __forceinline__ void bispec_one(int L, float2 *lds0, float2 *lds1, co
     const int b = burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; });
     const int F = bt.b[b].F;
     const int64_t rec0 = bt.b[b].spec0 + (int64_t)(patch - bt.b[b].patch0) * F;
-    const float invF = 1.0f / (float)F;
     const int *it = items + g * BS_ITEM_INTS;
     const int nq = __builtin_amdgcn_readfirstlane(it[8]) >> 2;   // the item's slots per wave / 4
     bispec_dispatch<N, K, K / 4, MODE>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
-                                 s_count, invF, acc);
+                                 s_count, acc);
 }
 
 // Item of position o in the launch order.  The order takes, for each XCD
@@ -334,7 +340,8 @@ __device__ __forceinline__ int item_at(const BurstTable &bt, int o, int n_items)
 // (two accumulators per slot value, 16 LDS offsets), i.e. 5 waves per
 // SIMD; more waves hide more of the latency of the one LDS gather each slot
 // waits for (measured: 51.7 ms at 5 waves against 53.6 ms at 4 with 97
-// VGPRs, and 52.5 ms at 4 with all 16 gathers of a frame issued ahead).
+// VGPRs, and 52.5 ms at 4 with all 16 gathers of a frame issued ahead; at 5
+// waves a second gather in flight gains nothing).
 // The photon form then keeps one 8-byte value in scratch across the frame
 // loop (stored before it, reloaded after).  The persistent form
 // (k_bispec_queue) needs about 100 VGPRs and runs at 4.

@@ -182,6 +182,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
         double tx[WPW], ty[WPW];
 #pragma unroll
         for (int m = 0; m < WPW; ++m) {
+            // (wave-uniform: most shells give a wave one w, and the second
+            // one's reductions are then skipped; not with 8 samples per
+            // lane, where the branch costs the registers of 4 waves per SIMD)
+            if (TPL <= 4 && m > 0 && r.w[m] < 0) {
+                tx[m] = ty[m] = 0.0;
+                continue;
+            }
             tx[m] = wave_total_lane63(zx[m]);
             ty[m] = wave_total_lane63(zy[m]);
         }
