@@ -229,10 +229,26 @@ def frames_dtype(frames):
     raise TypeError("frames must be uint16 (or int16 holding uint16 bits) or float32")
 
 
+def _row_pitch(frames, row_pitch=None):
+    """Row pitch (elements) of a frames tensor laid out as [F][H][pitch]
+    with unit stride along x.  Views of such a buffer (a crop in x or y,
+    a frame range) qualify; other layouts (transposed, strided in x, every
+    other frame) are rejected before any call.  An explicit row_pitch
+    states the layout of the memory behind the pointer instead."""
+    if row_pitch is not None:
+        return int(row_pitch)
+    F, H, W = frames.shape
+    pitch = frames.stride(1)
+    if (W > 1 and frames.stride(2) != 1) or pitch < W or (F > 1 and frames.stride(0) != H * pitch):
+        raise ValueError(f"frames must be a [F][H][pitch] buffer with unit x stride; got shape "
+                         f"{tuple(frames.shape)} strides {tuple(frames.stride())}")
+    return pitch
+
+
 def nvsm_accumulate(ctx, params, frames, power, mean_spec, mu, bispec, workspace, stream=None,
                     row_pitch=None):
     F, H, W = frames.shape
-    pitch = frames.stride(1) if row_pitch is None else row_pitch
+    pitch = _row_pitch(frames, row_pitch)
     st = lib().nvsm_accumulate(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W, pitch,
                                _ptr(power), _ptr(mean_spec), _ptr(mu), _ptr(bispec), _ptr(workspace),
                                workspace.numel() * workspace.element_size(), _stream(stream))
@@ -256,7 +272,7 @@ def nvsm_synthesize(ctx, params, H, W, amp, phasor, mu, patches_out, out, worksp
 
 def nvsm_reconstruct(ctx, params, frames, stf, out, workspace, stream=None, row_pitch=None):
     F, H, W = frames.shape
-    pitch = frames.stride(1) if row_pitch is None else row_pitch
+    pitch = _row_pitch(frames, row_pitch)
     st = lib().nvsm_reconstruct(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W, pitch,
                                 _ptr(stf), _ptr(out), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream))
@@ -269,7 +285,7 @@ def _bursts(bursts):
     arr = (Burst * len(bursts))()
     for i, (frames, stf, out) in enumerate(bursts):
         F, H, W = frames.shape
-        arr[i] = Burst(_ptr(frames), F, H, W, frames.stride(1), _ptr(stf), _ptr(out))
+        arr[i] = Burst(_ptr(frames), F, H, W, _row_pitch(frames), _ptr(stf), _ptr(out))
     return arr
 
 
@@ -296,7 +312,7 @@ def nvsm_reconstruct_batch(ctx, params, bursts, workspace, stream=None):
 def nvsm_autotune(ctx, params, frames, workspace, stream=None, row_pitch=None):
     """(slots per wave, form) chosen for params after timing the candidates."""
     F, H, W = frames.shape
-    pitch = frames.stride(1) if row_pitch is None else row_pitch
+    pitch = _row_pitch(frames, row_pitch)
     k, f = ctypes.c_int32(), ctypes.c_int32()
     st = lib().nvsm_autotune(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W, pitch,
                              _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream),
@@ -323,7 +339,7 @@ def _nbytes(t):
 
 def nvsm_stream_add(ctx, params, frames, frames_before, total_frames, state, ws, stream=None, row_pitch=None):
     G, H, W = frames.shape
-    pitch = frames.stride(1) if row_pitch is None else row_pitch
+    pitch = _row_pitch(frames, row_pitch)
     _check(lib().nvsm_stream_add(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), G, H, W, pitch,
                                  int(frames_before), int(total_frames), _ptr(state), _nbytes(state), _ptr(ws),
                                  _nbytes(ws), _stream(stream)), "nvsm_stream_add", ctx)
@@ -368,8 +384,9 @@ def nvsm_seeing(ctx, params, sp, frames, d_over_r0, stf, ws, curves=None, stream
     float64 [1 + cubes]; stf: device float64 [N][N]; curves: optional device
     float64 [cubes][bins]."""
     F, H, W = frames.shape
+    pitch = _row_pitch(frames)
     _check(lib().nvsm_seeing(ctx, ctypes.byref(params), ctypes.byref(sp), _ptr(frames), frames_dtype(frames), F, H, W,
-                             frames.stride(1), _ptr(d_over_r0), _ptr(stf), _ptr(curves), _ptr(ws), _nbytes(ws),
+                             pitch, _ptr(d_over_r0), _ptr(stf), _ptr(curves), _ptr(ws), _nbytes(ws),
                              _stream(stream)), "nvsm_seeing", ctx)
 
 

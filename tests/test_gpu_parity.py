@@ -100,6 +100,53 @@ def test_ragged_crop_accumulate(torch_cuda):
     _check_accumulate(s, fr, p, list(range(12)), S, "crop")
 
 
+@pytest.mark.parametrize("F,dtype,pad", [(1, "u16", 0), (2, "f32", 8), (3, "u16", 5)])
+def test_few_frames_strided_rows_clamped_patch(torch_cuda, F, dtype, pad):
+    """Degenerate frame counts (one frame: the bispectrum is a single
+    triple product and every closure is exact; two and three frames: one
+    transform pair with and without a partner), rows with a pitch wider
+    than the image (a strided view), scalar pixel loads (odd width), and a
+    second patch clamped to x0 = 3 that overlaps the first almost whole.
+    N = 128, R = 12, Hann taper."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    H, W = 128, 131
+    say(f"case few frames F={F} {dtype} pitch W+{pad}: accumulate")
+    fr = burst("burst1024", F=3, H=H, W=W)[:F]
+    if dtype == "f32":
+        fr = fr.astype(np.float32)
+    p = nv.default_params(128, v_radius=12)
+    s = _session(p, H, W, F)
+    assert s.info.patches == 2
+    big = np.zeros((F, H, W + pad), fr.dtype)
+    big[:, :, :W] = fr
+    d = to_device(big)[:, :, :W]
+    assert d.stride(1) == W + pad
+    s.accumulate(d)
+    torch.cuda.synchronize()
+    Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+    _check_accumulate(s, fr, p, [0, 1], S, f"F={F}")
+    if F != 1:
+        return
+    # one frame: the whole path against the oracle
+    st = stf("burst1024", screens=100)
+    s.solve(torch.from_numpy(st).cuda())
+    s.synthesize()
+    torch.cuda.synchronize()
+    ref = oracle.reconstruct(fr, oparams(p), st)
+    ph = as_complex(s.phasor)
+    for k, key in enumerate([(0, 0), (0, 1)]):
+        rms, mx = phase_rms(ph[k], ref["tiles"][key]["phasor"])
+        say(f"[F=1] patch {k}: phase rms {rms:.2e} max {mx:.2e}")
+        assert rms <= PHASE_RMS_TOL
+    img = s.image.cpu().numpy()
+    o = ref["image"]
+    inner = (slice(16, H - 16), slice(16, W - 16))
+    merr = np.linalg.norm(img[inner] - o[inner]) / np.linalg.norm(o[inner] - o[inner].mean())
+    say(f"[F=1] mosaic {merr:.2e}")
+    assert merr <= MOSAIC_TOL
+
+
 def test_solve_on_identical_inputs(torch_cuda):
     """The FP64 solve alone: both sides get the same FP32-rounded power,
     mean spectrum and bispectrum (computed by the oracle)."""

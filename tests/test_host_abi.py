@@ -145,6 +145,25 @@ def test_parameter_helpers_reject_unknown_fields():
     assert nv.default_params(128, lsq_iters=3).lsq_iters == 3
 
 
+def test_frame_layouts_other_than_F_H_pitch_are_rejected_before_any_call():
+    """The C ABI reads frames as [F][H][pitch]: views that keep that layout
+    pass their row pitch; transposed, x-strided or frame-strided views are
+    refused by the binding before the library is called."""
+    import torch
+    base = torch.zeros(3, 70, 90, dtype=torch.int16)
+    assert _lib._row_pitch(base) == 90
+    assert _lib._row_pitch(base[:, :, :81]) == 90          # crop in x: pitch 90
+    assert _lib._row_pitch(base[1:, :, :]) == 90           # a frame range
+    assert _lib._row_pitch(base[:, ::2, :]) == 180         # every other row: pitch 180
+    for bad in (base.transpose(1, 2), base[:, :, ::2], base[::2], base[:, :40, :]):
+        with pytest.raises(ValueError):
+            _lib._row_pitch(bad)
+    p = nv.default_params(64)
+    with pytest.raises(ValueError):
+        nv.nvsm_accumulate(None, p, base.transpose(1, 2), None, None, None, None, None)
+    assert _lib._row_pitch(base.transpose(1, 2), row_pitch=90) == 90
+
+
 def test_status_strings():
     for s in range(-6, 1):
         assert nv.status_string(s)
