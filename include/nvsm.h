@@ -14,7 +14,9 @@
  *
  * Conventions used throughout:
  *  - frames are [F][H][W] with x (the W axis) fastest; rows are
- *    row_pitch elements apart (row_pitch >= W);
+ *    row_pitch elements apart (W <= row_pitch <= 2^30 / N); one call takes at most
+ *    F * (N/2 + 16) * N * 8 < 2^31 frames (26214 for N = 128, 87381 for
+ *    N = 64; more gives NVSM_ERR_SHAPE);
  *  - a frequency u = (ux, uy) is stored at [uy mod N][ux mod N] of an
  *    N x N array ("DFT order");
  *  - the forward transform is exp(-2 pi i u.x / N), unnormalised;

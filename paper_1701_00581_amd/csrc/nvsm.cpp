@@ -100,6 +100,12 @@ nvsm_status check_params(const nvsm_params *p, std::string *msg) {
 
 nvsm_status check_shape(const nvsm_params *p, int H, int W, int F, std::string *msg) {
     if (F < 1) { *msg = "F must be >= 1"; return NVSM_ERR_SHAPE; }
+    // the bispectrum kernel addresses one patch's F spectrum records
+    // (rows -16 .. N/2-1 of N complex64) with 32-bit byte offsets
+    if ((int64_t)F * (p->patch / 2 + 16) * p->patch * 8 > (int64_t)INT32_MAX) {
+        *msg = "too many frames in one call: F * (N/2 + 16) * N * 8 must stay below 2^31";
+        return NVSM_ERR_SHAPE;
+    }
     if (H < p->patch || W < p->patch) { *msg = "frames smaller than a patch"; return NVSM_ERR_SHAPE; }
     if ((int64_t)H * W > ((int64_t)1 << 31) - 1) { *msg = "frame too large"; return NVSM_ERR_SHAPE; }
     return NVSM_OK;
@@ -456,10 +462,16 @@ nvsm_status hip_fail(nvsm_context *ctx, hipError_t e, const char *where) {
     return fail(ctx, NVSM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// The transform kernels address a patch's pixels in a frame with 32-bit
+// byte offsets from the patch origin: N rows of row_pitch elements of up
+// to 4 bytes must stay below 2^32.
+int64_t max_row_pitch(int N) { return ((int64_t)1 << 30) / N; }
+
 nvsm_status check_burst(const nvsm_params *p, const BurstIn &bi, std::string *msg) {
     nvsm_status s = check_shape(p, bi.H, bi.W, bi.F, msg);
     if (s != NVSM_OK) return s;
     if (bi.pitch < bi.W) { *msg = "row_pitch < W"; return NVSM_ERR_SHAPE; }
+    if (bi.pitch > max_row_pitch(p->patch)) { *msg = "row_pitch too large (N * row_pitch must stay below 2^30)"; return NVSM_ERR_SHAPE; }
     return NVSM_OK;
 }
 
@@ -1133,6 +1145,7 @@ nvsm_status nvsm_seeing(nvsm_context *ctx, const nvsm_params *p, const nvsm_seei
     nvsm_status s = seeing_sizes(p, sp, H, W, F, &z, &msg);
     if (s != NVSM_OK) return fail(ctx, s, msg);
     if (row_pitch < W) return fail(ctx, NVSM_ERR_SHAPE, "row_pitch < W");
+    if (row_pitch > max_row_pitch(p->patch)) return fail(ctx, NVSM_ERR_SHAPE, "row_pitch too large (N * row_pitch must stay below 2^30)");
     if (!workspace || workspace_bytes < z.total()) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small");
     DevicePlan *dp;
     if ((s = get_plan(ctx, p, &dp)) != NVSM_OK) return s;

@@ -276,6 +276,13 @@ def test_error_paths(torch_cuda):
         a = list(args(ws.data_ptr(), ws.numel()))
         a[3] = 7     # bad dtype
         assert L.nvsm_reconstruct(*a) == _lib.NVSM_ERR_INVALID_ARG
+        a = list(args(ws.data_ptr(), ws.numel()))
+        a[7] = (1 << 30) // 128 + 1   # pitch beyond 32-bit pixel offsets
+        assert L.nvsm_reconstruct(*a) == _lib.NVSM_ERR_SHAPE
+        assert "row_pitch" in nv.nvsm_last_error(ctx)
+        a = list(args(ws.data_ptr(), ws.numel()))
+        a[4] = 26215  # frame count beyond 32-bit spectrum offsets
+        assert L.nvsm_reconstruct(*a) == _lib.NVSM_ERR_SHAPE
         assert torch.count_nonzero(out).item() == 0
         torch.cuda.synchronize()
     finally:

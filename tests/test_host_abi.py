@@ -77,6 +77,12 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
     p = nv.default_params(128)
     p.phase_method = 2
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_NOT_IMPLEMENTED
+    # frame counts: 1 .. the largest whose spectrum records one patch spans in 32-bit offsets
+    for N, fmax in ((128, 26214), (64, 87381)):
+        p = nv.default_params(N)
+        for F, want in ((0, _lib.NVSM_ERR_SHAPE), (1, _lib.NVSM_OK), (fmax, _lib.NVSM_OK),
+                        (fmax + 1, _lib.NVSM_ERR_SHAPE)):
+            assert L.nvsm_plan(ctypes.byref(p), N, N, F, ctypes.byref(info)) == want, (N, F)
     p = nv.default_params(128)
     p.phase_method = 1
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_OK
