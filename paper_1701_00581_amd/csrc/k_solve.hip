@@ -16,6 +16,7 @@
 // computed, so only LDS latency sits on the dependency chain.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "plan.hpp"
 
 namespace nvsm {
 
@@ -238,27 +239,35 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
 //   u as the side v:       conj e(w - v) e(w) B
 // conjugated where the sample holds -u, and the new phasor
 // e'(u) = unit(unit(g) + e(u)), all from the previous step's table (Jacobi).
-// The samples are read in storage order (one w per wave, its samples over
-// the lanes), so B streams contiguously; each contribution is added to the
-// accumulator of its target in LDS.  The accumulators of all targets do not
-// fit beside the table, so a step makes two passes, each for half of the
-// targets.  The adds are 64-bit fixed point (scale 2^60 / sum |Re B| + |Im B|
-// of the patch, which bounds every |g| below 2^62): integer sums do not
-// depend on the order of the adds, so the result is reproducible bit for
-// bit.  Thread i keeps e'(u) for u = i + 1024 m in registers until both
-// passes are done; then the table is rewritten between two barriers.
+// The samples are read once per step in storage order (one w per wave, its
+// samples over the lanes), so B streams contiguously; each contribution is
+// added to the accumulator of its target in LDS.  W is ordered by |w|^2
+// and both sides of a sample are shorter than its w (|w - v| >= |w| - R),
+// so as the segments advance, the entries below some prefix are targeted by
+// no later segment: the segments are taken in rounds of LSQ_ROUND, and
+// after each round the entries that have just become final (a prefix of W
+// beyond the inner disk, from the plan's table lsq_fin) are turned into new
+// phasors and their accumulators cleared.  So accumulators are needed only
+// for the inner disk (|u| <= R, the sides v of every segment, final at the
+// end) and a ring over the live annulus, which fit in LDS beside the table.
+// The adds are 64-bit fixed point (scale 2^60 / sum |Re B| + |Im B| of the
+// patch, which bounds every |g| below 2^62): integer sums do not depend on
+// the order of the adds, so the result is reproducible bit for bit.  Thread
+// i keeps e'(u) for u = i + 1024 m in registers until the step ends; then
+// the table is rewritten between two barriers.
 constexpr int LSQ_MAXW = 6240;
-constexpr int LSQ_HALF = LSQ_MAXW / 2;
 constexpr int LSQ_NT = 1024;                 // 16 waves: the one workgroup a CU holds hides latency
 constexpr int LSQ_NWAVE = LSQ_NT / 64;
 constexpr int LSQ_SLOTS = (LSQ_MAXW + LSQ_NT - 1) / LSQ_NT;
 constexpr int LSQ_UNROLL = 4;
+static_assert(LSQ_ROUND % LSQ_NWAVE == 0, "a round gives every wave the same number of segments");
 
-__global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int iters, const int *__restrict__ woff,
-                                            const unsigned *__restrict__ code, const float2 *__restrict__ bispec,
-                                            int64_t s_count, double2 *__restrict__ phasor) {
+__global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, const int *__restrict__ woff,
+                                            const unsigned *__restrict__ code, const int *__restrict__ fin,
+                                            const float2 *__restrict__ bispec, int64_t s_count,
+                                            double2 *__restrict__ phasor) {
     __shared__ double2 e[LSQ_MAXW];
-    __shared__ unsigned long long acc[2 * LSQ_HALF];
+    __shared__ unsigned long long acc[2 * LSQ_ACC];
     __shared__ double red[LSQ_NWAVE];
     const int patch = blockIdx.x;
     const int tid = threadIdx.x;
@@ -278,6 +287,14 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int iters, const int *__
     for (int k = 0; k < LSQ_NWAVE; ++k) s1 += red[k];
     if (!(s1 > 0.0) || !isfinite(s1)) return;          // no usable samples: the phasors stay
     const double scale = 0x1p60 / s1, inv_scale = s1 * 0x1p-60;
+    const int ring = LSQ_ACC - n_inner;                 // >= the plan's live span (checked on the host)
+    // accumulator of entry x: the inner disk first, then the ring
+    auto slot = [&](unsigned x) __attribute__((always_inline)) {
+        if ((int)x < n_inner) return x;
+        int q = (int)x - n_inner;
+        if (q >= ring) q -= ring;                       // x - n_inner < |W| < 2 ring
+        return (unsigned)(n_inner + q);
+    };
     auto get = [&](unsigned c) __attribute__((always_inline)) {     // e of a code (index | conj << 15)
         double2 v = e[c & 0x7fffu];
         if (c & 0x8000u) v.y = -v.y;
@@ -287,20 +304,15 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int iters, const int *__
         atomicAdd(&acc[2 * k], (unsigned long long)__double2ll_rn(x * scale));
         atomicAdd(&acc[2 * k + 1], (unsigned long long)__double2ll_rn(y * scale));
     };
-    const int half = (nW + 1) / 2;
+    const int rounds = (nW + LSQ_ROUND - 1) / LSQ_ROUND;
     for (int it = 0; it < iters; ++it) {
         double2 res[LSQ_SLOTS];
-        for (int pass = 0; pass < 2; ++pass) {
-            const int lo = pass ? half : 0, n = pass ? nW - half : half;     // targets [lo, lo + n)
-            for (int i = tid; i < 2 * n; i += LSQ_NT) acc[i] = 0ull;
-            __syncthreads();
-            // W is ordered by |w|^2 and both sides of a sample are shorter than
-            // its w, so every target of segment w lies below w: the upper
-            // targets' pass needs only the segments from lo on (~52 % of S)
-            for (int w = (pass ? lo : 0) + wave; w < nW; w += LSQ_NWAVE) {
+        for (int i = tid; i < 2 * LSQ_ACC; i += LSQ_NT) acc[i] = 0ull;
+        __syncthreads();
+        for (int r = 0; r < rounds; ++r) {
+            for (int w = r * LSQ_ROUND + wave; w < min(nW, (r + 1) * LSQ_ROUND); w += LSQ_NWAVE) {
                 const int t0 = woff[w], t1 = woff[w + 1];
                 const double2 cw = e[w];
-                const bool own = (unsigned)(w - lo) < (unsigned)n;
                 double gx = 0.0, gy = 0.0;
                 for (int tb = t0; tb < t1; tb += 64 * LSQ_UNROLL) {
                     unsigned cd[LSQ_UNROLL];
@@ -316,49 +328,52 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int iters, const int *__
                         if (tb + 64 * k + lane >= t1) continue;
                         const double2 a = get(cd[k] >> 16), b = get(cd[k] & 0xffffu);
                         const double bx = (double)bb[k].x, by = (double)bb[k].y;
-                        if (own) {                                  // (a b) conj(B)
-                            const double px = a.x * b.x - a.y * b.y, py = a.x * b.y + a.y * b.x;
-                            gx += px * bx + py * by;
-                            gy += py * bx - px * by;
-                        }
-                        const unsigned ia = ((cd[k] >> 16) & 0x7fffu) - lo, ib = (cd[k] & 0x7fffu) - lo;
-                        if (ia < (unsigned)n) {                     // conj(b) e(w) B
+                        // own: (a b) conj(B)
+                        const double px = a.x * b.x - a.y * b.y, py = a.x * b.y + a.y * b.x;
+                        gx += px * bx + py * by;
+                        gy += py * bx - px * by;
+                        {   // side w - v: conj(b) e(w) B
                             const double qx = b.x * cw.x + b.y * cw.y, qy = b.x * cw.y - b.y * cw.x;
                             const double ry = qx * by + qy * bx;
-                            add(ia, qx * bx - qy * by, (cd[k] >> 31) ? -ry : ry);
+                            add(slot((cd[k] >> 16) & 0x7fffu), qx * bx - qy * by, (cd[k] >> 31) ? -ry : ry);
                         }
-                        if (ib < (unsigned)n) {                     // conj(a) e(w) B
+                        {   // side v: conj(a) e(w) B
                             const double qx = a.x * cw.x + a.y * cw.y, qy = a.x * cw.y - a.y * cw.x;
                             const double ry = qx * by + qy * bx;
-                            add(ib, qx * bx - qy * by, (cd[k] & 0x8000u) ? -ry : ry);
+                            add(slot(cd[k] & 0x7fffu), qx * bx - qy * by, (cd[k] & 0x8000u) ? -ry : ry);
                         }
                     }
                 }
-                if (own) {
-                    gx = wave_sum_d(gx);
-                    gy = wave_sum_d(gy);
-                    if (lane == 0) add((unsigned)(w - lo), gx, gy);
-                }
+                gx = wave_sum_d(gx);
+                gy = wave_sum_d(gy);
+                if (lane == 0) add(slot((unsigned)w), gx, gy);
             }
             __syncthreads();
+            // entries no later round targets: new phasors, accumulators cleared
+            // for the ring entries that will take their slots
+            const int f0 = fin[r], f1 = fin[r + 1];
+            const bool last = r + 1 == rounds;
 #pragma unroll
             for (int j = 0; j < LSQ_SLOTS; ++j) {
                 const int u = tid + LSQ_NT * j;
-                if (u >= 2 && (unsigned)(u - lo) < (unsigned)n) {
-                    const double gx = (double)(long long)acc[2 * (u - lo)] * inv_scale;
-                    const double gy = (double)(long long)acc[2 * (u - lo) + 1] * inv_scale;
+                if (u >= 2 && u < nW && ((u >= f0 && u < f1) || (last && u < n_inner))) {
+                    const unsigned k = slot((unsigned)u);
+                    const double gx = (double)(long long)acc[2 * k] * inv_scale;
+                    const double gy = (double)(long long)acc[2 * k + 1] * inv_scale;
+                    acc[2 * k] = 0ull;
+                    acc[2 * k + 1] = 0ull;
                     const double2 old = e[u];
                     double2 nw = old;
                     const double m = sqrt(gx * gx + gy * gy);
                     if (m > 0.0) {
                         const double sx = gx / m + old.x, sy = gy / m + old.y;
-                        const double r = sqrt(sx * sx + sy * sy);
-                        if (r > 0.0) nw = make_double2(sx / r, sy / r);
+                        const double rr = sqrt(sx * sx + sy * sy);
+                        if (rr > 0.0) nw = make_double2(sx / rr, sy / rr);
                     }
                     res[j] = nw;
                 }
             }
-            __syncthreads();                               // accumulators read before the next pass clears them
+            __syncthreads();                               // cleared before the next round adds
         }
 #pragma unroll
         for (int j = 0; j < LSQ_SLOTS; ++j) {
@@ -390,9 +405,10 @@ hipError_t launch_solve_n(const SolveArgs &a, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_lsq(const SolveArgs &a, hipStream_t st) {
-    if (a.nW > LSQ_MAXW || a.nW < 2 || a.lsq_iters < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lsq, dim3(a.bt.patches), dim3(LSQ_NT), 0, st, a.nW, a.lsq_iters, a.woff, a.wcode, a.bispec,
-                       a.s_count, a.phasor);
+    if (a.nW > LSQ_MAXW || a.nW < 2 || a.lsq_iters < 1 || !a.lsq_fin) return hipErrorInvalidValue;
+    if (a.n_inner < 2 || a.n_inner > LSQ_ACC / 2 || 2 * (LSQ_ACC - a.n_inner) <= a.nW) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lsq, dim3(a.bt.patches), dim3(LSQ_NT), 0, st, a.nW, a.n_inner, a.lsq_iters, a.woff, a.wcode,
+                       a.lsq_fin, a.bispec, a.s_count, a.phasor);
     return hipGetLastError();
 }
 

@@ -165,6 +165,7 @@ struct SolveArgs {
     // least-squares refinement (phase_method 1)
     int phase_method = 0, lsq_iters = 0;
     const unsigned *wcode = nullptr;      // sample codes with W indices
+    const int *lsq_fin = nullptr;         // flushed prefix before each round (see plan.hpp)
     SolveArgs() = default;
     SolveArgs(const SolveArgs &o, int method) : SolveArgs(o) { phase_method = method; }
 };

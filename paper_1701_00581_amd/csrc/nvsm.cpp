@@ -32,7 +32,7 @@ struct DevicePlan {
     int nshell = 0, max_sw = 0;
     std::vector<void *> bufs;
     int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr,
-        *group_xy = nullptr, *slot = nullptr, *out_idx = nullptr;
+        *group_xy = nullptr, *slot = nullptr, *out_idx = nullptr, *lsq_fin = nullptr;
     unsigned *code = nullptr, *wcode = nullptr;
     float2 *twiddle = nullptr;
     float *hann = nullptr, *filt = nullptr;
@@ -303,6 +303,8 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
     for (size_t i = 0; i + 1 < h.woff.size(); ++i) dp->max_sw = std::max(dp->max_sw, h.woff[i + 1] - h.woff[i]);
     if (max_per_shell > 16 || dp->max_sw > 512 || h.n_inner > 512 || h.ring_size > 3072)
         return fail(ctx, NVSM_ERR_INVALID_ARG, "shell or phasor window too large for the phase kernel");
+    if (h.n_inner + h.lsq_span > LSQ_ACC)
+        return fail(ctx, NVSM_ERR_INVALID_ARG, "least-squares accumulator window too large");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NVSM_ERR_HIP, "hipSetDevice failed");
     nvsm_status s;
     std::vector<float2> tw(h.N);
@@ -313,6 +315,7 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
         (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
         (s = upload(dp.get(), h.phase_slot_code, &dp->code, &msg)) ||
         (s = upload(dp.get(), h.phase_code, &dp->wcode, &msg)) ||
+        (s = upload(dp.get(), h.lsq_fin, &dp->lsq_fin, &msg)) ||
         (s = upload(dp.get(), h.items, &dp->items, &msg)) ||
         (s = upload(dp.get(), h.group_xy, &dp->group_xy, &msg)) ||
         (s = upload(dp.get(), h.slot_v, &dp->slot, &msg)) ||
@@ -422,7 +425,7 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, co
     a.floor = p->stf_floor; a.noise_bias = p->noise_bias == 1; a.amp = amp;
     a.phasor = (double2 *)phasor;
     a.phase_method = p->phase_method; a.lsq_iters = p->lsq_iters;
-    a.wcode = dp->wcode;
+    a.wcode = dp->wcode; a.lsq_fin = dp->lsq_fin;
     StageTimer t(ctx, ST_SOLVE, st);
     return launch_solve(a, st);
 }

@@ -175,6 +175,30 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     }
     if (pl->s_count >= (int64_t)1 << 31) { *err = "bispectrum set too large"; return false; }
 
+    // least-squares rounds: the last segment that targets each entry (as
+    // its own w or as a side of one of its samples), then the prefixes of
+    // entries that no later round targets
+    {
+        std::vector<int32_t> last(nW);
+        for (int w = 0; w < nW; ++w) {
+            last[w] = std::max(last[w], w);
+            for (int32_t t = pl->woff[w]; t < pl->woff[w + 1]; ++t) {
+                const int ia = (int)((pl->phase_code[t] >> 16) & 0x7fffu), ib = (int)(pl->phase_code[t] & 0x7fffu);
+                last[ia] = std::max(last[ia], w);
+                last[ib] = std::max(last[ib], w);
+            }
+        }
+        const int rounds = (nW + LSQ_ROUND - 1) / LSQ_ROUND;
+        pl->lsq_fin.assign(rounds + 1, nW);
+        pl->lsq_span = 0;
+        int fin = pl->n_inner;
+        for (int r = 0; r < rounds; ++r) {
+            while (fin < nW && last[fin] < r * LSQ_ROUND) ++fin;
+            pl->lsq_fin[r] = fin;
+            pl->lsq_span = std::max(pl->lsq_span, std::min(nW, (r + 1) * LSQ_ROUND) - fin);
+        }
+    }
+
     // Bispectrum work.  Lanes of a wave hold a group of up to 64 w that lie
     // close together in angle and radius: for |w| well above R, S(w) is the
     // part of the |v| <= R disk on w's side of a line through the origin

@@ -19,6 +19,12 @@ constexpr int BS_WAVES = 4;            // waves per workgroup
 constexpr int bs_max_region(int slots) { return slots <= 16 ? 1536 : 2048; }
 constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
 
+// Least-squares phase steps: segments (w) are taken in rounds of
+// LSQ_ROUND; accumulators live in LDS for the inner entries (|w| <= R) and
+// a ring for the rest, LSQ_ACC entries in all.
+constexpr int LSQ_ROUND = 64;
+constexpr int LSQ_ACC = 3968;
+
 struct Tiling {
     int ny = 0, nx = 0;
     std::vector<int32_t> ys, xs;
@@ -43,6 +49,12 @@ struct HostPlan {
     // while the sample's shell is solved, and the slot of every w.
     std::vector<uint32_t> phase_slot_code;
     std::vector<int32_t> w_slot;
+    // Least-squares rounds: before round r (segments [r, r + 1) * LSQ_ROUND)
+    // the entries [n_inner, lsq_fin[r]) are targets of no later segment;
+    // lsq_fin[0] = n_inner, lsq_fin[rounds] = |W|.  lsq_span is the most
+    // ring entries live in one round, [lsq_fin[r], (r + 1) * LSQ_ROUND).
+    std::vector<int32_t> lsq_fin;
+    int lsq_span = 0;
     // Per S entry: lookup codes of (w - v) and v in the phasor table
     // (bits 0..14 index into W, bit 15 set = use the conjugate).
     std::vector<uint32_t> phase_code;
