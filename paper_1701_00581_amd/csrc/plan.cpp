@@ -254,23 +254,32 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
         // Items: full ones (BS_WAVES chunks of K slots), then one for the
         // rest, whose waves all run ns slots (ns the smallest multiple of 4
         // that holds a quarter of the rest); chunks balanced within an item.
+        // Items hold fewer v (in steps of 4 per wave) where the staged
+        // region of a full item would not fit the LDS capacity.
         const int nU = (int)U.size();
         struct Item { int u0, m, ns, rx0, ry0, rw, rh; };
         std::vector<Item> gitems;
         int maxw = 0;
-        for (int u0 = 0; u0 < nU; u0 += BS_WAVES * K) {
-            const int m = std::min(nU - u0, BS_WAVES * K);
-            const int ns = std::min(K, 4 * (((m + BS_WAVES - 1) / BS_WAVES + 3) / 4));
-            int vxmin = 1 << 20, vxmax = -(1 << 20), vymin = 1 << 20, vymax = -(1 << 20);
-            for (int u = u0; u < u0 + m; ++u) {
-                vxmin = std::min(vxmin, U[u].first); vxmax = std::max(vxmax, U[u].first);
-                vymin = std::min(vymin, U[u].second); vymax = std::max(vymax, U[u].second);
+        for (int mcap = BS_WAVES * K; mcap > 0; mcap -= 4 * BS_WAVES) {
+            gitems.clear();
+            maxw = 0;
+            int maxh = 0;
+            for (int u0 = 0; u0 < nU; u0 += mcap) {
+                const int m = std::min(nU - u0, mcap);
+                const int ns = std::min(K, 4 * (((m + BS_WAVES - 1) / BS_WAVES + 3) / 4));
+                int vxmin = 1 << 20, vxmax = -(1 << 20), vymin = 1 << 20, vymax = -(1 << 20);
+                for (int u = u0; u < u0 + m; ++u) {
+                    vxmin = std::min(vxmin, U[u].first); vxmax = std::max(vxmax, U[u].first);
+                    vymin = std::min(vymin, U[u].second); vymax = std::max(vymax, U[u].second);
+                }
+                // x0 even: region pairs (x, x + 1) never straddle column 0
+                const int rx0 = (gx0 - vxmax) & ~1, ry0 = gy0 - vymax;
+                const int rw = gx1 - vxmin - rx0 + 1, rh = gy1 - vymin - ry0 + 1;
+                gitems.push_back({u0, m, ns, rx0, ry0, rw, rh});
+                maxw = std::max(maxw, rw);
+                maxh = std::max(maxh, rh);
             }
-            // x0 even: region pairs (x, x + 1) never straddle column 0
-            const int rx0 = (gx0 - vxmax) & ~1, ry0 = gy0 - vymax;
-            const int rw = gx1 - vxmin - rx0 + 1, rh = gy1 - vymin - ry0 + 1;
-            gitems.push_back({u0, m, ns, rx0, ry0, rw, rh});
-            maxw = std::max(maxw, rw);
+            if ((maxw + (maxw & 1)) * maxh <= bs_max_region(K)) break;
         }
         // One row pitch for all items of the group, even (the kernel moves
         // the region in pairs of columns).  A lane reads LDS at
@@ -278,7 +287,7 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
         // every gather follows key = (wx + pitch wy) mod 32 up to a shift
         // common to the wave.  A 64-bit LDS read serves 16 lanes per pass (32
         // on a 64-bank LDS): the pitch (one of the even values from the
-        // widest region up to 32 more, within the LDS capacity) is the one
+        // widest region up to 8 more, within the LDS capacity) is the one
         // whose keys spread most evenly over the group
         // (at most 4 w per key mod 16, then 2 per key), and lanes are then
         // assigned so that each run of 16 lanes has distinct key mod 16 and,
@@ -286,7 +295,7 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
         int maxh = 0;
         for (const Item &gt : gitems) maxh = std::max(maxh, gt.rh);
         int pitch = maxw + (maxw & 1), best = 1 << 30;
-        for (int cand = maxw + (maxw & 1); cand < maxw + 33; cand += 2) {
+        for (int cand = maxw + (maxw & 1); cand < maxw + 9; cand += 2) {
             if (cand * maxh > bs_max_region(K)) break;
             int c16[16] = {}, c32[32] = {};
             for (int i : gset) {
