@@ -17,8 +17,8 @@ constexpr int BS_WAVES = 4;            // waves per workgroup
 // Staged region extent (pitch x height) per frame, in whole 128s: larger
 // for more slots per wave, whose items span more v.  With 16 slots, 1024
 // (two 16-byte loads per lane and frame) holds the full items of every
-// (N, R) up to R = 12 and three in four items at R = 16; the planner gives
-// the groups whose regions are larger items of fewer v.
+// supported (N, R); the planner would give a group whose region is larger
+// items of fewer v.
 constexpr int bs_max_region(int slots) { return slots <= 16 ? 1024 : 2048; }
 constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
 
