@@ -16,6 +16,10 @@ BISPEC_TOL = 1e-4
 PHASE_RMS_TOL = 1e-3
 POWER_TOL = 1e-5
 MOSAIC_TOL = 1e-3
+# Mean spectrum at the two seed frequencies, relative: it only sets the
+# seeds' phases, which a relative error d moves by at most d rad, so it is
+# held 10x under the phase tolerance.
+MEAN_SPEC_TOL = 1e-4
 
 
 def say(*a):

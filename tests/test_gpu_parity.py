@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import (BISPEC_TOL, MOSAIC_TOL, PHASE_RMS_TOL, POWER_TOL, abs_bispectrum, as_complex,
+from gpu_helpers import (BISPEC_TOL, MEAN_SPEC_TOL, MOSAIC_TOL, PHASE_RMS_TOL, POWER_TOL, abs_bispectrum, as_complex,
                          bispec_errors, burst, cube, oparams, phase_rms, say, stf, to_device)
 
 pytestmark = pytest.mark.gpu
@@ -45,7 +45,10 @@ def _check_accumulate(s, frames, p, patches, Sset, label):
         say(f"[{label}] patch {k}: P {perr:.2e} M10 {m10:.2e} M01 {m01:.2e} mu {muerr:.2e} "
             f"B norm {nerr:.2e} B/A max {aerr:.2e}")
         assert perr <= POWER_TOL
-        assert m10 <= 1e-5 and m01 <= 1e-5 and muerr <= 1e-6
+        # the mean spectrum's only use is the phase of the two seeds, which a
+        # relative error d moves by at most d rad: kept 10x under the phase
+        # tolerance
+        assert m10 <= MEAN_SPEC_TOL and m01 <= MEAN_SPEC_TOL and muerr <= 1e-6
         assert nerr <= BISPEC_TOL and aerr <= BISPEC_TOL
 
 
@@ -187,6 +190,46 @@ def test_solve_on_identical_inputs(torch_cuda):
         aerr = np.max(np.abs(amp[i] - ao)) / np.max(ao)
         rms, mx = phase_rms(ph[i], eo)
         say(f"[solve] patch {ks[i]}: amp {aerr:.2e} phase rms {rms:.2e} max {mx:.2e}")
+        assert aerr <= 1e-12
+        assert rms <= 1e-9
+
+
+@pytest.mark.parametrize("N,u_cut,R,stride,window,H,W,F", [
+    (128, 40, 16, 40, 1, 200, 200, 8),     # the largest R, a low cut-off, 3x3 patches at a short stride
+    (64, 20, 5, 24, 0, 100, 90, 9),        # no taper, odd F, clamped last row and column
+    (64, 31, 3, 32, 1, 96, 130, 6),        # the smallest usual R
+])
+def test_other_geometries_accumulate_and_solve(torch_cuda, N, u_cut, R, stride, window, H, W, F):
+    """Parameter sets away from the benchmark's: the bispectrum work plan
+    (groups, regions, items) and the solve's phasor window differ.  The
+    accumulation against the oracle, then the solve on the GPU's own
+    accumulations against the oracle's solve of the same FP32 values."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    say(f"case geometry N={N} u_cut={u_cut} R={R} stride={stride} window={window} {H}x{W} F={F}")
+    fr = burst("burst1024", F=F, H=H, W=W)
+    p = nv.default_params(N, u_cut=u_cut, v_radius=R, stride=stride, window=window)
+    s = _session(p, H, W, F)
+    s.accumulate(to_device(fr))
+    torch.cuda.synchronize()
+    Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+    P = s.info.patches
+    _check_accumulate(s, fr, p, [0, P - 1], S, f"geom N={N} R={R}")
+    st = np.ones((N, N))
+    s.solve(torch.from_numpy(st).cuda())
+    torch.cuda.synchronize()
+    amp = s.amp.cpu().numpy()
+    ph = as_complex(s.phasor)
+    Pg = s.power.cpu().numpy().astype(np.float64)
+    Mg = s.mean_spec.cpu().numpy().astype(np.float64)
+    Bg = as_complex(s.bispec)
+    for k in (0, P - 1):
+        ao = oracle.amplitude(Pg[k], st, Wset, 0.0, p.stf_floor)
+        eo = oracle.phase_recursion(Bg[k].astype(np.complex128), complex(*Mg[k][0]), complex(*Mg[k][1]),
+                                    Wset, S, woff, N)
+        aerr = np.max(np.abs(amp[k] - ao)) / np.max(ao)
+        rms, mx = phase_rms(ph[k], eo)
+        say(f"[geom N={N} R={R}] patch {k}: solve amp {aerr:.2e} phase rms {rms:.2e} max {mx:.2e}")
         assert aerr <= 1e-12
         assert rms <= 1e-9
 
