@@ -121,7 +121,7 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
         const int fb = fa + 1;
         const bool hasb = fb < f1;
         load_pair(fa);
-        // weighted sums (compensated), raw pixels to LDS
+        // weighted sums (compensated); the pixels stay in registers
         float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
@@ -132,7 +132,6 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
                 const float w = hw[y] * hw[x + e];
                 kahan_add(sa, ca, w * va);
                 kahan_add(sb, cb, w * vb);
-                z[y * P + x + e] = make_float2(va, vb);
             }
         }
         float ra = wave_sum(sa - ca), rb = wave_sum(sb - cb);
@@ -147,15 +146,16 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
             kahan_add(mus, muc, mua);
             if (hasb) kahan_add(mus, muc, mub);
         }
-        // taper the mean-removed pixels
+        // the mean-removed, tapered pixels to LDS (the previous pair's
+        // transform was read before the loop's last barrier)
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
             const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
-                const float2 v = z[y * P + x + e];
-                z[y * P + x + e] = make_float2((v.x - mua) * w, hasb ? (v.y - mub) * w : 0.f);
+                const float va = qa[j][e], vb = hasb ? qb[j][e] : 0.f;
+                z[y * P + x + e] = make_float2((va - mua) * w, hasb ? (vb - mub) * w : 0.f);
             }
         }
         __syncthreads();
