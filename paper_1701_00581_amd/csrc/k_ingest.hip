@@ -380,19 +380,18 @@ __global__ __launch_bounds__(FT) void k_noise(const BurstTable bt, int stride, i
     for (int f = f0; f < f1; ++f) {
         const T *pf = frames + (size_t)f * H * pitch + (size_t)y0 * pitch + x0;
         float s1 = 0.f, c1 = 0.f, s2 = 0.f, s3 = 0.f;
+        Quad<T, VEC> v[QPT];           // the pixels stay in registers until tapered
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
             const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
-            Quad<T, VEC> v;
-            v.load(pf + (size_t)y * pitch + x);
+            v[j].load(pf + (size_t)y * pitch + x);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
-                const float wp = w * v[e];
+                const float wp = w * v[j][e];
                 kahan_add(s1, c1, wp);
                 s2 += w * wp;
                 s3 += w * w * wp;
-                z[y * P + x + e] = make_float2(v[e], 0.f);
             }
         }
         const float r1 = wave_sum(s1 - c1), r2 = wave_sum(s2), r3 = wave_sum(s3);
@@ -412,7 +411,7 @@ __global__ __launch_bounds__(FT) void k_noise(const BurstTable bt, int stride, i
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
-                const float d = (z[y * P + x + e].x - mu) * w;
+                const float d = (v[j][e] - mu) * w;
                 z[y * P + x + e] = make_float2(d, d * w);
             }
         }
@@ -564,7 +563,6 @@ __global__ __launch_bounds__(FT) void k_ratio(const RatioArgs a) {
                 const float w = hw[y] * hw[x + e];
                 kahan_add(sa, ca, w * va);
                 kahan_add(sb, cb, w * vb);
-                z[y * P + x + e] = make_float2(va, vb);
             }
         }
         const float r0 = wave_sum(sa - ca), r1 = wave_sum(sb - cb);
@@ -581,8 +579,8 @@ __global__ __launch_bounds__(FT) void k_ratio(const RatioArgs a) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
-                const float2 v = z[y * P + x + e];
-                z[y * P + x + e] = make_float2((v.x - mua) * w, hasb ? (v.y - mub) * w : 0.f);
+                const float va = qa[j][e], vb = hasb ? qb[j][e] : 0.f;
+                z[y * P + x + e] = make_float2((va - mua) * w, hasb ? (vb - mub) * w : 0.f);
             }
         }
         __syncthreads();
