@@ -223,15 +223,28 @@ def test_other_geometries_accumulate_and_solve(torch_cuda, N, u_cut, R, stride, 
     Pg = s.power.cpu().numpy().astype(np.float64)
     Mg = s.mean_spec.cpu().numpy().astype(np.float64)
     Bg = as_complex(s.bispec)
+    # three least-squares steps on the same inputs (the accumulator ring of
+    # the steps is largest at R = 16)
+    p2 = nv.default_params(N, u_cut=u_cut, v_radius=R, stride=stride, window=window, phase_method=1, lsq_iters=3)
+    amp2 = torch.empty_like(s.amp)
+    ph2 = torch.empty_like(s.phasor)
+    nv.nvsm_solve(s.ctx, p2, P, s.power, s.mean_spec, s.bispec, torch.from_numpy(st).cuda(), amp2, ph2)
+    torch.cuda.synchronize()
+    ph2 = as_complex(ph2)
     for k in (0, P - 1):
         ao = oracle.amplitude(Pg[k], st, Wset, 0.0, p.stf_floor)
         eo = oracle.phase_recursion(Bg[k].astype(np.complex128), complex(*Mg[k][0]), complex(*Mg[k][1]),
                                     Wset, S, woff, N)
         aerr = np.max(np.abs(amp[k] - ao)) / np.max(ao)
         rms, mx = phase_rms(ph[k], eo)
-        say(f"[geom N={N} R={R}] patch {k}: solve amp {aerr:.2e} phase rms {rms:.2e} max {mx:.2e}")
+        el = oracle.phase_least_squares(Bg[k].astype(np.complex128), eo, Wset, S, woff, 3)
+        lrms, lmx = phase_rms(ph2[k], el)
+        moved, _ = phase_rms(el, eo)
+        say(f"[geom N={N} R={R}] patch {k}: solve amp {aerr:.2e} phase rms {rms:.2e} max {mx:.2e}; "
+            f"3 least-squares steps rms {lrms:.2e} max {lmx:.2e} (moved {moved:.2e})")
         assert aerr <= 1e-12
         assert rms <= 1e-9
+        assert moved > 1e-6 and lrms <= 1e-9
 
 
 def test_synthesize_on_identical_inputs(torch_cuda):
