@@ -225,19 +225,39 @@ __global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, const double *
 // Sums the workgroups' partials in FP64 and writes <|OTF|^2> (and <OTF>)
 // over the full grid: the half plane directly, the other half from
 // S(-u) = S(u) and <OTF>(-u) = conj <OTF>(u).
+// Each workgroup takes 32 frequencies; 8 threads per frequency sum strided
+// eighths of the workgroup partials, combined in a fixed order (so the sums
+// are repeatable), which keeps 8 times as many loads in flight as one thread
+// per frequency would.
+constexpr int FIN_PARTS = 8, FIN_Q = 256 / FIN_PARTS;
 template <int N>
 __global__ __launch_bounds__(256) void k_stf_finalize(int nwg, double inv_screens, const float2 *__restrict__ part_a,
                                                       const float *__restrict__ part_s, double *__restrict__ stf,
                                                       double2 *__restrict__ mean_otf) {
     constexpr int NP = (N / 2 + 1) * N;
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= NP) return;
+    __shared__ double red[3][FIN_PARTS][FIN_Q];
+    const int lq = threadIdx.x % FIN_Q, part = threadIdx.x / FIN_Q;
+    const int q = blockIdx.x * FIN_Q + lq;
     double ax = 0.0, ay = 0.0, s = 0.0;
-    for (int b = 0; b < nwg; ++b) {
-        const float2 a = part_a[(size_t)b * NP + q];
-        ax += (double)a.x;
-        ay += (double)a.y;
-        s += (double)part_s[(size_t)b * NP + q];
+    if (q < NP) {
+        for (int b = part; b < nwg; b += FIN_PARTS) {
+            const float2 a = part_a[(size_t)b * NP + q];
+            ax += (double)a.x;
+            ay += (double)a.y;
+            s += (double)part_s[(size_t)b * NP + q];
+        }
+    }
+    red[0][part][lq] = ax;
+    red[1][part][lq] = ay;
+    red[2][part][lq] = s;
+    __syncthreads();
+    if (part != 0 || q >= NP) return;
+    ax = ay = s = 0.0;
+#pragma unroll
+    for (int k = 0; k < FIN_PARTS; ++k) {
+        ax += red[0][k][lq];
+        ay += red[1][k][lq];
+        s += red[2][k][lq];
     }
     ax *= inv_screens;
     ay *= inv_screens;
@@ -259,7 +279,7 @@ hipError_t launch_stf_t(const StfArgs &a, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     constexpr int NP = (N / 2 + 1) * N;
-    hipLaunchKernelGGL((k_stf_finalize<N>), dim3((NP + 255) / 256), dim3(256), 0, st, a.nwg, 1.0 / (2.0 * a.pairs),
+    hipLaunchKernelGGL((k_stf_finalize<N>), dim3((NP + FIN_Q - 1) / FIN_Q), dim3(256), 0, st, a.nwg, 1.0 / (2.0 * a.pairs),
                        a.part_a, a.part_s, a.stf, a.mean_otf);
     return hipGetLastError();
 }
