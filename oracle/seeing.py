@@ -50,9 +50,8 @@ import math
 
 import numpy as np
 
-__all__ = ["philox4x32", "normals", "screen_pair", "pupil", "otf", "model", "long_exposure_otf", "annulus_mean",
-           "seeing_cubes", "fit_grid", "half_plane_annuli", "spectral_ratio", "weighted_model_curve", "fit_curve",
-           "seeing"]
+__all__ = ["philox4x32", "normals", "screen_pair", "pupil", "otf", "model", "seeing_cubes", "fit_grid",
+           "half_plane_annuli", "spectral_ratio", "weighted_model_curve", "fit_curve", "seeing"]
 
 _M0, _M1 = 0xD2511F53, 0xCD9E8D57
 _W0, _W1 = 0x9E3779B9, 0xBB67AE85
@@ -159,25 +158,6 @@ def model(N, d_over_r0, screens, seed, m=0):
             A += o
             S += np.abs(o) ** 2
     return A / screens, S / screens
-
-
-def long_exposure_otf(N, d_over_r0):
-    """T(u) exp(-3.44 (|u| / r0)^(5/3)) (Fried 1966; T the OTF of pupil(N),
-    r0 = (N/2) / (D/r0) px, |u| the wrapped DFT lag): the mean OTF of
-    Kolmogorov turbulence of unlimited outer scale."""
-    T = otf(np.zeros((N, N)), pupil(N)).real
-    k = np.fft.fftfreq(N) * N
-    r = np.hypot(k[None, :], k[:, None])
-    r0 = (N / 2.0) / d_over_r0
-    return T * np.exp(-3.44 * (r / r0) ** (5.0 / 3.0))
-
-
-def annulus_mean(E, Q):
-    """Means of E [N][N] (DFT order) over q - 1/2 <= |u| < q + 1/2, q = 1..Q."""
-    N = E.shape[0]
-    k = np.fft.fftfreq(N) * N
-    r = np.hypot(k[None, :], k[:, None])
-    return np.array([E[(r >= q - 0.5) & (r < q + 0.5)].mean() for q in range(1, Q + 1)])
 
 
 def seeing_cubes(H, W, N):

@@ -504,3 +504,108 @@ def test_photon_corrected_spectra_are_unbiased(window, gain):
     pr = _zscores([r["P"] for r in raw], truth["P"])[off]
     assert pc.max() < 6.0
     assert pr.min() > 20.0
+
+
+# ---------------------------------------------------------------------------
+# The whole composition (tile, accumulate, seeds, Eq. 1, phase, synthesis,
+# mosaic) against a closed form: identical noiseless frames.
+# ---------------------------------------------------------------------------
+def _band_limited_periodic(N, radius, H, W, seed, mean=3.0):
+    """An N-periodic real image whose spectrum lies inside |u| <= radius,
+    tiled over H x W (every N x N cut is a circular shift of one period)."""
+    rng = _rng(seed)
+    k = np.fft.fftfreq(N) * N
+    ux, uy = np.meshgrid(k, k)
+    X = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    X[ux ** 2 + uy ** 2 > radius * radius] = 0.0
+    X[0, 0] = 0.0
+    base = np.real(np.fft.ifft2(X)) * N
+    base = mean + 0.3 * base / base.std()
+    reps = (-(-H // N), -(-W // N))
+    return np.tile(base, reps)[:H, :W]
+
+
+def _closed_form_case(window):
+    """F identical noiseless frames of a band-limited image, STF = 1.
+
+    Every frame has the spectrum I of its (tapered, mean-removed) patch, so
+    P = |I|^2, M = I and B(w, v) = I(w - v) I(v) conj I(w): Eq. 1 gives
+    |I| and the recursion, seeded by M(1,0) and M(0,1), gives arg I on W.
+    When I lies inside |u| <= u_cut the inverse transform returns the tapered
+    patch exactly, and the normalised overlap-add returns the image wherever
+    the summed taper is nonzero.
+    * window 0: one 32 x 32 patch, content inside |u| <= u_cut = 15.
+    * window 1: a 72 x 88 crop cut into 4 x 5 patches of 32 at stride 16
+      (the last row and column clamped flush with the edge).  The Hann taper
+      spreads each frequency by one step per axis, so the content is kept
+      inside |u| <= u_cut - 2 (13 + sqrt 2 < 15).
+    """
+    N, uc, R = 32, 15, 5
+    if window == 0:
+        H, W, radius, stride = 32, 32, uc, 32
+    else:
+        H, W, radius, stride = 72, 88, uc - 2, 16
+    img = _band_limited_periodic(N, radius, H, W, seed=41 + window)
+    frames = np.repeat(img[None], 3, axis=0)
+    p = oracle.Params(patch=N, stride=stride, u_cut=uc, v_radius=R, window=window)
+    stf = np.ones((N, N))
+    return img, frames, p, stf
+
+
+@pytest.mark.parametrize("window", [0, 1])
+def test_reconstruct_returns_identical_noiseless_frames(window):
+    img, frames, p, stf = _closed_form_case(window)
+    out = oracle.reconstruct(frames, p, stf)
+    ys, xs = out["ys"], out["xs"]
+    if window == 0:
+        np.testing.assert_allclose(out["image"], img, rtol=0, atol=1e-10)
+    else:
+        assert ys == [0, 16, 32, 40] and xs == [0, 16, 32, 48, 56]
+        # summed taper: 0 on row 0 and column 0, below 1e-3 only next to them
+        h = 0.5 - 0.5 * np.cos(2.0 * np.pi * np.arange(32) / 32)
+        den = np.zeros(img.shape)
+        for y0 in ys:
+            for x0 in xs:
+                den[y0:y0 + 32, x0:x0 + 32] += np.outer(h, h)
+        ok = den >= 1e-3
+        assert ok.sum() > 0.99 * (71 * 87)
+        np.testing.assert_allclose(out["image"][ok], img[ok], rtol=0, atol=1e-10)
+        assert np.all(out["image"][~ok] == 0)
+
+
+def _swap_seeds(acc):
+    acc["M10"], acc["M01"] = acc["M01"], acc["M10"]
+
+
+def _conjugate_bispectrum(acc):
+    acc["B"] = np.conj(acc["B"])
+
+
+def _drop_mean_level(acc):
+    acc["mu"] = 0.0
+
+
+def _transpose_power(acc):
+    acc["P"] = acc["P"].T.copy()
+
+
+@pytest.mark.parametrize("window", [0, 1])
+@pytest.mark.parametrize("mistake", [_swap_seeds, _conjugate_bispectrum, _drop_mean_level, _transpose_power])
+def test_closed_form_catches_planted_mistakes(monkeypatch, window, mistake):
+    """Negative controls: the closed form above fails when a plausible
+    mistake is planted in a copy of the composition (the seeds M(1,0) and
+    M(0,1) swapped, the bispectrum conjugated, the mean level not restored,
+    the power spectrum transposed)."""
+    import oracle.speckle as sp
+    img, frames, p, stf = _closed_form_case(window)
+    real = sp.accumulate_patch
+
+    def planted(cube, params, S=None):
+        acc = real(cube, params, S)
+        mistake(acc)
+        return acc
+
+    monkeypatch.setattr(sp, "accumulate_patch", planted)
+    out = sp.reconstruct(frames, p, stf)
+    err = np.max(np.abs(out["image"][1:, 1:] - img[1:, 1:]))
+    assert err > 1e-2, err

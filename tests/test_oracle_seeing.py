@@ -170,3 +170,56 @@ def test_seeing_recovers_the_generators_d_over_r0():
     r = oracle.seeing(fr, 128, 1, screens=200, seed=5, lo=6.0, hi=40.0, J=12, Q=12)
     assert abs(r["d_over_r0"] / cfg.d_over_r0 - 1.0) < 0.10, r["d_over_r0"]
     assert r["stf"][0, 0] == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("tstar", [7.3, 11.85, 4.0, 0.2])
+def test_fit_curve_vertex_of_an_exact_parabola(tstar):
+    """Model curves c_j = c + (j - t*) d make the squared distance to c an
+    exact parabola (j - t*)^2 |d|^2 in the grid index; the fit must return
+    D/r0 = lo (hi/lo)^(t*/(J-1)) (a sign slip in the vertex gives 2j - t*).
+    At the grid's ends (no neighbour on one side) the grid point itself."""
+    rng = np.random.default_rng(9)
+    J, Q, lo, hi = 20, 12, 2.0, 50.0
+    grid = oracle.fit_grid(lo, hi, J)
+    c = rng.random(Q)
+    d = rng.standard_normal(Q)
+    curves = c[None, :] + (np.arange(J)[:, None] - tstar) * d[None, :]
+    got = oracle.fit_curve(c, curves, grid)
+    j = int(round(tstar))
+    want_t = tstar if 0 < j < J - 1 else float(j)
+    assert got == pytest.approx(lo * (hi / lo) ** (want_t / (J - 1.0)), rel=1e-12)
+    # the minimum at the last point: the fit stops there
+    curves = c[None, :] + (np.arange(J)[:, None] - (J + 3.0)) * d[None, :]
+    assert oracle.fit_curve(c, curves, grid) == pytest.approx(hi, rel=1e-12)
+
+
+def test_weighted_model_curve_through_the_taper():
+    """The tapered branch, by hand.  With rho = c everywhere (rho(0) = 0 is
+    left out of both sums) every annulus reads c.  With the power spectrum
+    at two frequencies only, P(u) = 1 at k = (0, 0) from u and P = 16 at
+    k = (ky, kx) = (1, -1) (squared taper weights 1/4 * 1/4 = 1/16 and
+    1/16 * 1/16 = 1/256), u reads (rho1 / 16 + rho2 / 16) / (1/16 + 1/16),
+    the mean of the two ratios; a power at the origin adds nothing."""
+    N = 32
+    rho = np.full((N, N), 0.37)
+    rho[0, 0] = 0.0
+    P = np.random.default_rng(2).random((N, N)) + 0.5
+    annuli = oracle.half_plane_annuli(8)
+    got = oracle.weighted_model_curve(rho, P, 1, annuli)
+    np.testing.assert_allclose(got, 0.37, rtol=0, atol=1e-15)
+    uy, ux = 3, 5
+    rho = np.zeros((N, N))
+    P = np.zeros((N, N))
+    rho[uy, ux], P[uy, ux] = 0.2, 1.0
+    rho[uy - 1, ux + 1], P[uy - 1, ux + 1] = 0.9, 16.0
+    got = oracle.weighted_model_curve(rho, P, 1, [[(uy, ux)]])
+    assert got[0] == pytest.approx(0.55, abs=1e-15)
+    # u = (0, 1): the neighbour k = (0, 1) is the origin, left out
+    rho2 = np.zeros((N, N))
+    P2 = np.zeros((N, N))
+    rho2[0, 1], P2[0, 1] = 0.3, 2.0
+    P2[0, 0], rho2[0, 0] = 50.0, 0.0
+    rho2[1, 2], P2[1, 2] = 0.7, 8.0           # k = (-1, -1): weight 1/256
+    got = oracle.weighted_model_curve(rho2, P2, 1, [[(0, 1)]])
+    want = (2.0 / 16 * 0.3 + 8.0 / 256 * 0.7) / (2.0 / 16 + 8.0 / 256)
+    assert got[0] == pytest.approx(want, abs=1e-15)
