@@ -79,3 +79,26 @@ def phase_rms(eg, eo):
 def as_complex(t):
     a = t.detach().cpu().numpy()
     return a[..., 0] + 1j * a[..., 1]
+
+
+def _align(n):
+    return (n + 255) // 256 * 256
+
+
+def reconstruct_views(ws, P, N, nW, S):
+    """The intermediates nvsm_reconstruct and nvsm_reconstruct_batch leave at
+    the start of their workspace (the layout the header documents): power,
+    mean spectrum, mean level, bispectrum, modulus, phasors, subimages of the
+    P patches of the last launch group, each 256-byte aligned."""
+    import torch
+    out, off = {}, 0
+    for name, n, dt, shape in (("power", P * N * N * 4, torch.float32, (P, N, N)),
+                               ("mean_spec", P * 16, torch.float32, (P, 2, 2)),
+                               ("mu", P * 4, torch.float32, (P,)),
+                               ("bispec", P * S * 8, torch.float32, (P, S, 2)),
+                               ("amp", P * nW * 8, torch.float64, (P, nW)),
+                               ("phasor", P * nW * 16, torch.float64, (P, nW, 2)),
+                               ("patches", P * N * N * 4, torch.float32, (P, N, N))):
+        out[name] = ws[off:off + n].view(dt).view(shape)
+        off += _align(n)
+    return out

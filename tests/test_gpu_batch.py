@@ -227,3 +227,86 @@ def test_launch_choices_identical_and_autotune(torch_cuda):
     torch.cuda.synchronize()
     assert torch.equal(bis, base)
     nv.nvsm_destroy(ctx)
+
+
+# Two (N, R) classes of uneven bursts for the batch-versus-oracle test: the
+# four N = 64 bursts above (R = 8) and two N = 128 bursts (R = 12), one of
+# them with 100 frames.
+CLASS128 = [(256, 256, 100, 0), (300, 260, 57, 0)]
+
+
+def _np_burst(i, H, W, F, patch, v_radius, screens):
+    cfg = dataclasses.replace(synth.CONFIGS["burst1024"], name=f"batch{i}", index=40 + i, H=H, W=W, F=F,
+                              patch=patch, v_radius=v_radius)
+    return synth.make_burst(cfg), synth.stf_table(cfg, screens=screens, patch=patch)
+
+
+@pytest.mark.timeout(900)
+def test_batch_against_the_oracle(torch_cuda):
+    """nvsm_reconstruct_batch on six uneven bursts in two (N, R) classes, one
+    call per class with every burst in one launch group, against the FP64
+    oracle: the whole mosaic of every burst, and the bispectrum, modulus and
+    phases of the first and last patch of every burst (read from the
+    workspace, whose layout the header documents)."""
+    import oracle
+    import oracle_pool
+    import paper_1701_00581_amd as nv
+    from gpu_helpers import (BISPEC_TOL, MOSAIC_TOL, PHASE_RMS_TOL, abs_bispectrum, as_complex, bispec_errors,
+                             oparams, phase_rms, reconstruct_views)
+    torch = torch_cuda
+    classes = [(64, 8, [(i, *s) for i, s in enumerate(SHAPES)], 40),
+               (128, 12, [(10 + i, *s) for i, s in enumerate(CLASS128)], 100)]
+    for N, R, members, screens in classes:
+        p = nv.default_params(N, v_radius=R, noise_bias=1, filter=1)
+        say(f"case batch vs oracle: N {N} R {R}, bursts {[m[1:4] for m in members]}")
+        host, dev, outs = [], [], []
+        for i, H, W, F, pad in members:
+            fr, st = _np_burst(i, H, W, F, N, R, screens)
+            host.append((fr, st))
+            d = to_device(fr)
+            if pad:
+                wide = torch.zeros((F, H, W + pad), dtype=d.dtype, device=d.device)
+                wide[:, :, :W] = d
+                d = wide[:, :, :W]
+            outs.append(torch.full((H, W), float("nan"), device="cuda"))
+            dev.append((d, torch.from_numpy(st).cuda(), outs[-1]))
+        _, ws_all = nv.nvsm_batch_plan(p, [tuple(d.shape) for d, _, _ in dev])
+        ws = torch.empty(ws_all, dtype=torch.uint8, device="cuda")
+        ctx = nv.nvsm_create(0)
+        try:
+            nv.nvsm_reconstruct_batch(ctx, p, dev, ws)
+            torch.cuda.synchronize()
+        finally:
+            nv.nvsm_destroy(ctx)
+        infos = [nv.nvsm_plan(p, H, W, F) for _, H, W, F, _ in members]
+        P = sum(int(x.patches) for x in infos)
+        v = reconstruct_views(ws, P, N, infos[0].w_count, infos[0].s_count)
+        B = as_complex(v["bispec"])
+        ph = as_complex(v["phasor"])
+        amp = v["amp"].cpu().numpy()
+        imgs = [o.cpu().numpy() for o in outs]
+        Wset, S, woff = oracle.bispectrum_set(p.u_cut, p.v_radius)
+        op = oparams(p)
+        patch0 = 0
+        for (i, H, W, F, pad), info, (fr, st), g in zip(members, infos, host, imgs):
+            last = int(info.patches) - 1
+            keep = [(0, 0), divmod(last, int(info.patches_x))]
+            ref = oracle_pool.reconstruct(fr, op, st, keep=keep, say=say)
+            for k, t in zip((0, last), keep):
+                o = ref["tiles"][t]
+                ys, xs = ref["ys"], ref["xs"]
+                c = fr[:, ys[t[0]]:ys[t[0]] + N, xs[t[1]]:xs[t[1]] + N].astype(np.float64)
+                I, _ = oracle.patch_spectra(c, op.window)
+                nerr, aerr = bispec_errors(B[patch0 + k], o["B"], abs_bispectrum(I, S))
+                rms, mx = phase_rms(ph[patch0 + k], o["phasor"])
+                a_err = np.max(np.abs(amp[patch0 + k] - o["amp"])) / np.max(o["amp"])
+                say(f"[batch vs oracle] N {N} burst {H}x{W}x{F} patch {k}: B norm {nerr:.2e} B/A max {aerr:.2e} "
+                    f"amp {a_err:.2e} phase rms {rms:.2e}")
+                assert nerr <= BISPEC_TOL and aerr <= BISPEC_TOL
+                assert a_err <= 1e-4 and rms <= PHASE_RMS_TOL
+            o = ref["image"]
+            sl = np.s_[1:, 1:]
+            merr = np.linalg.norm(g[sl] - o[sl]) / np.linalg.norm(o[sl] - o[sl].mean())
+            say(f"[batch vs oracle] N {N} burst {H}x{W}x{F}: mosaic {merr:.2e}")
+            assert np.isfinite(g).all() and merr <= MOSAIC_TOL
+            patch0 += int(info.patches)
