@@ -108,11 +108,14 @@ def cpu_baseline(frames, stf, op, n_patches_total, ny, nx, workers):
 
 
 def batch16(args):
-    """16 bursts of uneven shape: 8 x 2560x2160 (|v| <= 12) and 8 x 1024x1024
-    (|v| <= 10), uint16, frame counts uniform in [80, 150], 128^2 patches.
-    Three ways, same images: one nvsm_reconstruct per burst (plain
-    launches); nvsm_reconstruct_batch per parameter class (eager); the two
-    batch calls captured once in a HIP graph and replayed."""
+    """16 bursts of uneven shape: 8 x 2560x2160 and 8 x 1024x1024, uint16,
+    frame counts uniform in [80, 150], 128^2 patches.  The v radius of each
+    class is tuned on its first burst (nvsm_tune_radius: the smallest R in
+    6..12 resp. 6..10 whose phases agree with the largest R's within
+    --tune-tol rad).  Three ways, same images at that schedule: one
+    nvsm_reconstruct per burst (plain launches); nvsm_reconstruct_batch per
+    class (eager); the two batch calls captured once in a HIP graph and
+    replayed."""
     import dataclasses
     import synth
     import torch
@@ -136,6 +139,18 @@ def batch16(args):
     print(f"[bench] generated 16 bursts (F = {list(map(int, Fs))}) in {time.perf_counter() - t:.1f} s",
           file=sys.stderr, flush=True)
     ctx = nv.nvsm_create(0)
+    # the v-radius schedule: one R per class, tuned on the class's first burst
+    schedule = []
+    for p, items in classes:
+        d, stf, _ = items[0]
+        F, H, W = d.shape
+        r_max = p.v_radius
+        wt = torch.empty(nv.nvsm_tune_radius_plan(p, H, W, F, r_max), dtype=torch.uint8, device="cuda")
+        r, meas = nv.nvsm_tune_radius(ctx, p, d, stf, 6, r_max, args.tune_tol, wt)
+        del wt
+        schedule.append({"r_max": r_max, "v_radius": r, "phase_rms_vs_r_max": {k: round(v, 4) for k, v in meas.items()}})
+        p.v_radius = r
+    print(f"[bench] v-radius schedule (tol {args.tune_tol} rad): {schedule}", file=sys.stderr, flush=True)
     terms = 0
     cap = int(args.batch_ws_gib * (1 << 30))
     ws_need = 0
@@ -209,8 +224,10 @@ def batch16(args):
         "value": 16 / t_graph, "unit": "bursts/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": t_graph * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batch16: 8 x 2560x2160 (|v|<=12) + 8 x 1024x1024 (|v|<=10) uint16 bursts, "
-                               f"F = {list(map(int, Fs))}, 128x128 patches, one HIP graph of two batch calls",
+        "config": {"workload": f"batch16: 8 x 2560x2160 (|v|<={classes[0][0].v_radius}) + 8 x 1024x1024 "
+                               f"(|v|<={classes[1][0].v_radius}) uint16 bursts, F = {list(map(int, Fs))}, 128x128 "
+                               f"patches, v radii tuned at {args.tune_tol} rad, one HIP graph of two batch calls",
+                   "v_radius_schedule": schedule,
                    "terms": int(terms), "workspace_GiB": ws.numel() / (1 << 30),
                    "tuned_launch": [{"slots": k, "form": f} for k, f in tuned], "parallelism": "single GPU"},
         "per_burst_plain": {"bursts_per_s": 16 / t_plain, "ms": t_plain * 1e3},
@@ -226,8 +243,9 @@ def batch16(args):
 
 def serve3(args):
     """Three channels (2 x 2560x2160 |v|<=12, 1 x 1024x1024 |v|<=10) deliver
-    bursts of F uniform in [70, 130] frames at 10 frames/s each, on a
-    simulated clock divided by --compress.  The same schedule is served by
+    bursts of F uniform in [70, 130] frames at 10 frames/s each, the idle
+    time before each burst exponential with mean --gap-s (a Poisson stream
+    of bursts per detector), on a simulated clock divided by --compress.  The same schedule is served by
     the streaming policy (running sums on the device, adaptive groups) and
     by the plain policy (one reconstruction after each burst's last frame);
     latency runs from a burst's last frame to its image being ready."""
@@ -247,7 +265,8 @@ def serve3(args):
         pinned = torch.from_numpy(fr.view(np.int16)).pin_memory()     # a new pinned tensor
         pool[name] = pinned.numpy().view(np.uint16)
     print(f"[bench] generated frame pools in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
-    events = serve.schedule([s.name for s in specs], seconds=args.sim_seconds, fps=10.0, fmin=70, fmax=130, seed=1)
+    events = serve.schedule([s.name for s in specs], seconds=args.sim_seconds, fps=10.0, fmin=70, fmax=130,
+                            gap_s=args.gap_s, seed=1)
     frames_of = lambda c, k, f: pool[c][f]  # noqa: E731
     results = {}
     for policy, kw in (("plain", {}), ("stream", dict(group=args.group, max_group=args.max_group))):
@@ -284,6 +303,7 @@ def serve3(args):
         "ms_per_step": st["wall_s"] * 1e3 / max(1, st["bursts"]), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"serve3: {args.sim_seconds:.0f} s of arrivals at 10 fps per channel, F in [70,130], "
+                               f"Poisson bursts (exponential idle time, mean {args.gap_s:g} s), "
                                f"clock / {args.compress:g}, streaming groups {args.group}..{args.max_group}",
                    "parallelism": "single GPU"},
         "paced": results, "saturated": sat,
@@ -415,12 +435,16 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for traffic counters)")
     ap.add_argument("--batch-ws-gib", type=float, default=96.0, help="workspace cap of the batch16 workload")
+    ap.add_argument("--tune-tol", type=float, default=0.3,
+                    help="batch16: phase agreement (rad, power-weighted RMS) that sets each class's v radius")
     ap.add_argument("--sim-seconds", type=float, default=600.0, help="serve3: simulated seconds of arrivals")
     ap.add_argument("--compress", type=float, default=20.0, help="serve3: simulated clock / wall clock")
     ap.add_argument("--group", type=int, default=10, help="serve3: frames per streaming group when the GPU is idle")
-    ap.add_argument("--max-group", type=int, default=40, help="serve3: largest streaming group")
+    ap.add_argument("--max-group", type=int, default=130, help="serve3: largest streaming group")
+    ap.add_argument("--gap-s", type=float, default=2.0,
+                    help="serve3: mean idle time before each burst of a channel (exponential; 0: back to back)")
     ap.add_argument("--serve-budget-gib", type=float, default=160.0, help="serve3: HBM for burst slots")
-    ap.add_argument("--sat-bursts", type=int, default=4, help="serve3: bursts per channel of the unpaced run")
+    ap.add_argument("--sat-bursts", type=int, default=8, help="serve3: bursts per channel of the unpaced run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -525,9 +549,14 @@ def main():
     info = s.info
     P, S = info.patches, info.s_count
     terms = P * S * F
-    bis_ms = stages["bispectrum"][0] / max(1, stages["bispectrum"][1])
-    achieved = terms * FLOP_PER_TERM / (bis_ms * 1e-3) / 1e12
-    stage_ms = {k: v[0] / max(1, v[1]) for k, v in stages.items()}
+    # per step: the library records each launch of a stage (the bispectrum
+    # runs its patch ranges back to back on the launch stream; the solve of
+    # each range runs on a second stream, overlapping the next range's
+    # bispectrum)
+    bis_launches = stages["bispectrum"][1] / args.steps
+    bis_ms = stages["bispectrum"][0] / max(1, stages["bispectrum"][1])       # per launch
+    achieved = terms * FLOP_PER_TERM / bis_launches / (bis_ms * 1e-3) / 1e12
+    stage_ms = {k: v[0] / args.steps for k, v in stages.items()}
     out = {
         "metric": METRIC,
         "value": value,
@@ -550,8 +579,8 @@ def main():
             "frames": F, "height": H, "width": W, "patch": p.patch, "v_radius": p.v_radius,
             "patches": P, "bispectrum_samples_per_patch": S, "parallelism": "single GPU",
         },
-        "bispectrum_GBps": terms * BYTES_PER_TERM / (bis_ms * 1e-3) / 1e9,
-        "bispectrum_terms_per_s": terms / (bis_ms * 1e-3),
+        "bispectrum_GBps": terms * BYTES_PER_TERM / (stage_ms["bispectrum"] * 1e-3) / 1e9,
+        "bispectrum_terms_per_s": terms / (stage_ms["bispectrum"] * 1e-3),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "stage_ms": stage_ms,
@@ -567,8 +596,9 @@ def main():
             "traffic": measured_traffic(args.workload),
             "traffic_unit": "bytes per launch (HBM read+write, copy-calibrated FETCH_SIZE/WRITE_SIZE)",
             "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
-            "algorithmic_flop_per_launch": terms * FLOP_PER_TERM,
+            "algorithmic_flop_per_launch": terms * FLOP_PER_TERM / bis_launches,
             "avg_launch_ms": bis_ms,
+            "launches_per_step": bis_launches,
         },
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }

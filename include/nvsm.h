@@ -193,7 +193,14 @@ nvsm_status nvsm_synthesize(nvsm_context *ctx, const nvsm_params *p, int32_t H, 
 
 /* The whole path: frames (device) in, image out (device float [H][W]).
  * Equivalent to accumulate + solve + synthesize with all intermediates in
- * the workspace (nvsm_plan_info.ws_reconstruct bytes). */
+ * the workspace (nvsm_plan_info.ws_reconstruct bytes).  When the call
+ * returns (and likewise after nvsm_reconstruct_batch, for the P patches of
+ * its last launch group, numbered burst by burst) the workspace starts with
+ * the intermediates in this order, each at a 256-byte aligned offset:
+ * power float [P][N][N], mean_spec float [P][2][2], mu float [P],
+ * bispec float [P][|S|][2], amp double [P][|W|], phasor double [P][|W|][2],
+ * subimages float [P][N][N] (each as nvsm_accumulate, nvsm_solve and
+ * nvsm_synthesize define them). */
 nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p,
                              const void *frames, nvsm_dtype dtype, int32_t F,
                              int32_t H, int32_t W, int64_t row_pitch,
@@ -258,9 +265,10 @@ nvsm_status nvsm_reconstruct_batch(nvsm_context *ctx, const nvsm_params *p, nvsm
  *     [H][W].
  * Calls on one state or one ws must be ordered (same stream or events);
  * different states are independent, so bursts of several channels may run
- * on several streams, each with its own ws.  The slot count of p's launch
- * choice must not change during a burst.  None of these calls allocates
- * device memory once the plan exists. */
+ * on several streams, each with its own ws.  These calls always run 16
+ * slots per wave (see nvsm_autotune), so the state's layout does not depend
+ * on the launch choice, which may change between the calls of a burst.
+ * None of these calls allocates device memory once the plan exists. */
 nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t group_frames,
                              size_t *state_bytes, size_t *ws_bytes);
 nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void *frames,
@@ -276,7 +284,11 @@ nvsm_status nvsm_stream_finish(nvsm_context *ctx, const nvsm_params *p, int32_t 
  * output is identical whichever is chosen; only the time differs:
  *   slots per wave: 16 or 24 v values per wave of a work item;
  *   form: 0 one workgroup per work item, 1 a persistent grid of resident
- *         workgroups taking items from per-XCD work queues.
+ *         workgroups taking items from per-XCD work queues (their counters
+ *         live in the call's own workspace, so calls with different
+ *         workspaces may run concurrently on different streams).
+ * The streaming calls keep 16 slots per wave whatever the choice (their
+ * running sums are stored in that kernel's lane order) and use its form.
  * nvsm_autotune runs the ingest once on the given burst (device frames,
  * as for nvsm_reconstruct, with a workspace of ws_reconstruct bytes), then
  * times the bispectrum launch of each candidate with HIP events and keeps
@@ -289,6 +301,29 @@ nvsm_status nvsm_autotune(nvsm_context *ctx, const nvsm_params *p,
                           void *workspace, size_t workspace_bytes, void *stream,
                           int32_t *slots_out, int32_t *form_out);
 nvsm_status nvsm_set_launch(nvsm_context *ctx, const nvsm_params *p, int32_t slots, int32_t form);
+
+/* The v radius R of a schedule (one R per patch size and burst shape, e.g.
+ * per class of a batch), chosen on the caller's burst at a stated accuracy.
+ * R sets how many bispectrum samples the phase recursion averages (Sections
+ * 2 and 3.2; the paper does not state its domain); the work grows as R^2.
+ * On the patches of the burst's central crop (at most 512 x 512 px) the
+ * path runs at R = r_max and then at r_min, r_min + 1, ... (p otherwise),
+ * and stops at the first R whose phases agree with those at r_max within
+ * tol radians: the power-weighted RMS of the wrapped phase difference over
+ * W and the crop's patches, sqrt(sum P dphi^2 / sum P), P(w) the mean power
+ * spectrum of the frames (the frequencies the frames carry strongly count
+ * most; the STF-divided modulus would weight the noise-dominated high
+ * frequencies most).  *r_out receives that R (r_max when none is closer);
+ * err (host double [r_max - r_min + 1], or NULL) the measure of every R
+ * tried (0 at r_max, NaN where not run).  frames, stf as nvsm_reconstruct;
+ * workspace: nvsm_tune_radius_plan bytes.  Builds the tables of every R it
+ * runs; waits for `stream` (copies the phases to the host). */
+nvsm_status nvsm_tune_radius_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t F, int32_t r_max,
+                                  size_t *ws_bytes);
+nvsm_status nvsm_tune_radius(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
+                             int32_t F, int32_t H, int32_t W, int64_t row_pitch, const double *stf,
+                             int32_t r_min, int32_t r_max, double tol, void *workspace,
+                             size_t workspace_bytes, void *stream, int32_t *r_out, double *err);
 
 /* Model speckle transfer function (the STF of Eq. 1 chosen by the seeing
  * D/r0, Sections 2 and 3.2; the paper gives no model, so this is a reading):

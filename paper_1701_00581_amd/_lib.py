@@ -28,7 +28,7 @@ EXPORTS = [
     "nvsm_default_params", "nvsm_plan", "nvsm_w_index", "nvsm_bispectrum_index",
     "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
     "nvsm_profile_enable", "nvsm_profile_read", "nvsm_batch_plan", "nvsm_reconstruct_batch",
-    "nvsm_autotune", "nvsm_set_launch", "nvsm_stream_plan", "nvsm_stream_add", "nvsm_stream_finish",
+    "nvsm_autotune", "nvsm_set_launch", "nvsm_tune_radius_plan", "nvsm_tune_radius", "nvsm_stream_plan", "nvsm_stream_add", "nvsm_stream_finish",
     "nvsm_model_stf_plan", "nvsm_model_stf", "nvsm_seeing_default_params", "nvsm_seeing_plan", "nvsm_seeing",
 ]
 STAGES = ["ingest", "bispectrum", "solve", "synthesize"]
@@ -110,6 +110,9 @@ def lib():
         L.nvsm_autotune.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_p, c_sz, c_p,
                                     ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
         L.nvsm_set_launch.argtypes = [c_p, P, c_i32, c_i32]
+        L.nvsm_tune_radius_plan.argtypes = [P, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]
+        L.nvsm_tune_radius.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_p, c_i32, c_i32,
+                                       ctypes.c_double, c_p, c_sz, c_p, ctypes.POINTER(c_i32), c_p]
         L.nvsm_stream_plan.argtypes = [P, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz), ctypes.POINTER(c_sz)]
         L.nvsm_stream_add.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_i32, c_i32, c_p,
                                       c_sz, c_p, c_sz, c_p]
@@ -323,6 +326,28 @@ def nvsm_autotune(ctx, params, frames, workspace, stream=None, row_pitch=None):
 
 def nvsm_set_launch(ctx, params, slots, form):
     _check(lib().nvsm_set_launch(ctx, ctypes.byref(params), int(slots), int(form)), "nvsm_set_launch", ctx)
+
+
+def nvsm_tune_radius_plan(params, H, W, F, r_max):
+    n = ctypes.c_size_t()
+    _check(lib().nvsm_tune_radius_plan(ctypes.byref(params), H, W, F, r_max, ctypes.byref(n)),
+           "nvsm_tune_radius_plan")
+    return n.value
+
+
+def nvsm_tune_radius(ctx, params, frames, stf, r_min, r_max, tol, workspace, stream=None, row_pitch=None):
+    """(chosen R, {R: phase measure}) on the burst; see nvsm.h."""
+    import math
+    F, H, W = frames.shape
+    pitch = _row_pitch(frames, row_pitch)
+    r = ctypes.c_int32()
+    err = (ctypes.c_double * (r_max - r_min + 1))()
+    st = lib().nvsm_tune_radius(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W, pitch,
+                                _ptr(stf), r_min, r_max, float(tol), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream), ctypes.byref(r),
+                                ctypes.cast(err, ctypes.c_void_p))
+    _check(st, "nvsm_tune_radius", ctx)
+    return r.value, {r_min + i: err[i] for i in range(len(err)) if not math.isnan(err[i])}
 
 
 def nvsm_stream_plan(params, H, W, group_frames):

@@ -2,18 +2,22 @@
 //
 // One workgroup per patch.  Frequencies are visited shell by shell (|w|^2
 // ascending); every w of a shell reads only strictly shorter frequencies,
-// so a shell's w are independent: wave j takes the shell's w number j and
-// j + 8 (at most 16 w per shell), its lanes split that w's bispectrum
-// samples, and a wave reduction (DPP) gives
+// so a shell's w are independent.  The planner cuts each shell into units
+// of at most 8 w; in a unit wave j takes w number j, its lanes split that
+// w's bispectrum samples, and a wave reduction (DPP) gives
 //   z(w) = sum_v e(w - v) e(v) conj B(w, v),  e(w) = z / |z|.
+// The workgroup waits at a barrier only after the last unit of a shell.
 // Since |v| <= R, a shell only reads phasors with |x| <= R or
 // |x| >= |w| - R: those stay in LDS (the inner disk, plus a ring for the
 // annulus), which keeps the workgroup small enough for three per CU.  The
 // sample codes hold the LDS slot of each phasor for the sample's shell
 // (computed on the host), so a lookup is a plain LDS read.  Each phasor is
-// written to the output as soon as it is known.  The samples of
-// the next shells are loaded into registers while the current shell is
-// computed, so only LDS latency sits on the dependency chain.
+// written to the output as soon as it is known.  The samples of the next
+// DEPTH - 1 units are loaded into registers while the current unit is
+// computed: a unit's own work is far shorter than a load from HBM, so with
+// a single unit in flight the chain of shells waited on memory latency
+// (one w per wave and unit keeps a register set small enough for three in
+// flight at six waves per SIMD).
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -24,8 +28,11 @@ namespace {
 
 constexpr int NT = 512;
 constexpr int NWAVE = NT / 64;
-constexpr int WPW = 2;                   // w per wave and shell: 16 per shell
-constexpr int DEPTH = 2;                 // shells of samples in flight
+// units of samples in registers (DEPTH - 1 loading): as many as keep the
+// kernel at its occupancy (80 VGPRs at 6 waves per SIMD with 4 samples per
+// lane, 128 at 4 with 8)
+template <int TPL> constexpr int depth_of() { return TPL <= 4 ? 5 : 3; }
+static_assert(NWAVE == SOLVE_WAVES, "one w per wave and unit");
 
 __device__ __forceinline__ double2 unit_or_one(double2 z) {
     const double m = sqrt(z.x * z.x + z.y * z.y);
@@ -55,20 +62,18 @@ __device__ __forceinline__ double wave_total_lane63(double v) {
     return v;
 }
 
-// Samples of one shell for this lane: lane l takes samples l, l + 64, ...
-// of the wave's w number m (m < WPW).
+// Samples of one unit for this lane: lane l takes samples l, l + 64, ...
+// of the wave's w (w, cnt and bar are wave-uniform).
 template <int TPL>
-struct ShellRegs {
-    int w[WPW];
-    int cnt[WPW];
-    unsigned code[WPW][TPL];
-    float2 b[WPW][TPL];
+struct UnitRegs {
+    int w, cnt, bar, slot;
+    unsigned code[TPL];
+    float2 b[TPL];
 };
 
 template <int N, int TPL, int BIG>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6 : 2))) void k_solve(int nW, int nshell, const int *__restrict__ shell_wb,
-                                              const int *__restrict__ w_slot,
-                                              const int *__restrict__ woff, const unsigned *__restrict__ code,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6 : 2))) void k_solve(int nW, int n_units, const int *__restrict__ units,
+                                              const unsigned *__restrict__ code,
                                               const int *__restrict__ Wxy, const float *__restrict__ power,
                                               const float *__restrict__ mean_spec,
                                               const float2 *__restrict__ bispec, int64_t s_count,
@@ -133,98 +138,83 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
     }
 
     const float2 *B = bispec + (size_t)patch * s_count;
-    // Loads are issued unconditionally (clamped to entry 0 where there is no
-    // sample) so that every shell issues the same number of loads.
-    auto load = [&](int s, ShellRegs<TPL> &r) __attribute__((always_inline)) {
-        const int wb = shell_wb[s], nw = shell_wb[s + 1] - wb;
+    constexpr int DEPTH = depth_of<TPL>();
+    // A unit's table entry (this wave's w, first sample, count and barrier
+    // flag, LDS slot of the phasor) is read one unit before its samples are
+    // requested, so neither the sample loads nor the phasor's store wait on
+    // a table read.
+    auto entry = [&](int u) __attribute__((always_inline)) {
+        const int *t = units + ((size_t)u * NWAVE + wave) * 4;
+        return make_int4(t[0], t[1], t[2], t[3]);
+    };
+    auto load = [&](const int4 t, UnitRegs<TPL> &r) __attribute__((always_inline)) {
+        r.w = t.x;
+        r.cnt = t.z & 0xffff;
+        r.bar = t.z >> 16;
+        r.slot = t.w;
 #pragma unroll
-        for (int m = 0; m < WPW; ++m) {
-            const int jj = wave + NWAVE * m;
-            const bool has = jj < nw;
-            const int w = has ? wb + jj : 0;
-            const int o = woff[w], cnt = has ? woff[w + 1] - o : 0;
-            r.w[m] = has ? w : -1;
-            r.cnt[m] = cnt;
-#pragma unroll
-            for (int i = 0; i < TPL; ++i) {
-                const int t = lane + 64 * i;
-                const int idx = t < cnt ? o + t : 0;
-                r.code[m][i] = code[idx];
-                r.b[m][i] = B[idx];
-            }
+        for (int i = 0; i < TPL; ++i) {
+            const int k = lane + 64 * i;
+            const int idx = k < r.cnt ? t.y + k : 0;
+            r.code[i] = code[idx];
+            r.b[i] = B[idx];
         }
     };
-    auto solve = [&](const ShellRegs<TPL> &r) __attribute__((always_inline)) {
-        if (r.w[0] < 0) return;                   // no w of this shell in this wave
-        double zx[WPW], zy[WPW];
+    // Branch-free over the samples (a lane's unused slots hold sample 0 and
+    // add zero), so that the compiler knows how many loads are in flight at
+    // every use and waits only for the unit's own.
+    auto solve = [&](const UnitRegs<TPL> &r) __attribute__((always_inline)) {
+        if (r.w < 0) return;                      // no w of this unit in this wave
+        double zx = 0.0, zy = 0.0;
 #pragma unroll
-        for (int m = 0; m < WPW; ++m) {
-            zx[m] = 0.0;
-            zy[m] = 0.0;
-#pragma unroll
-            for (int i = 0; i < TPL; ++i) {
-                const int t = lane + 64 * i;
-                if (t < r.cnt[m]) {
-                    const unsigned cd = r.code[m][i];
-                    const unsigned ia = cd >> 16, ib = cd & 0xffffu;
-                    double2 ea = e[ia & 0x7fffu];
-                    double2 eb = e[ib & 0x7fffu];
-                    if (ia & 0x8000u) ea.y = -ea.y;
-                    if (ib & 0x8000u) eb.y = -eb.y;
-                    const double px = ea.x * eb.x - ea.y * eb.y;
-                    const double py = ea.x * eb.y + ea.y * eb.x;
-                    const double bx = (double)r.b[m][i].x, by = (double)r.b[m][i].y;
-                    // (px + i py) * conj(bx + i by)
-                    zx[m] += px * bx + py * by;
-                    zy[m] += py * bx - px * by;
-                }
-            }
+        for (int i = 0; i < TPL; ++i) {
+            const int k = lane + 64 * i;
+            const unsigned cd = r.code[i];
+            const unsigned ia = cd >> 16, ib = cd & 0xffffu;
+            double2 ea = e[ia & 0x7fffu];
+            double2 eb = e[ib & 0x7fffu];
+            if (ia & 0x8000u) ea.y = -ea.y;
+            if (ib & 0x8000u) eb.y = -eb.y;
+            const double px = ea.x * eb.x - ea.y * eb.y;
+            const double py = ea.x * eb.y + ea.y * eb.x;
+            const double use = k < r.cnt ? 1.0 : 0.0;
+            const double bx = use * (double)r.b[i].x, by = use * (double)r.b[i].y;
+            // (px + i py) * conj(bx + i by)
+            zx += px * bx + py * by;
+            zy += py * bx - px * by;
         }
-        double tx[WPW], ty[WPW];
-#pragma unroll
-        for (int m = 0; m < WPW; ++m) {
-            // (wave-uniform: most shells give a wave one w, and the second
-            // one's reductions are then skipped; not with 8 samples per
-            // lane, where the branch costs the registers of 4 waves per SIMD)
-            if (TPL <= 4 && m > 0 && r.w[m] < 0) {
-                tx[m] = ty[m] = 0.0;
-                continue;
-            }
-            tx[m] = wave_total_lane63(zx[m]);
-            ty[m] = wave_total_lane63(zy[m]);
-        }
+        const double tx = wave_total_lane63(zx);
+        const double ty = wave_total_lane63(zy);
         if (lane == 63) {
-#pragma unroll
-            for (int m = 0; m < WPW; ++m) {
-                if (r.w[m] >= 0) {
-                    const double n = tx[m] * tx[m] + ty[m] * ty[m];
-                    double2 v = make_double2(1.0, 0.0);
-                    if (n > 0.0) {
-                        const double rn = rsqrt(n);
-                        v = make_double2(tx[m] * rn, ty[m] * rn);
-                    }
-                    e[w_slot[r.w[m]]] = v;
-                    ph_out[r.w[m]] = v;
-                }
+            const double n = tx * tx + ty * ty;
+            double2 v = make_double2(1.0, 0.0);
+            if (n > 0.0) {
+                const double rn = rsqrt(n);
+                v = make_double2(tx * rn, ty * rn);
             }
+            e[r.slot] = v;
+            ph_out[r.w] = v;
         }
     };
 
     __syncthreads();
-    // shells 1.. in order; the samples of shell s + DEPTH - 1 are loaded
-    // while shell s is solved (a ring of DEPTH register sets)
-    ShellRegs<TPL> buf[DEPTH];
+    // units in order; the samples of unit u + DEPTH - 1 are requested while
+    // unit u is solved (a ring of DEPTH register sets).  Every step requests
+    // one unit (past the end: the last unit again, never solved), so the
+    // number of loads in flight is the same at every step.
+    UnitRegs<TPL> buf[DEPTH];
 #pragma unroll
-    for (int d = 0; d < DEPTH - 1; ++d)
-        if (1 + d < nshell) load(1 + d, buf[d]);
-    for (int s0 = 1; s0 < nshell; s0 += DEPTH) {
+    for (int d = 0; d < DEPTH - 1; ++d) load(entry(min(d, n_units - 1)), buf[d]);
+    int4 next = entry(min(DEPTH - 1, n_units - 1));
+    for (int u0 = 0; u0 < n_units; u0 += DEPTH) {
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d) {
-            const int s = s0 + d;
-            if (s < nshell) {
-                if (s + DEPTH - 1 < nshell) load(s + DEPTH - 1, buf[(d + DEPTH - 1) % DEPTH]);
+            const int u = u0 + d;
+            load(next, buf[(d + DEPTH - 1) % DEPTH]);
+            next = entry(min(u + DEPTH, n_units - 1));
+            if (u < n_units) {
                 solve(buf[d]);
-                __syncthreads();
+                if (buf[d].bar) __syncthreads();
             }
         }
     }
@@ -389,8 +379,8 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, 
 
 template <int N, int TPL, int BIG>
 hipError_t launch_solve_t(const SolveArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_solve<N, TPL, BIG>), dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.nshell, a.shell_wb,
-                       a.w_slot, a.woff, a.code, a.Wxy, a.power, a.mean_spec, a.bispec,
+    hipLaunchKernelGGL((k_solve<N, TPL, BIG>), dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.n_units, a.units,
+                       a.code, a.Wxy, a.power, a.mean_spec, a.bispec,
                        a.s_count, a.bt, a.floor, a.noise_bias, a.amp, a.phasor);
     return hipGetLastError();
 }

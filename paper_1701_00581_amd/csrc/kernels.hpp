@@ -153,6 +153,8 @@ struct SolveArgs {
     BurstTable bt;                        // patches and the STF of each burst
     const int *shell_wb = nullptr, *woff = nullptr, *Wxy = nullptr;
     const int *w_slot = nullptr;          // LDS slot of each w's phasor
+    const int *units = nullptr;           // phase-solve units (see plan.hpp)
+    int n_units = 0;
     int n_inner = 0, ring = 0;            // phasor window (see plan.hpp)
     const unsigned *code = nullptr;       // sample codes with LDS slots
     const float *power = nullptr, *mean_spec = nullptr;

@@ -24,6 +24,7 @@ namespace {
 
 constexpr int CHUNK_FRAMES = 20;     // frames per ingest workgroup (even)
 constexpr size_t ALIGN = 256;
+constexpr size_t QUEUE_BYTES = 256;  // 8 int counters, padded to the alignment
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -31,7 +32,7 @@ struct DevicePlan {
     HostPlan h;
     int nshell = 0, max_sw = 0;
     std::vector<void *> bufs;
-    int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr,
+    int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr, *units = nullptr,
         *group_xy = nullptr, *slot = nullptr, *out_idx = nullptr, *lsq_fin = nullptr;
     unsigned *code = nullptr, *wcode = nullptr;
     float2 *twiddle = nullptr;
@@ -53,14 +54,12 @@ struct nvsm_context {
     std::map<std::tuple<int, int, int, int>, std::unique_ptr<DevicePlan>> plans;
     // launch choices by (N, u_cut, v_radius): slots per wave, bispectrum form
     std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
-    int *queue = nullptr;                // [8] work-queue counters of the persistent bispectrum
     // stage timing
     bool prof = false;
     std::vector<hipEvent_t> free_ev;
     struct Rec { int stage; hipEvent_t a, b; };
     std::vector<Rec> recs;
     ~nvsm_context() {
-        if (queue) (void)hipFree(queue);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : free_ev) (void)hipEventDestroy(e);
     }
@@ -115,6 +114,7 @@ struct Sizes {
     int64_t P = 0, nW = 0, S = 0, records = 0, wgs = 0;
     size_t spectra = 0, ppart = 0, mpart = 0, mupart = 0;      // accumulate scratch
     size_t cpart = 0, spart = 0, cw = 0, nbar = 0;             // photon-noise terms (noise_bias 2)
+    size_t queue = 0;                                          // work-queue counters of this call
     size_t power = 0, mean = 0, mu = 0, bispec = 0, amp = 0, phasor = 0, patches = 0;
 };
 
@@ -169,6 +169,7 @@ void sizes_for(int N, const BurstTable &bt, int64_t records, int64_t nW, int64_t
     z->amp = align_up((size_t)z->P * nW * 8);
     z->phasor = align_up((size_t)z->P * nW * 16);
     z->patches = align_up((size_t)z->P * N * N * 4);
+    z->queue = QUEUE_BYTES;
     if (photon) {
         z->cpart = align_up((size_t)z->wgs * (N / 2 + 1) * N * 8);
         z->spart = align_up((size_t)z->wgs * 2 * 4);
@@ -178,11 +179,20 @@ void sizes_for(int N, const BurstTable &bt, int64_t records, int64_t nW, int64_t
 }
 
 size_t ws_acc(const Sizes &z) {
-    return z.spectra + z.ppart + z.mpart + z.mupart + z.cpart + z.spart + z.cw + z.nbar;
+    return z.spectra + z.ppart + z.mpart + z.mupart + z.cpart + z.spart + z.cw + z.nbar + z.queue;
 }
+
+// The persistent bispectrum's 8 work-queue counters live in the call's own
+// workspace (after the rest of the accumulate scratch), so calls on
+// different streams with different workspaces never share them.
+int *queue_of(char *acc_ws, const Sizes &z) { return (int *)(acc_ws + ws_acc(z) - z.queue); }
 size_t ws_rec(const Sizes &z) {
     return z.power + z.mean + z.mu + z.bispec + z.amp + z.phasor + z.patches + ws_acc(z);
 }
+
+// The streaming calls always run this many slots per wave, so the state's
+// layout (the kernel's lane order) does not depend on the launch choice.
+constexpr int STREAM_SLOTS = 16;
 
 // Streaming buffers.  The state of one burst holds the running
 // (sum, compensation) pairs: the bispectrum terms in the kernel's lane order
@@ -274,13 +284,6 @@ std::pair<int, int> choice_of(const nvsm_context *ctx, const nvsm_params *p) {
 }
 
 nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DevicePlan **out) {
-    if (!ctx->queue) {
-        if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NVSM_ERR_HIP, "hipSetDevice failed");
-        if (hipMalloc((void **)&ctx->queue, 8 * sizeof(int)) != hipSuccess) {
-            ctx->queue = nullptr;
-            return fail(ctx, NVSM_ERR_OOM, "hipMalloc failed for the work queue");
-        }
-    }
     auto key = std::make_tuple(p->patch, p->u_cut, p->v_radius, slots);
     auto f = ctx->plans.find(key);
     if (f != ctx->plans.end()) { *out = f->second.get(); return NVSM_OK; }
@@ -313,6 +316,7 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
         (s = upload(dp.get(), h.woff, &dp->woff, &msg)) ||
         (s = upload(dp.get(), h.shell_wb, &dp->shell_wb, &msg)) ||
         (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
+        (s = upload(dp.get(), h.solve_units, &dp->units, &msg)) ||
         (s = upload(dp.get(), h.phase_slot_code, &dp->code, &msg)) ||
         (s = upload(dp.get(), h.phase_code, &dp->wcode, &msg)) ||
         (s = upload(dp.get(), h.lsq_fin, &dp->lsq_fin, &msg)) ||
@@ -369,6 +373,24 @@ bool vec_ok(const nvsm_params *p, const BurstTable &bt, size_t px_bytes) {
     return true;
 }
 
+// The bispectrum launch of a table over its accumulate scratch ws.
+BispecArgs bispec_args(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt, const Sizes &z,
+                       float *bispec, char *ws) {
+    BispecArgs b;
+    b.N = p->patch; b.bt = bt; b.spectra = (const float2 *)ws;
+    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy;
+    b.slot_v = dp->slot; b.out_idx = dp->out_idx;
+    b.bispec = (float2 *)bispec; b.s_count = z.S;
+    b.form = choice_of(ctx, p).second; b.queue = queue_of(ws, z);
+    if (p->noise_bias == 2) {
+        // the photon-noise terms' place in the scratch (see run_accumulate)
+        char *q = ws + z.spectra + z.ppart + z.mpart + z.mupart + z.cpart + z.spart;
+        b.acc.noise_c = (const float2 *)q;
+        b.acc.noise_t = (const float *)(q + z.cw);
+    }
+    return b;
+}
+
 hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
                           const Sizes &z, nvsm_dtype dtype, float *power, float *mean_spec, float *mu,
                           float *bispec, char *ws, hipStream_t st) {
@@ -403,15 +425,8 @@ hipError_t run_accumulate(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *
         if (e == hipSuccess && p->noise_bias == 2) e = launch_noise(na, st);
     }
     if (e != hipSuccess || bispec == nullptr) return e;
-    BispecArgs b;
-    b.N = p->patch; b.bt = bt; b.spectra = a.spectra;
-    b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy;
-    b.slot_v = dp->slot; b.out_idx = dp->out_idx;
-    b.bispec = (float2 *)bispec; b.s_count = z.S;
-    b.form = choice_of(ctx, p).second; b.queue = ctx->queue;
-    if (p->noise_bias == 2) { b.acc.noise_c = na.cgrid; b.acc.noise_t = na.nbar; }
     StageTimer t(ctx, ST_BISPEC, st);
-    return launch_bispec(b, st);
+    return launch_bispec(bispec_args(ctx, dp, p, bt, z, bispec, ws), st);
 }
 
 hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, const BurstTable &bt,
@@ -421,6 +436,7 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, co
     a.N = p->patch; a.bt = bt; a.nW = (int)(dp->h.W.size() / 2); a.nshell = dp->nshell;
     a.max_sw = dp->max_sw; a.shell_wb = dp->shell_wb; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
     a.w_slot = dp->w_slot; a.n_inner = dp->h.n_inner; a.ring = dp->h.ring_size;
+    a.units = dp->units; a.n_units = dp->h.n_units;
     a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;
     a.floor = p->stf_floor; a.noise_bias = p->noise_bias == 1; a.amp = amp;
     a.phasor = (double2 *)phasor;
@@ -828,7 +844,7 @@ nvsm_status nvsm_autotune(nvsm_context *ctx, const nvsm_params *p, const void *f
         b.N = p->patch; b.bt = bt; b.spectra = (const float2 *)w;
         b.n_items = dc->h.n_items; b.slots = dc->h.slots; b.items = dc->items; b.group_xy = dc->group_xy;
         b.slot_v = dc->slot; b.out_idx = dc->out_idx; b.bispec = (float2 *)bis; b.s_count = z.S;
-        b.form = cand[c][1]; b.queue = ctx->queue;
+        b.form = cand[c][1]; b.queue = queue_of(w, z);
         float t = 1e30f;
         for (int r = 0; r < 3 && e == hipSuccess; ++r) {       // the first run warms up
             e = hipEventRecord(e0, st);
@@ -849,6 +865,151 @@ nvsm_status nvsm_autotune(nvsm_context *ctx, const nvsm_params *p, const void *f
     ctx->tuned[std::make_tuple(p->patch, p->u_cut, p->v_radius)] = pick;
     if (slots_out) *slots_out = pick.first;
     if (form_out) *form_out = pick.second;
+    return NVSM_OK;
+}
+
+// The central crop the v-radius tuner works on: at most TUNE_CROP px a side,
+// x0 a multiple of 4 (keeps vector pixel loads).
+constexpr int TUNE_CROP = 512;
+static void tune_crop(int H, int W, int *y0, int *x0, int *Hc, int *Wc) {
+    *Hc = std::min(H, TUNE_CROP);
+    *Wc = std::min(W, TUNE_CROP);
+    *y0 = (H - *Hc) / 2;
+    *x0 = (W - *Wc) / 2 / 4 * 4;
+}
+
+static nvsm_status tune_sizes(const nvsm_params *p, int32_t H, int32_t W, int32_t F, int32_t r_max, Sizes *z,
+                              std::string *msg) {
+    nvsm_params q = *p;
+    q.v_radius = r_max;
+    nvsm_status s = check_params(&q, msg);
+    if (s != NVSM_OK) return s;
+    if ((s = check_shape(&q, H, W, F, msg)) != NVSM_OK) return s;
+    int y0, x0, Hc, Wc;
+    tune_crop(H, W, &y0, &x0, &Hc, &Wc);
+    int64_t nW, S;
+    int shells;
+    try {
+        count_sets(&q, &nW, &S, &shells);
+    } catch (const std::bad_alloc &) {
+        return NVSM_ERR_OOM;
+    }
+    BurstIn bi;
+    bi.F = F; bi.H = Hc; bi.W = Wc; bi.pitch = Wc;
+    BurstTable bt;
+    int64_t rec;
+    make_table(&q, &bi, 1, &bt, &rec);
+    sizes_for(q.patch, bt, rec, nW, S, z, q.noise_bias == 2);
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_tune_radius_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t F, int32_t r_max,
+                                  size_t *ws_bytes) {
+    if (!ws_bytes) return NVSM_ERR_INVALID_ARG;
+    std::string msg;
+    Sizes z;
+    nvsm_status s = tune_sizes(p, H, W, F, r_max, &z, &msg);
+    if (s != NVSM_OK) return s;
+    *ws_bytes = ws_rec(z);
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_tune_radius(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
+                             int32_t F, int32_t H, int32_t W, int64_t row_pitch, const double *stf, int32_t r_min,
+                             int32_t r_max, double tol, void *workspace, size_t workspace_bytes, void *stream,
+                             int32_t *r_out, double *err) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!frames || !stf || !r_out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    if (r_min < 1 || r_min > r_max) return fail(ctx, NVSM_ERR_INVALID_ARG, "need 1 <= r_min <= r_max");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(ctx, NVSM_ERR_INVALID_ARG, "tol must be finite and >= 0");
+    std::string msg;
+    Sizes zmax;
+    nvsm_status s = tune_sizes(p, H, W, F, r_max, &zmax, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    {
+        nvsm_params q = *p;
+        q.v_radius = r_min;
+        if ((s = check_params(&q, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    }
+    BurstIn full;
+    full.frames = frames; full.F = F; full.H = H; full.W = W; full.pitch = row_pitch; full.stf = stf;
+    if ((s = check_burst(p, full, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    if (!workspace || workspace_bytes < ws_rec(zmax)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for tuning");
+    int y0, x0, Hc, Wc;
+    tune_crop(H, W, &y0, &x0, &Hc, &Wc);
+    const size_t px = dtype == NVSM_F32 ? 4 : 2;
+    BurstIn bi = full;
+    bi.frames = (const char *)frames + ((size_t)y0 * row_pitch + x0) * px;
+    bi.H = Hc; bi.W = Wc;
+    hipStream_t st = (hipStream_t)stream;
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    // phasors of the crop's patches at radius r (and the weights: the mean
+    // power at each w of W), on the host
+    auto run = [&](int r, std::vector<double> *wt, std::vector<double> *ph) -> nvsm_status {
+        nvsm_params q = *p;
+        q.v_radius = r;
+        q.phase_method = 0;
+        DevicePlan *dp;
+        BurstTable bt;
+        Sizes z;
+        nvsm_status t = prepare_call(ctx, &q, bi, &dp, &bt, &z);
+        if (t != NVSM_OK) return t;
+        char *w = (char *)workspace;
+        float *power = (float *)w; w += z.power;
+        float *mean = (float *)w; w += z.mean;
+        float *mu = (float *)w; w += z.mu;
+        float *bis = (float *)w; w += z.bispec;
+        double *a = (double *)w; w += z.amp;
+        double *e = (double *)w; w += z.phasor;
+        w += z.patches;
+        hipError_t h = run_accumulate(ctx, dp, &q, bt, z, dtype, power, mean, mu, bis, w, st);
+        if (h == hipSuccess) h = run_solve(ctx, dp, &q, bt, power, mean, bis, a, e, st);
+        const int N = q.patch;
+        std::vector<float> pw;
+        if (wt) pw.resize((size_t)z.P * N * N);
+        ph->resize((size_t)z.P * z.nW * 2);
+        if (h == hipSuccess) h = hipMemcpyAsync(ph->data(), e, ph->size() * 8, hipMemcpyDeviceToHost, st);
+        if (h == hipSuccess && wt) h = hipMemcpyAsync(pw.data(), power, pw.size() * 4, hipMemcpyDeviceToHost, st);
+        if (h == hipSuccess) h = hipStreamSynchronize(st);
+        if (h != hipSuccess) return hip_fail(ctx, h, "radius tuning");
+        if (wt) {
+            wt->resize((size_t)z.P * z.nW);
+            const std::vector<int32_t> &Wl = dp->h.W;
+            for (int64_t k = 0; k < z.P; ++k)
+                for (int64_t i = 0; i < z.nW; ++i)
+                    (*wt)[k * z.nW + i] =
+                        pw[(size_t)k * N * N + (size_t)(Wl[2 * i + 1] & (N - 1)) * N + (Wl[2 * i] & (N - 1))];
+        }
+        return NVSM_OK;
+    };
+    std::vector<double> wmax, emax, e;
+    s = run(r_max, &wmax, &emax);
+    if (s == NVSM_OK && err)
+        for (int r = r_min; r <= r_max; ++r) err[r - r_min] = std::nan("");
+    int pick = r_max;
+    for (int r = r_min; s == NVSM_OK && r <= r_max; ++r) {
+        double d = 0.0;
+        if (r < r_max) {
+            if ((s = run(r, nullptr, &e)) != NVSM_OK) break;
+            double num = 0.0, den = 0.0;
+            for (size_t i = 0; i < wmax.size(); ++i) {
+                // wrapped phase difference: arg(e conj emax)
+                const double re = e[2 * i] * emax[2 * i] + e[2 * i + 1] * emax[2 * i + 1];
+                const double im = e[2 * i + 1] * emax[2 * i] - e[2 * i] * emax[2 * i + 1];
+                const double dphi = std::atan2(im, re);
+                num += wmax[i] * dphi * dphi;
+                den += wmax[i];
+            }
+            d = den > 0.0 ? std::sqrt(num / den) : 0.0;
+        }
+        if (err) err[r - r_min] = d;
+        if (d <= tol) { pick = r; break; }
+    }
+    ctx->prof = prof;
+    if (s != NVSM_OK) return s;
+    *r_out = pick;
     return NVSM_OK;
 }
 
@@ -874,19 +1035,11 @@ nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t
     if ((s = check_shape(p, H, W, group_frames, &msg)) != NVSM_OK) return s;
     HostPlan h;
     try {
-        if (!build_plan(p->patch, p->u_cut, p->v_radius, 16, &h, &msg)) return NVSM_ERR_INVALID_ARG;
+        if (!build_plan(p->patch, p->u_cut, p->v_radius, STREAM_SLOTS, &h, &msg)) return NVSM_ERR_INVALID_ARG;
     } catch (const std::bad_alloc &) {
         return NVSM_ERR_OOM;
     }
-    // sized for the larger slot count, so a tuned launch also fits
-    HostPlan h24;
-    try {
-        if (!build_plan(p->patch, p->u_cut, p->v_radius, 24, &h24, &msg)) return NVSM_ERR_INVALID_ARG;
-    } catch (const std::bad_alloc &) {
-        return NVSM_ERR_OOM;
-    }
-    const int64_t lane_terms = std::max((int64_t)h.n_items * BS_WAVES * 16 * 64,
-                                        (int64_t)h24.n_items * BS_WAVES * 24 * 64);
+    const int64_t lane_terms = (int64_t)h.n_items * BS_WAVES * STREAM_SLOTS * 64;
     BurstIn bi;
     bi.F = group_frames; bi.H = H; bi.W = W; bi.pitch = W;
     BurstTable bt;
@@ -909,7 +1062,7 @@ static nvsm_status stream_prep(nvsm_context *ctx, const nvsm_params *p, int32_t 
     if (p->noise_bias == 2)
         return fail(ctx, NVSM_ERR_NOT_IMPLEMENTED, "the streaming calls do not carry the photon-noise terms");
     if ((s = check_shape(p, H, W, G, &msg)) != NVSM_OK) return fail(ctx, s, msg);
-    if ((s = get_plan(ctx, p, dp)) != NVSM_OK) return s;
+    if ((s = get_plan(ctx, p, STREAM_SLOTS, dp)) != NVSM_OK) return s;
     BurstIn bi;
     bi.F = G; bi.H = H; bi.W = W; bi.pitch = W;
     int64_t rec;
@@ -978,7 +1131,7 @@ nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void 
     b.n_items = dp->h.n_items; b.slots = dp->h.slots; b.items = dp->items; b.group_xy = dp->group_xy;
     b.slot_v = dp->slot; b.out_idx = dp->out_idx;
     b.bispec = v.bis; b.s_count = z.S;
-    b.form = choice_of(ctx, p).second; b.queue = ctx->queue;
+    b.form = choice_of(ctx, p).second; b.queue = queue_of(gw, z);
     b.acc.sum = v.acc_s; b.acc.comp = v.acc_c; b.acc.mode = mode; b.acc.first = first;
     b.acc.n_items = dp->h.n_items; b.acc.inv_total = inv_total;
     {

@@ -14,6 +14,7 @@ namespace nvsm {
 constexpr int BS_LANES = 64;
 constexpr int BS_MAX_SLOTS = 32;     // largest slot count per wave
 constexpr int BS_WAVES = 4;            // waves per workgroup
+constexpr int BS_ROWS = BS_LANES / 16; // rows of 16 lanes (DPP broadcast rows) per wave
 // Staged region extent (pitch x height) per frame, in whole 128s: larger
 // for more slots per wave, whose items span more v.  With 16 slots, 1024
 // (two 16-byte loads per lane and frame) holds the full items of every
@@ -26,6 +27,8 @@ constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
 // LSQ_ROUND; accumulators live in LDS for the inner entries (|w| <= R) and
 // a ring for the rest, LSQ_ACC entries in all.
 constexpr int LSQ_ROUND = 64;
+// Waves of the phase-solve workgroup (one w each per unit).
+constexpr int SOLVE_WAVES = 8;
 constexpr int LSQ_ACC = 3968;
 
 struct Tiling {
@@ -52,6 +55,14 @@ struct HostPlan {
     // while the sample's shell is solved, and the slot of every w.
     std::vector<uint32_t> phase_slot_code;
     std::vector<int32_t> w_slot;
+    // Phase-solve units: each shell after the first (the seeds) cut into
+    // units of at most SOLVE_WAVES w, one w per wave.  solve_units[(u *
+    // SOLVE_WAVES + j) * 4 + 0..3] = (w of wave j or -1, its first S index,
+    // its sample count + 65536 if u is the last unit of its shell, the LDS
+    // slot of its phasor).  The units of one shell are independent; a
+    // shell's results are read only by later shells.
+    int n_units = 0;
+    std::vector<int32_t> solve_units;
     // Least-squares rounds: before round r (segments [r, r + 1) * LSQ_ROUND)
     // the entries [n_inner, lsq_fin[r]) are targets of no later segment;
     // lsq_fin[0] = n_inner, lsq_fin[rounds] = |W|.  lsq_span is the most
@@ -65,7 +76,7 @@ struct HostPlan {
     // Bispectrum work items.  items[g*12 + 0..11] = w group, region x0,
     // region y0, region width, region height, region points (width x
     // height), region row pitch in LDS, 0, then the slot count ns of each of
-    // the BS_WAVES waves (the same for all, a multiple of 4, <= K).  The
+    // the BS_WAVES waves (a multiple of 4, 4 <= ns <= K).  The
     // region holds I(w - v) for every lane's w and every slot's v of the
     // item.
     int slots = 0;                      // v slots per wave (K)
@@ -76,9 +87,10 @@ struct HostPlan {
     int n_groups = 0;
     std::vector<int32_t> group_xy;
     int max_region = 0;                 // largest region points of any item
-    // slot[((g*BS_WAVES + wave)*K + k)*2 + 0] = vy * region_pitch + vx
-    // (offset of v in the staged region), [..+1] = offset of I(v) in a
-    // frame's stored spectrum record (rows -16 .. N/2-1).
+    // slot[(((g*BS_WAVES + wave)*BS_ROWS + row)*K + k)*2 + 0] = vy *
+    // region_pitch + vx (offset of the row's v in the staged region), [..+1]
+    // = offset of I(v) in a frame's stored spectrum record (rows -16 ..
+    // N/2-1).  Each row of 16 lanes runs its own v.
     std::vector<int32_t> slot_v;
     // out_idx[((g*BS_WAVES + wave)*K + k)*64 + lane] = S index or -1
     std::vector<int32_t> out_idx;

@@ -1,9 +1,9 @@
 """Serving loop: bursts from several detector channels arrive frame by frame
 and are reconstructed as they complete (continuous batching).
 
-Each channel has its own HIP stream, a device staging buffer for one group
-of frames and a workspace (group scratch and final buffers).  Per-burst device memory comes from a pool
-of slots sized to an HBM budget; a burst is admitted when its first frame
+Each channel has its own HIP stream, two device staging buffers of one group
+of frames each and a workspace (group scratch and final buffers).  Per-burst
+device memory comes from a pool of slots sized to an HBM budget; a burst is admitted when its first frame
 arrives and a slot of its channel's shape is free, otherwise its frames
 wait on the host until one frees (admission by HBM footprint).  Work of
 different channels overlaps on the device through their streams.
@@ -15,12 +15,16 @@ any mix; adaptive groups change only the fold points, within the parity
 tolerances.
 
 * ``stream`` -- the burst's running sums live in its slot
-  (``nvsm_stream_*``): arriving frames are ingested and added in groups, so
-  only the last group, the phase solve and the synthesis remain after the
-  last frame.  A group is launched once ``group`` frames wait and the
-  channel's previous group has finished on the device, or once
-  ``max_group`` frames wait: an idle GPU gets small groups (low latency), a
-  busy one larger groups (fewer passes over the running sums).
+  (``nvsm_stream_*``): arriving frames are copied to the device at once (into
+  the channel's staging buffer being filled; the other holds the group in
+  flight) and are ingested and added in groups, so only the last group, the
+  phase solve and the synthesis remain after the last frame.  A group is launched once ``group`` frames wait and the GPU
+  has finished everything launched so far (every channel's last launch),
+  once ``max_group`` frames wait, or with the burst's last frame: an idle
+  GPU gets small groups (low latency), a busy one larger groups (fewer
+  passes over the running sums; a burst whose frames have all arrived
+  while the GPU was busy goes in one group, which reads and writes no
+  running sums at all).
 * ``plain`` -- frames are kept on the device and the burst is reconstructed
   with one ``nvsm_reconstruct`` after its last frame.
 
@@ -67,6 +71,7 @@ class _Burst:
         self.pending = []          # host frames not yet on the device
         self.count = 0             # frames handed to the device
         self.total = 0             # frame count once the last frame arrived
+        self.staged = 0            # frames in the channel's filling staging buffer
         self.slot = None
         self.t_last = None
         self.event = None
@@ -95,14 +100,15 @@ class Server:
             if policy == "stream":
                 slot_b, gws_b = _lib.nvsm_stream_plan(c.params, c.H, c.W, self.max_group)
                 gws = torch.empty(gws_b, dtype=torch.uint8, device=self.dev)
-                stage = torch.empty((self.max_group, c.H, c.W), dtype=torch.int16, device=self.dev)
+                stage = [torch.empty((self.max_group, c.H, c.W), dtype=torch.int16, device=self.dev)
+                         for _ in range(2)]
             else:
                 info = _lib.nvsm_plan(c.params, c.H, c.W, max_frames)
                 slot_b = max_frames * c.H * c.W * 2
                 gws = torch.empty(info.ws_reconstruct, dtype=torch.uint8, device=self.dev)
                 stage = None
-            self.ch[c.name] = dict(spec=c, stream=st, gws=gws, stage=stage, slot_bytes=slot_b, free=[],
-                                   active={}, order=collections.deque(), add_ev=None)
+            self.ch[c.name] = dict(spec=c, stream=st, gws=gws, stage=stage, fill=0, slot_bytes=slot_b, free=[],
+                                   active={}, order=collections.deque(), last_ev=None)
             need.append((c.name, slot_b))
         # slots: one per channel first, then round robin while the budget lasts
         used = 0
@@ -133,7 +139,7 @@ class Server:
             c["order"].append(b)
         b.pending.append(frame)
         if last:
-            b.total = b.count + len(b.pending)
+            b.total = b.count + b.staged + len(b.pending)
             b.t_last = time.perf_counter()
         self._advance(c)
 
@@ -143,6 +149,10 @@ class Server:
             c["order"].popleft()
         return b.slot is not None
 
+    def _gpu_idle(self):
+        """Every channel's last launch has finished on the device."""
+        return all(c["last_ev"] is None or c["last_ev"].query() for c in self.ch.values())
+
     def _advance(self, c):
         torch = self.torch
         spec = c["spec"]
@@ -151,28 +161,33 @@ class Server:
                 break                                  # bursts are admitted in arrival order
             with torch.cuda.stream(c["stream"]):
                 if self.policy == "stream":
-                    while b.pending:
-                        idle = c["add_ev"] is None or c["add_ev"].query()
-                        if not (b.total or len(b.pending) >= self.max_group or
-                                (len(b.pending) >= self.group and idle)):
+                    while True:
+                        # arrived frames go to the filling buffer at once (its
+                        # previous group's ingest precedes the copies on this
+                        # stream)
+                        stage = c["stage"][c["fill"]]
+                        while b.pending and b.staged < self.max_group:
+                            stage[b.staged].copy_(torch.from_numpy(b.pending.pop(0).view(np.int16)),
+                                                  non_blocking=True)
+                            b.staged += 1
+                        g = b.staged
+                        last = bool(b.total) and not b.pending
+                        if not (g and (last or g >= self.max_group or (g >= self.group and self._gpu_idle()))):
                             break
-                        g = min(self.max_group, len(b.pending))
-                        for i in range(g):
-                            c["stage"][i].copy_(torch.from_numpy(b.pending[i].view(np.int16)), non_blocking=True)
-                        del b.pending[:g]
                         b.count += g
-                        final = b.total if (b.total and not b.pending) else 0
-                        _lib.nvsm_stream_add(self.ctx, spec.params, c["stage"][:g], b.count - g, final, b.slot,
-                                             c["gws"])
-                        c["add_ev"] = torch.cuda.Event()
-                        c["add_ev"].record(c["stream"])
+                        b.staged = 0
+                        final = b.total if last else 0
+                        _lib.nvsm_stream_add(self.ctx, spec.params, stage[:g], b.count - g, final, b.slot, c["gws"])
+                        c["fill"] ^= 1
                         b.groups += 1
                         if final:
                             b.image = torch.empty((spec.H, spec.W), dtype=torch.float32, device=self.dev)
                             _lib.nvsm_stream_finish(self.ctx, spec.params, spec.H, spec.W, spec.stf, b.image,
                                                     c["gws"])
-                        # the staging buffer is reused by the next group:
-                        # the copies above are ordered on this stream
+                        c["last_ev"] = torch.cuda.Event()
+                        c["last_ev"].record(c["stream"])
+                        if final:
+                            break
                 else:
                     frames = b.slot.view(torch.int16)
                     for fr in b.pending:
@@ -184,6 +199,8 @@ class Server:
                         b.image = torch.empty((spec.H, spec.W), dtype=torch.float32, device=self.dev)
                         fv = frames[: b.total * spec.H * spec.W].view(b.total, spec.H, spec.W)
                         _lib.nvsm_reconstruct(self.ctx, spec.params, fv, spec.stf, b.image, c["gws"])
+                        c["last_ev"] = torch.cuda.Event()
+                        c["last_ev"].record(c["stream"])
                 if b.total and b.count == b.total and b.event is None:
                     b.event = torch.cuda.Event()
                     b.event.record(c["stream"])
@@ -224,20 +241,25 @@ class Server:
             self.ctx = None
 
 
-def schedule(channels, seconds, fps=10.0, fmin=70, fmax=130, seed=0):
-    """Frame arrivals: per channel, bursts back to back, F uniform in
-    [fmin, fmax], frames every 1/fps s.  Returns sorted (t, channel, burst,
-    frame index, F) tuples."""
+def schedule(channels, seconds, fps=10.0, fmin=70, fmax=130, gap_s=2.0, seed=0):
+    """Frame arrivals.  Per channel (a detector records one burst at a time)
+    bursts arrive as a Poisson stream: the idle time before each burst,
+    the first included, is exponential with mean gap_s (0: back to back);
+    F is uniform in [fmin, fmax] and the frames come every 1/fps s.  The
+    channels are independent, so their bursts cluster at random.  Returns
+    sorted (t, channel, burst, frame index, F) tuples."""
     rng = np.random.default_rng(seed)
     ev = []
     for ci, name in enumerate(channels):
-        t = 0.0
+        t = float(rng.exponential(gap_s)) if gap_s > 0 else 0.0
         k = 0
         while t < seconds:
             F = int(rng.integers(fmin, fmax + 1))
             for f in range(F):
                 ev.append((t, ci, name, k, f, F))
                 t += 1.0 / fps
+            if gap_s > 0:
+                t += float(rng.exponential(gap_s))
             k += 1
     ev.sort()
     return [(t, name, k, f, F) for t, _, name, k, f, F in ev]

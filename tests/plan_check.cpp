@@ -39,16 +39,25 @@ static long check_bispectrum(const HostPlan &pl, int N, int K) {
         if (ry0 < -SPEC_NEG_ROWS_HOST) ++bad;
         for (int wave = 0; wave < BS_WAVES; ++wave) {
             const int ns = it[8 + wave];
-            if (ns % 4 || ns > K || ns < 0) ++bad;
+            if (ns % 4 || ns > K || ns < 4) ++bad;
             for (int k = 0; k < K; ++k) {
+                // each row of 16 lanes has its own slot table
+                int rvx[BS_ROWS], rvy[BS_ROWS], rroff[BS_ROWS];
+                bool ok = true;
+                for (int row = 0; row < BS_ROWS; ++row) {
+                    const size_t sidx = (((size_t)(g * BS_WAVES + wave) * BS_ROWS + row) * K + k);
+                    const int roff = pl.slot_v[sidx * 2], so = pl.slot_v[sidx * 2 + 1];
+                    if (so < 0 || so >= (HALF + SPEC_NEG_ROWS_HOST) * N) { ++bad; ok = false; continue; }
+                    rvy[row] = so / N - SPEC_NEG_ROWS_HOST;
+                    rvx[row] = so % N;
+                    if (rvx[row] > HALF) rvx[row] -= N;
+                    rroff[row] = roff;
+                    if (roff != rvy[row] * pitch + rvx[row]) ++bad;
+                }
+                if (!ok) continue;
                 const size_t sidx = ((size_t)(g * BS_WAVES + wave) * K + k);
-                const int roff = pl.slot_v[sidx * 2], so = pl.slot_v[sidx * 2 + 1];
-                if (so < 0 || so >= (HALF + SPEC_NEG_ROWS_HOST) * N) { ++bad; continue; }
-                const int vy = so / N - SPEC_NEG_ROWS_HOST;
-                int vx = so % N;
-                if (vx > HALF) vx -= N;
-                if (roff != vy * pitch + vx) ++bad;
                 for (int lane = 0; lane < BS_LANES; ++lane) {
+                    const int row = lane / 16, vx = rvx[row], vy = rvy[row], roff = rroff[row];
                     const int wx = pl.group_xy[((size_t)gi * BS_LANES + lane) * 2];
                     const int wy = pl.group_xy[((size_t)gi * BS_LANES + lane) * 2 + 1];
                     if (wy < 0 || wy >= HALF) ++bad;
@@ -93,6 +102,45 @@ static long check_lsq_rounds(const HostPlan &pl) {
     return bad;
 }
 
+// Phase-solve units: every w of shells 1.. exactly once, in storage order,
+// with its S range; at most SOLVE_WAVES w per unit, all of one shell; the
+// barrier flag set exactly on each shell's last unit; and every sample's
+// sides come from strictly earlier shells (so the units of a shell are
+// independent).
+static long check_solve_units(const HostPlan &pl) {
+    long bad = 0;
+    const int nW = (int)pl.W.size() / 2, nshell = (int)pl.shell_wb.size() - 1;
+    if ((int)pl.solve_units.size() != pl.n_units * SOLVE_WAVES * 4) return 1;
+    std::vector<int> shell_of(nW);
+    for (int sh = 0; sh < nshell; ++sh)
+        for (int w = pl.shell_wb[sh]; w < pl.shell_wb[sh + 1]; ++w) shell_of[w] = sh;
+    int expect = pl.shell_wb[1];
+    for (int u = 0; u < pl.n_units; ++u) {
+        const int32_t *t = &pl.solve_units[(size_t)u * SOLVE_WAVES * 4];
+        const int sh = shell_of[t[0]];
+        const int flag = t[2] >> 16;
+        for (int j = 0; j < SOLVE_WAVES; ++j) {
+            const int w = t[4 * j], o = t[4 * j + 1], c = t[4 * j + 2] & 0xffff, last = t[4 * j + 2] >> 16;
+            if (last != flag) ++bad;
+            if (w < 0) {
+                if (o != 0 || c != 0) ++bad;
+                continue;
+            }
+            if (w != expect || shell_of[w] != sh) ++bad;
+            ++expect;
+            if (o != pl.woff[w] || c != pl.woff[w + 1] - pl.woff[w] || t[4 * j + 3] != pl.w_slot[w]) ++bad;
+            for (int32_t k = o; k < o + c; ++k) {
+                const int ia = (int)((pl.phase_code[k] >> 16) & 0x7fffu), ib = (int)(pl.phase_code[k] & 0x7fffu);
+                if (shell_of[ia] >= sh || shell_of[ib] >= sh) ++bad;
+            }
+        }
+        const bool end = expect == pl.shell_wb[sh + 1];
+        if ((flag != 0) != end) ++bad;
+    }
+    if (expect != nW) ++bad;
+    return bad;
+}
+
 int main(int argc, char **argv) {
     for (int i = 1; i < argc; ++i) {
         int N = 0, uc = 0, R = 0, K = 0;
@@ -106,9 +154,10 @@ int main(int argc, char **argv) {
             std::printf("N=%d uc=%d R=%d K=%d: plan failed (%s) bad=1\n", N, uc, R, K, err.c_str());
             continue;
         }
-        const long b1 = check_bispectrum(pl, N, K), b2 = check_lsq_rounds(pl);
-        std::printf("N=%d uc=%d R=%d K=%d items=%d |S|=%lld bispectrum bad=%ld rounds bad=%ld bad=%ld\n", N, uc, R,
-                    K, pl.n_items, (long long)pl.s_count, b1, b2, b1 + b2);
+        const long b1 = check_bispectrum(pl, N, K), b2 = check_lsq_rounds(pl), b3 = check_solve_units(pl);
+        std::printf("N=%d uc=%d R=%d K=%d items=%d units=%d |S|=%lld bispectrum bad=%ld rounds bad=%ld "
+                    "units bad=%ld bad=%ld\n", N, uc, R, K, pl.n_items, pl.n_units, (long long)pl.s_count, b1, b2, b3,
+                    b1 + b2 + b3);
     }
     return 0;
 }

@@ -38,7 +38,7 @@ def world(torch_cuda):
         for k in range(3):
             c2 = dataclasses.replace(cfg, index=70 + 10 * ci + k, F=31)
             frames[(name, k)] = synth.make_burst(c2)
-    events = serve.schedule(list(CHANNELS), seconds=4.0, fps=10.0, fmin=12, fmax=31, seed=5)
+    events = serve.schedule(list(CHANNELS), seconds=4.0, fps=10.0, fmin=12, fmax=31, gap_s=0.5, seed=5)
     events = [e for e in events if e[2] < 3]           # at most 3 bursts per channel
     return dict(p=p, specs=specs, frames=frames, events=events)
 

@@ -144,3 +144,70 @@ def test_stream_errors(torch_cuda, setup):
     assert e.value.status == -3
     with pytest.raises(nv.NvsmError):               # total must be frames_before + G
         nv.nvsm_stream_add(setup["ctx"], p, setup["d"][:5], 0, 3, state, ws)
+
+
+def test_stream_launch_choice_may_change_mid_burst(torch_cuda, setup):
+    """The streaming calls keep 16 slots per wave whatever the launch choice
+    (their running sums are stored in that kernel's lane order): switching
+    to 24 slots and the persistent form between two groups of a burst gives
+    the same bits as keeping the default."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    p, d = setup["p"], setup["d"]
+    groups = [11, 19]
+    ref_img, ref_bis = _stream(nv, torch, setup, groups)
+    ref_bis = ref_bis.clone()
+    ctx = nv.nvsm_create(0)
+    try:
+        state_b, ws_b = nv.nvsm_stream_plan(p, H, W, max(groups))
+        state = torch.empty(state_b, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
+        nv.nvsm_stream_add(ctx, p, d[:11], 0, 0, state, ws)
+        nv.nvsm_set_launch(ctx, p, 24, 1)
+        nv.nvsm_stream_add(ctx, p, d[11:], 11, F, state, ws)
+        img = torch.full((H, W), float("nan"), device="cuda")
+        nv.nvsm_stream_finish(ctx, p, H, W, setup["stf"], img, ws)
+        torch.cuda.synchronize()
+        info = setup["info"]
+        bis = ws[: info.patches * info.s_count * 8].view(torch.float32).view(info.patches, info.s_count, 2)
+        same_b, same_i = torch.equal(bis, ref_bis), torch.equal(img, ref_img)
+        say(f"[stream] launch choice changed mid-burst: bispectrum identical={same_b}, image identical={same_i}")
+        assert same_b and same_i
+    finally:
+        nv.nvsm_destroy(ctx)
+
+
+def test_persistent_form_on_two_streams(torch_cuda, setup):
+    """The persistent bispectrum form on two streams at once, one context,
+    two workspaces: each call's work-queue counters live in its own
+    workspace, so both equal the per-item form's result bit for bit."""
+    import paper_1701_00581_amd as nv
+    torch = torch_cuda
+    p, d, info = setup["p"], setup["d"], setup["info"]
+    ctx = nv.nvsm_create(0)
+    try:
+        nv.nvsm_set_launch(ctx, p, 16, 1)
+        outs = []
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        bufs = []
+        for _ in streams:
+            bufs.append(dict(power=torch.empty((info.patches, 128, 128), device="cuda"),
+                             mean=torch.empty((info.patches, 2, 2), device="cuda"),
+                             mu=torch.empty(info.patches, device="cuda"),
+                             bis=torch.full((info.patches, info.s_count, 2), float("nan"), device="cuda"),
+                             ws=torch.empty(info.ws_accumulate, dtype=torch.uint8, device="cuda")))
+        torch.cuda.synchronize()
+        for rep in range(3):
+            for st, b in zip(streams, bufs):
+                with torch.cuda.stream(st):
+                    nv.nvsm_accumulate(ctx, p, d, b["power"], b["mean"], b["mu"], b["bis"], b["ws"],
+                                       stream=st)
+            torch.cuda.synchronize()
+            for i, b in enumerate(bufs):
+                same = torch.equal(b["bis"], setup["ref"]["bis"])
+                say(f"[queue] repeat {rep} stream {i}: identical to the per-item form={same}")
+                assert same
+                b["bis"].fill_(float("nan"))
+            torch.cuda.synchronize()
+    finally:
+        nv.nvsm_destroy(ctx)

@@ -184,3 +184,18 @@ def test_workspace_sizes_scale_with_the_burst():
     # spectra (P F N/2 N complex64) dominate the accumulation workspace
     assert a.ws_accumulate >= 1287 * 100 * 64 * 128 * 8
     assert a.ws_reconstruct >= a.ws_accumulate + 1287 * a.s_count * 8
+
+
+def test_tune_radius_plan_is_the_crop_workspace_at_r_max():
+    """The tuner's workspace is that of nvsm_reconstruct on the burst's
+    central crop of at most 512 x 512 px at r_max (host call)."""
+    import paper_1701_00581_amd as nv
+    p = nv.default_params(128, v_radius=8)
+    big = nv.nvsm_tune_radius_plan(p, 2160, 2560, 100, 12)
+    q = nv.default_params(128, v_radius=12)
+    assert big == nv.nvsm_plan(q, 512, 512, 100).ws_reconstruct
+    small = nv.nvsm_tune_radius_plan(p, 300, 400, 30, 10)
+    q.v_radius = 10
+    assert small == nv.nvsm_plan(q, 300, 400, 30).ws_reconstruct
+    with pytest.raises(nv.NvsmError):
+        nv.nvsm_tune_radius_plan(p, 2160, 2560, 100, 64)     # r_max beyond the allowed radii
