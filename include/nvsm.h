@@ -207,6 +207,25 @@ nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p,
                              const double *stf, float *out,
                              void *workspace, size_t workspace_bytes, void *stream);
 
+/* nvsm_reconstruct for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same path and the same result bit for bit, with the
+ * workspace taken from a fixed array in the library's device data instead of
+ * a caller buffer.  The array holds 256 MiB on each GPU the library runs on
+ * (found once per device by nvsm_create, kept until the process ends): a
+ * burst whose nvsm_plan_info.ws_reconstruct exceeds that gives
+ * NVSM_ERR_WORKSPACE and launches nothing.  The parameter set's tables must
+ * exist first (nvsm_prepare, or an earlier compute call with p), else
+ * NVSM_ERR_INVALID_ARG; the call then allocates nothing and records no
+ * stage-timing events.  Every call on one GPU shares that GPU's array (it
+ * keeps the last call's intermediates; nothing in it needs clearing between
+ * calls): calls that overlap on one GPU, on different streams or from
+ * different contexts, race and give wrong results.  Order them. */
+nvsm_status nvsm_reconstruct_noalloc(nvsm_context *ctx, const nvsm_params *p,
+                                     const void *frames, nvsm_dtype dtype, int32_t F,
+                                     int32_t H, int32_t W, int64_t row_pitch,
+                                     const double *stf, float *out, void *stream);
+
 /* One burst of a batch.  frames: device [F][H][row_pitch] pixels of the
  * batch's dtype; stf: device double [N][N] (DFT order) for this burst's
  * seeing; out: device float [H][W].  All caller-owned. */

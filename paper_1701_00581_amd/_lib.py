@@ -27,6 +27,7 @@ EXPORTS = [
     "nvsm_create", "nvsm_destroy", "nvsm_status_string", "nvsm_last_error",
     "nvsm_default_params", "nvsm_plan", "nvsm_w_index", "nvsm_bispectrum_index",
     "nvsm_prepare", "nvsm_accumulate", "nvsm_solve", "nvsm_synthesize", "nvsm_reconstruct",
+    "nvsm_reconstruct_noalloc",
     "nvsm_profile_enable", "nvsm_profile_read", "nvsm_batch_plan", "nvsm_reconstruct_batch",
     "nvsm_autotune", "nvsm_set_launch", "nvsm_tune_radius_plan", "nvsm_tune_radius", "nvsm_stream_plan", "nvsm_stream_add", "nvsm_stream_finish",
     "nvsm_model_stf_plan", "nvsm_model_stf", "nvsm_seeing_default_params", "nvsm_seeing_plan", "nvsm_seeing",
@@ -104,6 +105,7 @@ def lib():
         L.nvsm_synthesize.argtypes = [c_p, P, c_i32, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]
         L.nvsm_reconstruct.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64,
                                        c_p, c_p, c_p, c_sz, c_p]
+        L.nvsm_reconstruct_noalloc.argtypes = [c_p, P, c_p, ctypes.c_int, c_i32, c_i32, c_i32, c_i64, c_p, c_p, c_p]
         L.nvsm_batch_plan.argtypes = [P, ctypes.POINTER(Burst), c_i32, ctypes.POINTER(c_sz),
                                       ctypes.POINTER(c_sz)]
         L.nvsm_reconstruct_batch.argtypes = [c_p, P, ctypes.c_int, ctypes.POINTER(Burst), c_i32, c_p, c_sz, c_p]
@@ -280,6 +282,14 @@ def nvsm_reconstruct(ctx, params, frames, stf, out, workspace, stream=None, row_
                                 _ptr(stf), _ptr(out), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream))
     _check(st, "nvsm_reconstruct", ctx)
+
+
+def nvsm_reconstruct_noalloc(ctx, params, frames, stf, out, stream=None, row_pitch=None):
+    F, H, W = frames.shape
+    pitch = _row_pitch(frames, row_pitch)
+    st = lib().nvsm_reconstruct_noalloc(ctx, ctypes.byref(params), _ptr(frames), frames_dtype(frames), F, H, W,
+                                        pitch, _ptr(stf), _ptr(out), _stream(stream))
+    _check(st, "nvsm_reconstruct_noalloc", ctx)
 
 
 def _bursts(bursts):

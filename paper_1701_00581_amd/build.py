@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnvsm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["nvsm.cpp", "plan.cpp", "k_ingest.hip", "k_bispec.hip", "k_solve.hip", "k_synth.hip", "k_stf.hip"]
+SOURCES = ["nvsm.cpp", "plan.cpp", "k_ingest.hip", "k_bispec.hip", "k_solve.hip", "k_synth.hip", "k_stf.hip", "scratch.hip"]
 
 # Packed FP32 instructions are disabled (they are not used by hand either).
 HIPCC_FLAGS = [

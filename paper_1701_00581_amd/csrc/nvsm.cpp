@@ -17,6 +17,7 @@
 
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "scratch.hpp"
 
 using namespace nvsm;
 
@@ -337,6 +338,12 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, DevicePlan **out) 
     return get_plan(ctx, p, choice_of(ctx, p).first, out);
 }
 
+// The plan of p's launch choice if it already exists (no allocation).
+DevicePlan *find_plan(const nvsm_context *ctx, const nvsm_params *p) {
+    auto f = ctx->plans.find(std::make_tuple(p->patch, p->u_cut, p->v_radius, choice_of(ctx, p).first));
+    return f == ctx->plans.end() ? nullptr : f->second.get();
+}
+
 // Records an event pair around one stage when profiling is on.
 struct StageTimer {
     nvsm_context *ctx;
@@ -518,6 +525,8 @@ nvsm_status nvsm_create(int hip_device, nvsm_context **out) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess) return NVSM_ERR_HIP;
     if (hip_device < 0 || hip_device >= n) return NVSM_ERR_INVALID_ARG;
+    // the no-allocation entry point's scratch array on this device
+    if (scratch_setup(hip_device) != hipSuccess) return NVSM_ERR_HIP;
     nvsm_context *c = new (std::nothrow) nvsm_context();
     if (!c) return NVSM_ERR_OOM;
     c->device = hip_device;
@@ -706,6 +715,42 @@ nvsm_status nvsm_reconstruct(nvsm_context *ctx, const nvsm_params *p, const void
     if (s != NVSM_OK) return s;
     if (!workspace || workspace_bytes < ws_rec(z)) return fail(ctx, NVSM_ERR_WORKSPACE, "workspace too small for reconstruct");
     hipError_t e = run_reconstruct(ctx, dp, p, bt, z, dtype, (char *)workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reconstruct launch");
+    return NVSM_OK;
+}
+
+nvsm_status nvsm_reconstruct_noalloc(nvsm_context *ctx, const nvsm_params *p, const void *frames, nvsm_dtype dtype,
+                                     int32_t F, int32_t H, int32_t W, int64_t row_pitch, const double *stf,
+                                     float *out, void *stream) {
+    if (!ctx) return NVSM_ERR_INVALID_ARG;
+    if (!frames || !stf || !out) return fail(ctx, NVSM_ERR_INVALID_ARG, "null buffer");
+    if (dtype != NVSM_U16 && dtype != NVSM_F32) return fail(ctx, NVSM_ERR_INVALID_ARG, "bad dtype");
+    std::string msg;
+    nvsm_status s = check_params(p, &msg);
+    if (s != NVSM_OK) return fail(ctx, s, msg);
+    BurstIn bi;
+    bi.frames = frames; bi.F = F; bi.H = H; bi.W = W; bi.pitch = row_pitch; bi.stf = stf; bi.out = out;
+    if ((s = check_burst(p, bi, &msg)) != NVSM_OK) return fail(ctx, s, msg);
+    DevicePlan *dp = find_plan(ctx, p);
+    if (!dp)
+        return fail(ctx, NVSM_ERR_INVALID_ARG,
+                    "no tables for these parameters: call nvsm_prepare (or any compute call) with them first");
+    void *scr = scratch_address(ctx->device);
+    if (!scr) return fail(ctx, NVSM_ERR_HIP, "scratch array not set up on this device");
+    BurstTable bt;
+    int64_t rec;
+    Sizes z;
+    make_table(p, &bi, 1, &bt, &rec);
+    sizes_for(p->patch, bt, rec, (int64_t)(dp->h.W.size() / 2), dp->h.s_count, &z, p->noise_bias == 2);
+    if (ws_rec(z) > SCRATCH_BYTES)
+        return fail(ctx, NVSM_ERR_WORKSPACE,
+                    "burst needs " + std::to_string(ws_rec(z)) + " bytes of workspace, more than the " +
+                        std::to_string(SCRATCH_BYTES) + "-byte scratch array: use nvsm_reconstruct");
+    // no stage events here (creating one may allocate)
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    hipError_t e = run_reconstruct(ctx, dp, p, bt, z, dtype, (char *)scr, (hipStream_t)stream);
+    ctx->prof = prof;
     if (e != hipSuccess) return hip_fail(ctx, e, "reconstruct launch");
     return NVSM_OK;
 }
