@@ -3,15 +3,13 @@
 //
 // Work decomposition (see plan.cpp): a workgroup owns one patch and one
 // work item = a group of up to 64 w close in angle and radius (one w per
-// lane) times 4 x NS values of v (one v per wave slot; each row of 16 lanes,
-// a quarter of the group by angle, has its own v list).  Per frame, and for
-// the next frame while this one is computed:
+// lane) times 4 x NS values of v (one v per wave slot, the same for all 64
+// lanes).  Per frame, and for the next frame while this one is computed:
 //   * the region of I holding every w - v of the item goes to LDS by direct
 //     16-byte global-to-LDS loads (no registers involved), double buffered;
-//   * each lane loads its own I(w), and lane l the slot value I(v) of its
-//     row's slot l mod 16, into registers; a slot's value reaches every lane
-//     of the row through a DPP row broadcast folded into the multiplies that
-//     use it.
+//   * each lane loads its own I(w), and lane l the slot value I(v) of slot
+//     l mod 16, into registers; a slot's value reaches every lane through a
+//     DPP row broadcast folded into the multiplies that use it.
 // Each slot then costs one 64-bit LDS gather and 8 FP32 FMA/MUL per lane.
 // LDS bandwidth is the other limit of this loop (a 64-bit read returns 16
 // lanes per clock), so I(v) and I(w) stay out of LDS and the lanes of a
@@ -125,8 +123,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     const int lane = tid & 63;
     const int wx = gxy[2 * lane], wy = gxy[2 * lane + 1];
     const int lane_base = (wy - ry0) * pitch + (wx - rx0);
-    // this lane's row of 16 runs its own v (slot table of the row)
-    const int *sl = slot + ((size_t)(g * BS_WAVES + wave) * BS_ROWS + (lane >> 4)) * K * 2;
+    const int *sl = slot + (size_t)(g * BS_WAVES + wave) * K * 2;
 
     constexpr int NQ = (NS + 15) / 16;           // rows of 16 slot values
     int addr[NS];     // LDS byte offset of I(w - v) in the region, per slot
@@ -264,9 +261,6 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         // table gives v's record index; w - v lies within the record's rows)
         // (w's row and column come from its record index, which stays live)
         const float2 *Cp = acc.noise_c + (size_t)patch * FS;
-        // the row's slot table, formed again from the lane index (not kept
-        // through the frame loop)
-        const int *slr = slot + ((size_t)(g * BS_WAVES + wave) * BS_ROWS + (lane_e >> 4)) * K * 2;
         const float t2 = 2.0f * acc.noise_t[(size_t)patch * 2 + 1];
         const int wi = wo / (int)sizeof(float2);
         // the means first, so the block-sum registers are free for the loads
@@ -275,7 +269,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         const float2 c_w = Cp[wi];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            const int vo = slr[2 * k + 1];
+            const int vo = sl[2 * k + 1];
             const float2 c_v = Cp[vo];
             const float2 c_d = Cp[(wi / N - vo / N + SPEC_NEG_ROWS) * N + ((wi - vo) & (N - 1))];
             const int o = oi[k * 64];

@@ -221,12 +221,10 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     // close together in angle and radius: for |w| well above R, S(w) is the
     // part of the |v| <= R disk on w's side of a line through the origin
     // normal to w, so w of similar direction share most of their v and the
-    // union of their sets (the v slots a row of lanes runs) is little larger
+    // union of their sets (the v slots the wave runs) is little larger
     // than each set.  Groups: radial bands (8 wide up to 24, then about 10
-    // wide), each sorted by angle and cut into equal groups of <= 64; each
-    // row of 16 lanes (the rows of the DPP broadcast) takes about a quarter
-    // of its group by angle and runs the union of its own 16 sets.  Wider
-    // bands give narrower angles (fewer idle lanes) but larger staged
+    // wide), each sorted by angle and cut into equal groups of <= 64.
+    // Wider bands give narrower angles (fewer idle lanes) but larger staged
     // regions.
     std::vector<int> edges = {0};
     for (int e = 8; e <= 24; e += 8)
@@ -262,162 +260,110 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     pl->max_region = 0;
     for (int gi = 0; gi < pl->n_groups; ++gi) {
         const std::vector<int> &gset = groups[gi];
-        // Rows: each run of 16 lanes (a row of the DPP broadcast) holds a
-        // quarter of the group by angle and runs its own v: the union of S(w)
-        // over 16 w of close direction is nearer each S(w) than the union over
-        // all 64.
-        const int ng = (int)gset.size();
-        std::vector<int> rw[BS_ROWS];
-        std::vector<std::pair<int, int>> U[BS_ROWS];   // (vx, vy) per row, sorted by (vy, vx)
-        int bx0[BS_ROWS], bx1[BS_ROWS], by0[BS_ROWS], by1[BS_ROWS];
-        size_t nUmax = 0;
-        struct Item { int u0, m, rx0, ry0, rh; };
+        int gx0 = 1 << 20, gx1 = -(1 << 20), gy0 = 1 << 20, gy1 = -(1 << 20);
+        std::map<std::pair<int, int>, int> uni;  // (vy, vx) sorted union
+        for (int i : gset) {
+            const int wx = pl->W[2 * i], wy = pl->W[2 * i + 1];
+            gx0 = std::min(gx0, wx); gx1 = std::max(gx1, wx);
+            gy0 = std::min(gy0, wy); gy1 = std::max(gy1, wy);
+            for (size_t j = 0; j < Sw[i].size() / 2; ++j) uni[{Sw[i][2 * j + 1], Sw[i][2 * j]}] = 1;
+        }
+        std::vector<std::pair<int, int>> U;  // (vx, vy)
+        for (auto &u : uni) U.push_back({u.first.second, u.first.first});
+        if (U.empty()) continue;
+        // Items: full ones (BS_WAVES chunks of K slots), then one for the
+        // rest, whose waves all run ns slots (ns the smallest multiple of 4
+        // that holds a quarter of the rest); chunks balanced within an item.
+        // Items hold fewer v (in steps of 4 per wave) where the staged
+        // region of a full item would not fit the LDS capacity.
+        const int nU = (int)U.size();
+        struct Item { int u0, m, ns, rx0, ry0, rw, rh; };
         std::vector<Item> gitems;
-        int maxw = 0, maxh = 0;
-        auto dummy = [&](int r, int u0) -> std::pair<int, int> {
-            if (U[r].empty()) return {0, 0};
-            return u0 < (int)U[r].size() ? U[r][u0] : U[r].back();
-        };
-        // The rows' unions, and items: item i takes positions [i mcap,
-        // (i + 1) mcap) of every row's list.  A slot past a row's list runs
-        // the row's dummy v (its chunk's first v, or its list's last once the
-        // list is used up), which the staged region covers too.  Items hold
-        // fewer v (in steps of 4 per wave) where the region of a full item
-        // would not fit the LDS capacity.
-        auto make_items = [&]() {
-            nUmax = 0;
-            for (int r = 0; r < BS_ROWS; ++r) {
-                std::map<std::pair<int, int>, int> uni;  // (vy, vx)
-                bx0[r] = by0[r] = 1 << 20;
-                bx1[r] = by1[r] = -(1 << 20);
-                U[r].clear();
-                for (int i : rw[r]) {
-                    const int wx = pl->W[2 * i], wy = pl->W[2 * i + 1];
-                    bx0[r] = std::min(bx0[r], wx); bx1[r] = std::max(bx1[r], wx);
-                    by0[r] = std::min(by0[r], wy); by1[r] = std::max(by1[r], wy);
-                    for (size_t j = 0; j < Sw[i].size() / 2; ++j) uni[{Sw[i][2 * j + 1], Sw[i][2 * j]}] = 1;
+        int maxw = 0;
+        for (int mcap = BS_WAVES * K; mcap > 0; mcap -= 4 * BS_WAVES) {
+            gitems.clear();
+            maxw = 0;
+            int maxh = 0;
+            for (int u0 = 0; u0 < nU; u0 += mcap) {
+                const int m = std::min(nU - u0, mcap);
+                const int ns = std::min(K, 4 * (((m + BS_WAVES - 1) / BS_WAVES + 3) / 4));
+                int vxmin = 1 << 20, vxmax = -(1 << 20), vymin = 1 << 20, vymax = -(1 << 20);
+                for (int u = u0; u < u0 + m; ++u) {
+                    vxmin = std::min(vxmin, U[u].first); vxmax = std::max(vxmax, U[u].first);
+                    vymin = std::min(vymin, U[u].second); vymax = std::max(vymax, U[u].second);
                 }
-                for (auto &u : uni) U[r].push_back({u.first.second, u.first.first});
-                nUmax = std::max(nUmax, U[r].size());
+                // x0 even: region pairs (x, x + 1) never straddle column 0
+                const int rx0 = (gx0 - vxmax) & ~1, ry0 = gy0 - vymax;
+                const int rw = gx1 - vxmin - rx0 + 1, rh = gy1 - vymin - ry0 + 1;
+                gitems.push_back({u0, m, ns, rx0, ry0, rw, rh});
+                maxw = std::max(maxw, rw);
+                maxh = std::max(maxh, rh);
             }
-            for (int mcap = BS_WAVES * K; mcap > 0; mcap -= 4 * BS_WAVES) {
-                gitems.clear();
-                maxw = maxh = 0;
-                for (int u0 = 0; u0 < (int)nUmax; u0 += mcap) {
-                    int m = 0, x0 = 1 << 20, x1 = -(1 << 20), y0 = 1 << 20, y1 = -(1 << 20);
-                    for (int r = 0; r < BS_ROWS; ++r) {
-                        if (rw[r].empty()) continue;
-                        const int n = std::max(0, std::min((int)U[r].size() - u0, mcap));
-                        m = std::max(m, n);
-                        auto extend = [&](const std::pair<int, int> &v) {
-                            x0 = std::min(x0, bx0[r] - v.first); x1 = std::max(x1, bx1[r] - v.first);
-                            y0 = std::min(y0, by0[r] - v.second); y1 = std::max(y1, by1[r] - v.second);
-                        };
-                        for (int u = u0; u < u0 + n; ++u) extend(U[r][u]);
-                        extend(dummy(r, u0));
-                    }
-                    // x0 even: region pairs (x, x + 1) never straddle column 0
-                    x0 &= ~1;
-                    gitems.push_back({u0, m, x0, y0, y1 - y0 + 1});
-                    maxw = std::max(maxw, x1 - x0 + 1);
-                    maxh = std::max(maxh, y1 - y0 + 1);
-                }
-                if ((maxw + (maxw & 1)) * maxh <= bs_max_region(K)) break;
-            }
-        };
+            if ((maxw + (maxw & 1)) * maxh <= bs_max_region(K)) break;
+        }
         // One row pitch for all items of the group, even (the kernel moves
         // the region in pairs of columns).  A lane reads LDS at
-        // (wy - ry0) pitch + (wx - rx0) - (its row's slot offset), so within
-        // a row the bank of every gather follows key = (wx + pitch wy) mod 32
-        // up to a shift common to the row.  A 64-bit LDS read serves one row
-        // of 16 lanes per pass, so a row's lanes should hold distinct keys
-        // mod 16.
-        auto key_of = [&](int i, int pch) { return ((pl->W[2 * i] + pch * pl->W[2 * i + 1]) % 32 + 32) % 32; };
-        auto collisions = [&](int pch) {
+        // (wy - ry0) pitch + (wx - rx0) - (slot offset), so the bank of
+        // every gather follows key = (wx + pitch wy) mod 32 up to a shift
+        // common to the wave.  A 64-bit LDS read serves 16 lanes per pass (32
+        // on a 64-bank LDS): the pitch (one of the even values from the
+        // widest region up to 8 more, within the LDS capacity) is the one
+        // whose keys spread most evenly over the group
+        // (at most 4 w per key mod 16, then 2 per key), and lanes are then
+        // assigned so that each run of 16 lanes has distinct key mod 16 and,
+        // where the keys allow, each run of 32 distinct key.
+        int maxh = 0;
+        for (const Item &gt : gitems) maxh = std::max(maxh, gt.rh);
+        int pitch = maxw + (maxw & 1), best = 1 << 30;
+        for (int cand = maxw + (maxw & 1); cand < maxw + 9; cand += 2) {
+            if (cand * maxh > bs_max_region(K)) break;
+            int c16[16] = {}, c32[32] = {};
+            for (int i : gset) {
+                const int key = ((pl->W[2 * i] + cand * pl->W[2 * i + 1]) % 32 + 32) % 32;
+                ++c32[key];
+                ++c16[key & 15];
+            }
             int score = 0;
-            for (int r = 0; r < BS_ROWS; ++r) {
-                int c16[16] = {};
-                for (int i : rw[r]) ++c16[key_of(i, pch) & 15];
-                for (int k = 0; k < 16; ++k) score += std::max(0, c16[k] - 1);
-            }
-            return score;
-        };
-        // Rows by angle: quarters of the group (which is sorted by angle).
-        auto angular_rows = [&]() {
-            for (int r = 0; r < BS_ROWS; ++r) rw[r].clear();
-            for (int j = 0; j < ng; ++j) rw[j * BS_ROWS / ng].push_back(gset[j]);
-        };
-        // Rows by angle with distinct keys: the w are taken in angle order
-        // and each goes to the first row (from the current one on) whose
-        // lanes do not hold its key mod 16 yet, else to the current row.
-        auto keyed_rows = [&](int pch) {
-            for (int r = 0; r < BS_ROWS; ++r) rw[r].clear();
-            const int cap = (ng + BS_ROWS - 1) / BS_ROWS;
-            int cur = 0;
-            for (int j = 0; j < ng; ++j) {
-                while (cur < BS_ROWS - 1 && (int)rw[cur].size() >= cap) ++cur;
-                const int key = key_of(gset[j], pch) & 15;
-                int dst = -1;
-                for (int r = cur; r < BS_ROWS && dst < 0; ++r) {
-                    if ((int)rw[r].size() >= cap) continue;
-                    bool used = false;
-                    for (int i : rw[r]) used |= (key_of(i, pch) & 15) == key;
-                    if (!used) dst = r;
-                }
-                rw[dst < 0 ? cur : dst].push_back(gset[j]);
-            }
-        };
-        angular_rows();
-        make_items();
-        // the pitch (an even value from the widest region up to 8 more,
-        // within the LDS capacity) with the fewest repeated keys, for the
-        // angular rows and for the keyed rows of that pitch; the keyed rows
-        // are taken where their own regions fit that pitch
-        int pitch = maxw + (maxw & 1), best = 1 << 30, best_keyed = -1;
-        const int w_ang = maxw, h_ang = maxh;
-        for (int cand = w_ang + (w_ang & 1); cand < w_ang + 9; cand += 2) {
-            if (cand * h_ang > bs_max_region(K)) break;
-            angular_rows();
-            int sc = collisions(cand);
-            if (sc < best) { best = sc; pitch = cand; best_keyed = 0; }
-            keyed_rows(cand);
-            sc = collisions(cand);
-            if (sc < best) { best = sc; pitch = cand; best_keyed = 1; }
+            for (int k = 0; k < 16; ++k) score += 4 * std::max(0, c16[k] - 4);
+            for (int k = 0; k < 32; ++k) score += std::max(0, c32[k] - 2);
+            if (score < best) { best = score; pitch = cand; }
         }
-        if (best_keyed == 1) {
-            keyed_rows(pitch);
-            make_items();
-            if (maxw > pitch || pitch * maxh > bs_max_region(K)) {
-                angular_rows();
-                make_items();
-                best_keyed = 0;
-            }
-        } else {
-            angular_rows();
-            make_items();
-        }
-        if (nUmax == 0) continue;
         int lane_w[BS_LANES];
         std::fill(lane_w, lane_w + BS_LANES, -1);
-        for (int r = 0; r < BS_ROWS; ++r) {
-            std::vector<int> rest;
-            for (int i : rw[r]) {
-                const int l = 16 * r + (key_of(i, pitch) & 15);
-                if (lane_w[l] < 0) lane_w[l] = i;
-                else rest.push_back(i);
+        {
+            // bucket by key mod 16, each bucket alternating its two key
+            // classes, dealt to the 4 runs of 16 lanes in order
+            std::vector<std::vector<int>> bucket(16);
+            for (int k16 = 0; k16 < 16; ++k16) {
+                std::vector<int> a, b;
+                for (int i : gset) {
+                    const int key = ((pl->W[2 * i] + pitch * pl->W[2 * i + 1]) % 32 + 32) % 32;
+                    if ((key & 15) == k16) (key < 16 ? a : b).push_back(i);
+                }
+                if (a.size() < b.size()) std::swap(a, b);
+                for (size_t j = 0; j < a.size(); ++j) {
+                    bucket[k16].push_back(a[j]);
+                    if (j < b.size()) bucket[k16].push_back(b[j]);
+                }
             }
-            for (int l = 16 * r; l < 16 * r + 16 && !rest.empty(); ++l)
-                if (lane_w[l] < 0) { lane_w[l] = rest.back(); rest.pop_back(); }
+            std::vector<int> rest;
+            for (int k16 = 0; k16 < 16; ++k16) {
+                for (size_t j = 0; j < bucket[k16].size(); ++j) {
+                    if (j < 4) lane_w[16 * j + k16] = bucket[k16][j];
+                    else rest.push_back(bucket[k16][j]);
+                }
+            }
+            for (int lane = 0; lane < BS_LANES && !rest.empty(); ++lane)
+                if (lane_w[lane] < 0) { lane_w[lane] = rest.back(); rest.pop_back(); }
         }
         std::vector<std::unordered_map<int, int>> rank(BS_LANES);
         for (int lane = 0; lane < BS_LANES; ++lane) {
             int i = lane_w[lane];
             if (i < 0) {
-                // idle lane: repeat a w of its own row (same address, no extra
-                // bank conflict); its results are dropped.  A row with no w
-                // repeats the group's first.
+                // idle lane: repeat a w of its own 16-lane run (same address,
+                // no extra bank conflict); its results are dropped
                 for (int l = lane & ~15; l < (lane & ~15) + 16 && i < 0; ++l) i = lane_w[l];
-                if (i < 0) i = gset[0];
+                for (int l = 0; l < BS_LANES && i < 0; ++l) i = lane_w[l];
             } else {
                 for (size_t j = 0; j < Sw[i].size() / 2; ++j)
                     rank[lane][(Sw[i][2 * j + 1] + 64) * 256 + (Sw[i][2 * j] + 64)] = (int)j;
@@ -426,45 +372,41 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
             pl->group_xy[((size_t)gi * BS_LANES + lane) * 2 + 1] = pl->W[2 * i + 1];
         }
         for (const Item &gt : gitems) {
-            const int u0 = gt.u0, m = gt.m, rx0 = gt.rx0, ry0 = gt.ry0, rh = gt.rh;
-            // the item's v positions in runs of 4 slots, dealt to the waves in
-            // turn (at least one run each): wave c runs nsw[c] slots, at
-            // positions cstart[c] .. of every row's chunk
+            const int u0 = gt.u0, m = gt.m, rx0 = gt.rx0, ry0 = gt.ry0, rw = pitch, rh = gt.rh;
+            // the item's v in runs of 4 slots, dealt to the waves in turn (at
+            // least one run each): wave c runs nsw[c] slots, the first of its
+            // runs real, so an item of m v runs 4 ceil(m / 4) slots in all
             int nsw[BS_WAVES], cstart[BS_WAVES + 1];
             const int runs = std::max(BS_WAVES, (m + 3) / 4);
             cstart[0] = u0;
             for (int c = 0; c < BS_WAVES; ++c) {
                 nsw[c] = 4 * (runs / BS_WAVES + (c < runs % BS_WAVES ? 1 : 0));
-                cstart[c + 1] = cstart[c] + nsw[c];
+                cstart[c + 1] = cstart[c] + std::min(nsw[c], std::max(0, u0 + m - cstart[c]));
             }
             if (pitch * rh > bs_max_region(K)) { *err = "bispectrum region too large"; return false; }
             pl->max_region = std::max(pl->max_region, pitch * rh);
-            int32_t it[BS_ITEM_INTS] = {gi, rx0, ry0, pitch, rh, pitch * rh, pitch, 0, nsw[0], nsw[1], nsw[2], nsw[3]};
+            int32_t it[BS_ITEM_INTS] = {gi, rx0, ry0, rw, rh, rw * rh, pitch, 0, nsw[0], nsw[1], nsw[2], nsw[3]};
             for (int wv = 0; wv < BS_WAVES; ++wv) {
+                const int nreal = cstart[wv + 1] - cstart[wv];
                 pl->computed_terms += (int64_t)nsw[wv] * BS_LANES;
-                // the v of each row and slot (dummy past the row's chunk)
-                std::pair<int, int> vs[BS_ROWS][BS_MAX_SLOTS];
-                bool real[BS_ROWS][BS_MAX_SLOTS];
-                for (int r = 0; r < BS_ROWS; ++r)
-                    for (int k = 0; k < K; ++k) {
-                        const int u = cstart[wv] + k;
-                        real[r][k] = k < nsw[wv] && u < u0 + m && u < (int)U[r].size();
-                        vs[r][k] = real[r][k] ? U[r][u] : dummy(r, u0);
-                        const int vx = vs[r][k].first, vy = vs[r][k].second;
-                        pl->slot_v.push_back(vy * pitch + vx);
-                        pl->slot_v.push_back((int32_t)((vy + 16) * N + (vx & (N - 1))));
-                    }
-                for (int k = 0; k < K; ++k)
+                for (int k = 0; k < K; ++k) {
+                    // slots past the real v of the chunk repeat the item's first v
+                    const bool real = k < nreal;
+                    const int u = real ? cstart[wv] + k : u0;
+                    const int vx = U[u].first, vy = U[u].second;
+                    pl->slot_v.push_back(vy * pitch + vx);
+                    const uint32_t so = (uint32_t)((vy + 16) * N + (vx & (N - 1)));
+                    pl->slot_v.push_back((int32_t)so);
                     for (int lane = 0; lane < BS_LANES; ++lane) {
-                        const int r = lane / 16;
                         int32_t o = -1;
-                        if (real[r][k] && lane_w[lane] >= 0) {
-                            auto f = rank[lane].find((vs[r][k].second + 64) * 256 + (vs[r][k].first + 64));
+                        if (real && lane_w[lane] >= 0) {
+                            auto f = rank[lane].find((vy + 64) * 256 + (vx + 64));
                             if (f != rank[lane].end()) o = pl->woff[lane_w[lane]] + f->second;
                         }
                         if (o >= 0) ++covered;
                         pl->out_idx.push_back(o);
                     }
+                }
             }
             pl->items.insert(pl->items.end(), it, it + BS_ITEM_INTS);
         }

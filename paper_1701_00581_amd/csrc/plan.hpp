@@ -14,7 +14,6 @@ namespace nvsm {
 constexpr int BS_LANES = 64;
 constexpr int BS_MAX_SLOTS = 32;     // largest slot count per wave
 constexpr int BS_WAVES = 4;            // waves per workgroup
-constexpr int BS_ROWS = BS_LANES / 16; // rows of 16 lanes (DPP broadcast rows) per wave
 // Staged region extent (pitch x height) per frame, in whole 128s: larger
 // for more slots per wave, whose items span more v.  With 16 slots, 1024
 // (two 16-byte loads per lane and frame) holds the full items of every
@@ -87,10 +86,9 @@ struct HostPlan {
     int n_groups = 0;
     std::vector<int32_t> group_xy;
     int max_region = 0;                 // largest region points of any item
-    // slot[(((g*BS_WAVES + wave)*BS_ROWS + row)*K + k)*2 + 0] = vy *
-    // region_pitch + vx (offset of the row's v in the staged region), [..+1]
-    // = offset of I(v) in a frame's stored spectrum record (rows -16 ..
-    // N/2-1).  Each row of 16 lanes runs its own v.
+    // slot[((g*BS_WAVES + wave)*K + k)*2 + 0] = vy * region_pitch + vx
+    // (offset of v in the staged region), [..+1] = offset of I(v) in a
+    // frame's stored spectrum record (rows -16 .. N/2-1).
     std::vector<int32_t> slot_v;
     // out_idx[((g*BS_WAVES + wave)*K + k)*64 + lane] = S index or -1
     std::vector<int32_t> out_idx;

@@ -41,23 +41,14 @@ static long check_bispectrum(const HostPlan &pl, int N, int K) {
             const int ns = it[8 + wave];
             if (ns % 4 || ns > K || ns < 4) ++bad;
             for (int k = 0; k < K; ++k) {
-                // each row of 16 lanes has its own slot table
-                int rvx[BS_ROWS], rvy[BS_ROWS], rroff[BS_ROWS];
-                bool ok = true;
-                for (int row = 0; row < BS_ROWS; ++row) {
-                    const size_t sidx = (((size_t)(g * BS_WAVES + wave) * BS_ROWS + row) * K + k);
-                    const int roff = pl.slot_v[sidx * 2], so = pl.slot_v[sidx * 2 + 1];
-                    if (so < 0 || so >= (HALF + SPEC_NEG_ROWS_HOST) * N) { ++bad; ok = false; continue; }
-                    rvy[row] = so / N - SPEC_NEG_ROWS_HOST;
-                    rvx[row] = so % N;
-                    if (rvx[row] > HALF) rvx[row] -= N;
-                    rroff[row] = roff;
-                    if (roff != rvy[row] * pitch + rvx[row]) ++bad;
-                }
-                if (!ok) continue;
                 const size_t sidx = ((size_t)(g * BS_WAVES + wave) * K + k);
+                const int roff = pl.slot_v[sidx * 2], so = pl.slot_v[sidx * 2 + 1];
+                if (so < 0 || so >= (HALF + SPEC_NEG_ROWS_HOST) * N) { ++bad; continue; }
+                const int vy = so / N - SPEC_NEG_ROWS_HOST;
+                int vx = so % N;
+                if (vx > HALF) vx -= N;
+                if (roff != vy * pitch + vx) ++bad;
                 for (int lane = 0; lane < BS_LANES; ++lane) {
-                    const int row = lane / 16, vx = rvx[row], vy = rvy[row], roff = rroff[row];
                     const int wx = pl.group_xy[((size_t)gi * BS_LANES + lane) * 2];
                     const int wy = pl.group_xy[((size_t)gi * BS_LANES + lane) * 2 + 1];
                     if (wy < 0 || wy >= HALF) ++bad;
