@@ -100,7 +100,16 @@ def cpu_baseline(frames, stf, op, n_patches_total, ny, nx, workers):
         cpu_s = pool.map(_oracle_worker, chunks)
     wall = time.perf_counter() - t0
     per_burst_s = wall * n_patches_total / n
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=1.0 / per_burst_s, unit="bursts/s", cores=workers, kind="oracle",
+                host_cores=os.cpu_count(), cpu_model=cpu_model,
                 sample=f"{n} of {n_patches_total} patches (stratified, full frame count), FP64 NumPy oracle, "
                        f"{workers} worker processes, {wall:.1f} s wall / {sum(cpu_s):.1f} s CPU, "
                        f"extrapolated x{n_patches_total / n:.1f} to the whole burst (mosaic excluded)",
@@ -600,7 +609,8 @@ def main():
             "avg_launch_ms": bis_ms,
             "launches_per_step": bis_launches,
         },
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                                      "host_cores", "cpu_model")},
     }
     print(json.dumps(out), flush=True)
     s.close()

@@ -1,8 +1,10 @@
 """Serving loop: bursts from several detector channels arrive frame by frame
 and are reconstructed as they complete (continuous batching).
 
-Each channel has its own HIP stream, two device staging buffers of one group
-of frames each and a workspace (group scratch and final buffers).  Per-burst
+Each channel has a compute stream and a copy stream (both of default
+priority; frames move host to device on the copy stream while the channel's
+earlier work computes), two device staging buffers of one group of frames
+each and a workspace (group scratch and final buffers).  Per-burst
 device memory comes from a pool of slots sized to an HBM budget; a burst is admitted when its first frame
 arrives and a slot of its channel's shape is free, otherwise its frames
 wait on the host until one frees (admission by HBM footprint).  Work of
@@ -97,6 +99,7 @@ class Server:
         for c in channels:
             _lib.nvsm_prepare(self.ctx, c.params)
             st = torch.cuda.Stream(device=self.dev)           # default priority
+            cp = torch.cuda.Stream(device=self.dev)           # host-to-device copies, default priority
             if policy == "stream":
                 slot_b, gws_b = _lib.nvsm_stream_plan(c.params, c.H, c.W, self.max_group)
                 gws = torch.empty(gws_b, dtype=torch.uint8, device=self.dev)
@@ -107,8 +110,8 @@ class Server:
                 slot_b = max_frames * c.H * c.W * 2
                 gws = torch.empty(info.ws_reconstruct, dtype=torch.uint8, device=self.dev)
                 stage = None
-            self.ch[c.name] = dict(spec=c, stream=st, gws=gws, stage=stage, fill=0, slot_bytes=slot_b, free=[],
-                                   active={}, order=collections.deque(), last_ev=None)
+            self.ch[c.name] = dict(spec=c, stream=st, copy=cp, gws=gws, stage=stage, fill=0, read_ev=[None, None],
+                                   slot_bytes=slot_b, free=[], active={}, order=collections.deque(), last_ev=None)
             need.append((c.name, slot_b))
         # slots: one per channel first, then round robin while the budget lasts
         used = 0
@@ -153,32 +156,42 @@ class Server:
         """Every channel's last launch has finished on the device."""
         return all(c["last_ev"] is None or c["last_ev"].query() for c in self.ch.values())
 
+    def _copies_done(self, c):
+        """The channel's compute stream waits for the copies issued so far."""
+        ev = self.torch.cuda.Event()
+        ev.record(c["copy"])
+        c["stream"].wait_event(ev)
+
     def _advance(self, c):
         torch = self.torch
         spec = c["spec"]
         for b in list(c["active"].values()):
             if not self._admit(c, b):
                 break                                  # bursts are admitted in arrival order
-            with torch.cuda.stream(c["stream"]):
-                if self.policy == "stream":
-                    while True:
-                        # arrived frames go to the filling buffer at once (its
-                        # previous group's ingest precedes the copies on this
-                        # stream)
-                        stage = c["stage"][c["fill"]]
+            if self.policy == "stream":
+                while True:
+                    # arrived frames go to the filling buffer at once, on the
+                    # copy stream (which waited for that buffer's last
+                    # reader when it became the filling one)
+                    stage = c["stage"][c["fill"]]
+                    with torch.cuda.stream(c["copy"]):
                         while b.pending and b.staged < self.max_group:
                             stage[b.staged].copy_(torch.from_numpy(b.pending.pop(0).view(np.int16)),
                                                   non_blocking=True)
                             b.staged += 1
-                        g = b.staged
-                        last = bool(b.total) and not b.pending
-                        if not (g and (last or g >= self.max_group or (g >= self.group and self._gpu_idle()))):
-                            break
-                        b.count += g
-                        b.staged = 0
-                        final = b.total if last else 0
+                    g = b.staged
+                    last = bool(b.total) and not b.pending
+                    if not (g and (last or g >= self.max_group or (g >= self.group and self._gpu_idle()))):
+                        break
+                    self._copies_done(c)
+                    b.count += g
+                    b.staged = 0
+                    final = b.total if last else 0
+                    with torch.cuda.stream(c["stream"]):
                         _lib.nvsm_stream_add(self.ctx, spec.params, stage[:g], b.count - g, final, b.slot, c["gws"])
-                        c["fill"] ^= 1
+                        rd = torch.cuda.Event()
+                        rd.record(c["stream"])
+                        c["read_ev"][c["fill"]] = rd
                         b.groups += 1
                         if final:
                             b.image = torch.empty((spec.H, spec.W), dtype=torch.float32, device=self.dev)
@@ -186,21 +199,29 @@ class Server:
                                                     c["gws"])
                         c["last_ev"] = torch.cuda.Event()
                         c["last_ev"].record(c["stream"])
-                        if final:
-                            break
-                else:
-                    frames = b.slot.view(torch.int16)
+                    # the other buffer fills next, once its last group was read
+                    c["fill"] ^= 1
+                    if c["read_ev"][c["fill"]] is not None:
+                        c["copy"].wait_event(c["read_ev"][c["fill"]])
+                    if final:
+                        break
+            else:
+                frames = b.slot.view(torch.int16)
+                with torch.cuda.stream(c["copy"]):
                     for fr in b.pending:
                         frames[b.count * spec.H * spec.W:(b.count + 1) * spec.H * spec.W].copy_(
                             torch.from_numpy(fr.view(np.int16)).reshape(-1), non_blocking=True)
                         b.count += 1
-                    b.pending.clear()
-                    if b.total and b.count == b.total:
+                b.pending.clear()
+                if b.total and b.count == b.total:
+                    self._copies_done(c)
+                    with torch.cuda.stream(c["stream"]):
                         b.image = torch.empty((spec.H, spec.W), dtype=torch.float32, device=self.dev)
                         fv = frames[: b.total * spec.H * spec.W].view(b.total, spec.H, spec.W)
                         _lib.nvsm_reconstruct(self.ctx, spec.params, fv, spec.stf, b.image, c["gws"])
                         c["last_ev"] = torch.cuda.Event()
                         c["last_ev"].record(c["stream"])
+            with torch.cuda.stream(c["stream"]):
                 if b.total and b.count == b.total and b.event is None:
                     b.event = torch.cuda.Event()
                     b.event.record(c["stream"])
