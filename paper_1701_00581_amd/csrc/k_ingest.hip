@@ -100,16 +100,20 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
     const size_t spec_patch = (size_t)(bd.spec0 + (int64_t)lpatch * F) * FS;
 
     // raw pixels of the current frame pair (wave-uniform frame bases, 32-bit
-    // lane offsets).  Loading the next pair during the transform measured no
-    // faster at 8 waves per CU and made the registers spill.
+    // lane offsets).  The next pair's are requested after the transform,
+    // before the record stores (see below).
     Quad<T, VEC> qa[QPT], qb[QPT];
     auto load_pair = [&](int fa) __attribute__((always_inline)) {
         const int fb = min(fa + 1, f1 - 1);
         const gptr_c pa = uniform_ptr(frames + (size_t)fa * H * pitch + (size_t)y0 * pitch + x0);
         const gptr_c pb = uniform_ptr(frames + (size_t)fb * H * pitch + (size_t)y0 * pitch + x0);
+        // the thread index, opaque to the optimizer: the offsets are formed
+        // here rather than kept (spilled) across the loop
+        int tid_l;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid_l) : "v"(tid));
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * FT + tid_l, y = (4 * q) / N, x = (4 * q) % N;
             const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(T);
             qa[j].load(pa, off);
             qb[j].load(pb, off);
@@ -117,10 +121,13 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
     };
     __syncthreads();
 
+    load_pair(f0);
+    // all of the first pair here, so that at the loop's head only the loads
+    // of a pass's prefetch are waited for (not the stores that follow them)
+    __builtin_amdgcn_s_waitcnt(0x0f70);          // vmcnt(0)
     for (int fa = f0; fa < f1; fa += 2) {
         const int fb = fa + 1;
         const bool hasb = fb < f1;
-        load_pair(fa);
         // weighted sums (compensated); the pixels stay in registers
         float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
 #pragma unroll
@@ -160,43 +167,62 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
         }
         __syncthreads();
         fft2d_lds<N, FT>(z, tw);
+        // the next pair's pixels, requested now (into the registers this
+        // pair's pixels left), before this pair's record stores: loads and
+        // stores share one counter, so the next pair then waits for its
+        // pixels only.  Every pass issues the same loads and stores (past the
+        // group's end the last frame is loaded again, unused; a missing
+        // second frame's stores go to the first frame's record, ahead of the
+        // first frame's own), so the compiler knows how many are in flight.
+        load_pair(min(fa + 2, f1 - 1));
         // records of the two frames: wave-uniform bases, 32-bit lane offsets
-        // (fb = F when the group has no second frame: never stored to)
         const gptr_m rec_a = uniform_ptr_m(spectra + spec_patch + (size_t)fa * FS);
-        const gptr_m rec_b = uniform_ptr_m(spectra + spec_patch + (size_t)fb * FS);
-        // split the two spectra, write rows 0..N/2-1, accumulate |I|^2
+        const gptr_m rec_b = uniform_ptr_m(spectra + spec_patch + (size_t)(hasb ? fb : fa) * FS);
+        int tid_o;                   // opaque thread index (addresses formed here)
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid_o) : "v"(tid));
+        // I_a and I_b of frequency (ux, uy) from the transform of z = a + i b
+        auto split = [&](int ux, int uy, float2 &Ia, float2 &Ib) __attribute__((always_inline)) {
+            const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
+            const float2 Zm = z[fft_pos<N>((N - uy) & (N - 1)) * P + fft_pos<N>((N - ux) & (N - 1))];
+            Ia = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+            Ib = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+        };
+        // rows 0..N/2-1: the record rows and the power; row N/2: the power
+        static_assert(HALF * N % FT == 0 && SPEC_NEG_ROWS * N % FT == 0, "whole rows per pass");
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int j = k * FT + tid;
-            if (j < NP) {
+            const int j = k * FT + tid_o;
+            if (k * FT + tid < NP) {
                 const int uy = j / N, ux = j % N;
-                const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
-                const float2 Zm = z[fft_pos<N>((N - uy) & (N - 1)) * P + fft_pos<N>((N - ux) & (N - 1))];
-                const float2 Ia = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
-                const float2 Ib = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+                float2 Ia, Ib;
+                split(ux, uy, Ia, Ib);
                 ps[k] += Ia.x * Ia.x + Ia.y * Ia.y;
                 if (hasb) ps[k] += Ib.x * Ib.x + Ib.y * Ib.y;
-                if (uy < HALF) {
-                    // row uy of the stored record, and its conjugate mirror
-                    // I(-u) = conj I(u) in row -uy for the rows below 0
+                if (k * FT < HALF * N) {
                     const unsigned o = ((uy + SPEC_NEG_ROWS) * N + ux) * (unsigned)sizeof(float2);
+                    store_global_f2(rec_b, o, Ib);
                     store_global_f2(rec_a, o, Ia);
-                    if (hasb) store_global_f2(rec_b, o, Ib);
-                    if (uy >= 1 && uy <= SPEC_NEG_ROWS) {
-                        const unsigned om = ((SPEC_NEG_ROWS - uy) * N + ((N - ux) & (N - 1))) * (unsigned)sizeof(float2);
-                        store_global_f2(rec_a, om, conjf2(Ia));
-                        if (hasb) store_global_f2(rec_b, om, conjf2(Ib));
-                    }
                 }
-                if (j == 1) {          // u = (1, 0)
+                if (k * FT + tid == 1) {   // u = (1, 0)
                     kahan_add(m10s[0], m10c[0], Ia.x); kahan_add(m10s[1], m10c[1], Ia.y);
                     if (hasb) { kahan_add(m10s[0], m10c[0], Ib.x); kahan_add(m10s[1], m10c[1], Ib.y); }
                 }
-                if (j == N) {          // u = (0, 1)
+                if (k * FT + tid == N) {   // u = (0, 1)
                     kahan_add(m01s[0], m01c[0], Ia.x); kahan_add(m01s[1], m01c[1], Ia.y);
                     if (hasb) { kahan_add(m01s[0], m01c[0], Ib.x); kahan_add(m01s[1], m01c[1], Ib.y); }
                 }
             }
+        }
+        // the conjugate mirrors I(-u) = conj I(u) of rows 1..16 in rows -1..-16
+#pragma unroll
+        for (int k = 0; k < SPEC_NEG_ROWS * N / FT; ++k) {
+            const int j = k * FT + tid_o;
+            const int uy = 1 + j / N, ux = j % N;
+            float2 Ia, Ib;
+            split(ux, uy, Ia, Ib);
+            const unsigned om = ((SPEC_NEG_ROWS - uy) * N + ((N - ux) & (N - 1))) * (unsigned)sizeof(float2);
+            store_global_f2(rec_b, om, conjf2(Ib));
+            store_global_f2(rec_a, om, conjf2(Ia));
         }
         __syncthreads();
     }
