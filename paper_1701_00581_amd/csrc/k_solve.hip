@@ -46,40 +46,42 @@ template <> struct Win<0> { static constexpr int INNER = 416, RING = 2560; };
 template <> struct Win<1> { static constexpr int INNER = 512, RING = 3072; };
 
 // Sum over the 64 lanes with DPP row operations; the total lands in lane 63.
-template <int CTRL, int ROWMASK>
+// Every step reads a valid source lane for lane 63 (and bound_ctrl gives 0
+// to lanes without one), so no lane needs an initial value.
+template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, ROWMASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double wave_total_lane63(double v) {
-    v += dpp_d<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
-    v += dpp_d<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
-    v += dpp_d<0x141, 0xf>(v);   // row_half_mirror
-    v += dpp_d<0x140, 0xf>(v);   // row_mirror: every lane holds its row sum
-    v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
-    v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    v += dpp_d<0xb1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_d<0x4e>(v);     // quad_perm [2,3,0,1]
+    v += dpp_d<0x141>(v);    // row_half_mirror
+    v += dpp_d<0x140>(v);    // row_mirror: every lane holds its row sum
+    v += dpp_d<0x142>(v);    // row_bcast:15: row 3 gets rows 2 + 3, row 1 rows 0 + 1
+    v += dpp_d<0x143>(v);    // row_bcast:31: row 3 gets the total
     return v;
 }
 
 // Samples of one unit for this lane: lane l takes samples l, l + 64, ...
-// of the wave's w (w, cnt and bar are wave-uniform).
+// of the wave's w (w and bar are wave-uniform).
 template <int TPL>
 struct UnitRegs {
-    int w, cnt, bar, slot;
+    int w, bar, slot;
     unsigned code[TPL];
     float2 b[TPL];
 };
 
 template <int N, int TPL, int BIG>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6 : 2))) void k_solve(int nW, int n_units, const int *__restrict__ units,
-                                              const unsigned *__restrict__ code,
+                                              int zero_slot, const unsigned *__restrict__ code,
                                               const int *__restrict__ Wxy, const float *__restrict__ power,
                                               const float *__restrict__ mean_spec,
                                               const float2 *__restrict__ bispec, int64_t s_count,
                                               const BurstTable bt, double floor_, int noise_bias,
                                               double *__restrict__ amp, double2 *__restrict__ phasor) {
-    __shared__ double2 e[Win<BIG>::INNER + Win<BIG>::RING];
+    __shared__ double2 e[Win<BIG>::INNER + Win<BIG>::RING + 1];   // + the zero phasor
     __shared__ double red[NWAVE];
     const int patch = blockIdx.x;
     const double *stf = bt.b[burst_of(bt, patch, [](const BurstDesc &d) { return (int64_t)d.patch0; })].stf;
@@ -133,12 +135,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
         const double2 e1 = unit_or_one(make_double2((double)m[2], (double)m[3]));
         e[0] = e0;
         e[1] = e1;
+        e[zero_slot] = make_double2(0.0, 0.0);
         ph_out[0] = e0;
         ph_out[1] = e1;
     }
 
-    const float2 *B = bispec + (size_t)patch * s_count;
+    // B of this patch through a buffer resource: a read past the patch's
+    // samples returns zero (those lanes' codes are padding anyway)
+    const __amdgpu_buffer_rsrc_t brsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(bispec + (size_t)patch * s_count), (short)0,
+                                          (int)(s_count * (int64_t)sizeof(float2)), 0x00020000);
     constexpr int DEPTH = depth_of<TPL>();
+    constexpr int PAD = 64 * TPL;
     // A unit's table entry (this wave's w, first sample, count and barrier
     // flag, LDS slot of the phasor) is read one unit before its samples are
     // requested, so neither the sample loads nor the phasor's store wait on
@@ -147,41 +155,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
         const int *t = units + ((size_t)u * NWAVE + wave) * 4;
         return make_int4(t[0], t[1], t[2], t[3]);
     };
+    // The code block of the wave's w holds PAD codes (padding: two reads of
+    // the zero phasor), so every lane reads TPL codes and TPL samples of B
+    // without a bounds test; a padding sample adds zero whatever B it read.
     auto load = [&](const int4 t, UnitRegs<TPL> &r) __attribute__((always_inline)) {
         r.w = t.x;
-        r.cnt = t.z & 0xffff;
         r.bar = t.z >> 16;
         r.slot = t.w;
+        const unsigned *cw = code + (size_t)max(t.x, 0) * PAD;
+        const int b0 = (t.y + lane) * (int)sizeof(float2);
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
-            const int k = lane + 64 * i;
-            const int idx = k < r.cnt ? t.y + k : 0;
-            r.code[i] = code[idx];
-            r.b[i] = B[idx];
+            r.code[i] = cw[lane + 64 * i];
+            // the whole byte offset in the lane's register (none in the
+            // instruction's offset field), so the range test covers all of it
+            int off;
+            asm("v_add_u32 %0, %2, %1" : "=v"(off) : "v"(b0), "i"(64 * (int)sizeof(float2) * i));
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(brsrc, off, 0, 0);
+            r.b[i] = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
         }
     };
-    // Branch-free over the samples (a lane's unused slots hold sample 0 and
-    // add zero), so that the compiler knows how many loads are in flight at
-    // every use and waits only for the unit's own.
+    // Branch-free over the samples, so that the compiler knows how many
+    // loads are in flight at every use and waits only for the unit's own.
+    // A code holds the LDS slots of e(w - v) (bits 16..30) and e(v) (bits
+    // 0..14), each with a conjugation flag above it (bits 31 and 15).
     auto solve = [&](const UnitRegs<TPL> &r) __attribute__((always_inline)) {
         if (r.w < 0) return;                      // no w of this unit in this wave
         double zx = 0.0, zy = 0.0;
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
-            const int k = lane + 64 * i;
             const unsigned cd = r.code[i];
-            const unsigned ia = cd >> 16, ib = cd & 0xffffu;
-            double2 ea = e[ia & 0x7fffu];
-            double2 eb = e[ib & 0x7fffu];
-            if (ia & 0x8000u) ea.y = -ea.y;
-            if (ib & 0x8000u) eb.y = -eb.y;
-            const double px = ea.x * eb.x - ea.y * eb.y;
-            const double py = ea.x * eb.y + ea.y * eb.x;
-            const double use = k < r.cnt ? 1.0 : 0.0;
-            const double bx = use * (double)r.b[i].x, by = use * (double)r.b[i].y;
-            // (px + i py) * conj(bx + i by)
-            zx += px * bx + py * by;
-            zy += py * bx - px * by;
+            double2 ea = e[(cd >> 16) & 0x7fffu];
+            double2 eb = e[cd & 0x7fffu];
+            // conjugation: the flag bit moved onto the sign of the imaginary part
+            ea.y = __longlong_as_double(__double_as_longlong(ea.y) ^ ((long long)(cd & 0x80000000u) << 32));
+            eb.y = __longlong_as_double(__double_as_longlong(eb.y) ^ ((long long)((cd << 16) & 0x80000000u) << 32));
+            const double px = fma(ea.x, eb.x, -ea.y * eb.y);
+            const double py = fma(ea.x, eb.y, ea.y * eb.x);
+            const double bx = (double)r.b[i].x, by = (double)r.b[i].y;
+            // z += (px + i py) * conj(bx + i by)
+            zx = fma(px, bx, fma(py, by, zx));
+            zy = fma(py, bx, fma(-px, by, zy));
         }
         const double tx = wave_total_lane63(zx);
         const double ty = wave_total_lane63(zy);
@@ -380,16 +394,18 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, 
 template <int N, int TPL, int BIG>
 hipError_t launch_solve_t(const SolveArgs &a, hipStream_t st) {
     hipLaunchKernelGGL((k_solve<N, TPL, BIG>), dim3(a.bt.patches), dim3(NT), 0, st, a.nW, a.n_units, a.units,
-                       a.code, a.Wxy, a.power, a.mean_spec, a.bispec,
+                       a.zero_slot, a.code, a.Wxy, a.power, a.mean_spec, a.bispec,
                        a.s_count, a.bt, a.floor, a.noise_bias, a.amp, a.phasor);
     return hipGetLastError();
 }
 
 template <int N, int BIG>
 hipError_t launch_solve_n(const SolveArgs &a, hipStream_t st) {
-    if (a.max_sw <= 128) return launch_solve_t<N, 2, BIG>(a, st);
-    if (a.max_sw <= 256) return launch_solve_t<N, 4, BIG>(a, st);
-    return launch_solve_t<N, 8, BIG>(a, st);
+    switch (solve_samples_per_lane(a.max_sw)) {
+    case 2: return launch_solve_t<N, 2, BIG>(a, st);
+    case 4: return launch_solve_t<N, 4, BIG>(a, st);
+    default: return launch_solve_t<N, 8, BIG>(a, st);
+    }
 }
 
 }  // namespace
@@ -408,7 +424,8 @@ hipError_t launch_solve(const SolveArgs &a, hipStream_t st) {
         hipError_t e = launch_solve(SolveArgs(a, 0), st);
         return e != hipSuccess ? e : launch_lsq(a, st);
     }
-    if (a.max_sw > 512) return hipErrorInvalidValue;
+    if (a.max_sw > SOLVE_MAX_SAMPLES || a.zero_slot != a.n_inner + a.ring) return hipErrorInvalidValue;
+    if (a.s_count * (int64_t)sizeof(float2) > INT32_MAX) return hipErrorInvalidValue;   // buffer range of B
     const bool small = a.n_inner <= Win<0>::INNER && a.ring <= Win<0>::RING;
     if (!small && (a.n_inner > Win<1>::INNER || a.ring > Win<1>::RING)) return hipErrorInvalidValue;
     if (a.N == 128) return small ? launch_solve_n<128, 0>(a, st) : launch_solve_n<128, 1>(a, st);

@@ -156,7 +156,8 @@ struct SolveArgs {
     const int *units = nullptr;           // phase-solve units (see plan.hpp)
     int n_units = 0;
     int n_inner = 0, ring = 0;            // phasor window (see plan.hpp)
-    const unsigned *code = nullptr;       // sample codes with LDS slots
+    int zero_slot = 0;                    // window slot of the zero phasor
+    const unsigned *code = nullptr;       // padded sample codes with LDS slots (solve_code)
     const float *power = nullptr, *mean_spec = nullptr;
     const float2 *bispec = nullptr;
     int64_t s_count = 0;

@@ -304,8 +304,8 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
     dp->nshell = (int)h.shell_wb.size() - 1;
     int max_per_shell = 0;
     for (int s = 0; s < dp->nshell; ++s) max_per_shell = std::max(max_per_shell, h.shell_wb[s + 1] - h.shell_wb[s]);
-    for (size_t i = 0; i + 1 < h.woff.size(); ++i) dp->max_sw = std::max(dp->max_sw, h.woff[i + 1] - h.woff[i]);
-    if (max_per_shell > 16 || dp->max_sw > 512 || h.n_inner > 512 || h.ring_size > 3072)
+    dp->max_sw = h.max_sw;
+    if (max_per_shell > 16 || h.solve_code.empty() || h.n_inner > 512 || h.ring_size > 3072)
         return fail(ctx, NVSM_ERR_INVALID_ARG, "shell or phasor window too large for the phase kernel");
     if (h.n_inner + h.lsq_span > LSQ_ACC)
         return fail(ctx, NVSM_ERR_INVALID_ARG, "least-squares accumulator window too large");
@@ -318,7 +318,7 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
         (s = upload(dp.get(), h.shell_wb, &dp->shell_wb, &msg)) ||
         (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
         (s = upload(dp.get(), h.solve_units, &dp->units, &msg)) ||
-        (s = upload(dp.get(), h.phase_slot_code, &dp->code, &msg)) ||
+        (s = upload(dp.get(), h.solve_code, &dp->code, &msg)) ||
         (s = upload(dp.get(), h.phase_code, &dp->wcode, &msg)) ||
         (s = upload(dp.get(), h.lsq_fin, &dp->lsq_fin, &msg)) ||
         (s = upload(dp.get(), h.items, &dp->items, &msg)) ||
@@ -442,6 +442,7 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, co
     SolveArgs a;
     a.N = p->patch; a.bt = bt; a.nW = (int)(dp->h.W.size() / 2); a.nshell = dp->nshell;
     a.max_sw = dp->max_sw; a.shell_wb = dp->shell_wb; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
+    a.zero_slot = dp->h.zero_slot;
     a.w_slot = dp->w_slot; a.n_inner = dp->h.n_inner; a.ring = dp->h.ring_size;
     a.units = dp->units; a.n_units = dp->h.n_units;
     a.power = power; a.mean_spec = mean_spec; a.bispec = (const float2 *)bispec; a.s_count = dp->h.s_count;

@@ -175,6 +175,21 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     }
     if (pl->s_count >= (int64_t)1 << 31) { *err = "bispectrum set too large"; return false; }
 
+    // the solve's padded code blocks
+    pl->max_sw = 0;
+    for (int w = 0; w < nW; ++w) pl->max_sw = std::max(pl->max_sw, pl->woff[w + 1] - pl->woff[w]);
+    pl->zero_slot = pl->n_inner + pl->ring_size;
+    pl->solve_code.clear();
+    pl->solve_pad = 0;
+    if (pl->max_sw <= SOLVE_MAX_SAMPLES) {
+        pl->solve_pad = 64 * solve_samples_per_lane(pl->max_sw);
+        const uint32_t zero = ((uint32_t)pl->zero_slot << 16) | (uint32_t)pl->zero_slot;
+        pl->solve_code.assign((size_t)nW * pl->solve_pad, zero);
+        for (int w = pl->shell_wb[1]; w < nW; ++w)
+            std::copy(pl->phase_slot_code.begin() + pl->woff[w], pl->phase_slot_code.begin() + pl->woff[w + 1],
+                      pl->solve_code.begin() + (size_t)w * pl->solve_pad);
+    }
+
     // phase-solve units: shells 1.. cut into runs of SOLVE_WAVES w
     pl->solve_units.clear();
     pl->n_units = 0;

@@ -28,6 +28,10 @@ constexpr int BS_ITEM_INTS = 12;       // ints per workgroup item
 constexpr int LSQ_ROUND = 64;
 // Waves of the phase-solve workgroup (one w each per unit).
 constexpr int SOLVE_WAVES = 8;
+// Samples per lane in a phase-solve unit: a w's samples over 64 lanes,
+// rounded up to 2, 4 or 8 (the largest sample count of any w decides).
+constexpr int SOLVE_MAX_SAMPLES = 512;
+constexpr int solve_samples_per_lane(int max_sw) { return max_sw <= 128 ? 2 : max_sw <= 256 ? 4 : 8; }
 constexpr int LSQ_ACC = 3968;
 
 struct Tiling {
@@ -54,6 +58,15 @@ struct HostPlan {
     // while the sample's shell is solved, and the slot of every w.
     std::vector<uint32_t> phase_slot_code;
     std::vector<int32_t> w_slot;
+    // phase_slot_code as the phase-solve kernel reads it: one block of
+    // solve_pad = 64 x solve_samples_per_lane(max_sw) codes per w, entry k
+    // of block w the code of sample woff[w] + k for k below its count and
+    // otherwise two reads of zero_slot (= n_inner + ring_size, a window
+    // slot past the ring that holds a zero phasor, so that padding samples
+    // add nothing); the seeds' blocks are all padding.  Empty when some w
+    // has more than SOLVE_MAX_SAMPLES samples.
+    int max_sw = 0, solve_pad = 0, zero_slot = 0;
+    std::vector<uint32_t> solve_code;
     // Phase-solve units: each shell after the first (the seeds) cut into
     // units of at most SOLVE_WAVES w, one w per wave.  solve_units[(u *
     // SOLVE_WAVES + j) * 4 + 0..3] = (w of wave j or -1, its first S index,

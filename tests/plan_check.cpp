@@ -8,7 +8,9 @@
 //    of that very (w, v);
 //  * the least-squares rounds are consistent: every target of a round's
 //    samples is an inner entry or lies in the round's live window, the
-//    window fits the accumulator ring, and the flushed prefixes grow to |W|.
+//    window fits the accumulator ring, and the flushed prefixes grow to |W|;
+//  * the phase-solve units cover W in order, and each w's padded code block
+//    holds its own sample codes followed by reads of the zero phasor's slot.
 // Prints one line per case ending in "bad=<count>"; exit status 0.
 #include "plan.hpp"
 
@@ -129,6 +131,25 @@ static long check_solve_units(const HostPlan &pl) {
         if ((flag != 0) != end) ++bad;
     }
     if (expect != nW) ++bad;
+    // the padded code blocks: w's codes, then reads of the zero slot, which
+    // lies past every phasor slot
+    if (pl.zero_slot != pl.n_inner + pl.ring_size || pl.zero_slot > 0x7fff) ++bad;
+    if (pl.solve_pad != 64 * solve_samples_per_lane(pl.max_sw) || pl.solve_pad < pl.max_sw) return bad + 1;
+    if (pl.solve_code.size() != (size_t)nW * pl.solve_pad) return bad + 1;
+    const uint32_t zero = ((uint32_t)pl.zero_slot << 16) | (uint32_t)pl.zero_slot;
+    for (int w = 0; w < nW; ++w) {
+        if (pl.w_slot[w] >= pl.zero_slot) ++bad;
+        const int cnt = w < pl.shell_wb[1] ? 0 : pl.woff[w + 1] - pl.woff[w];
+        for (int k = 0; k < pl.solve_pad; ++k) {
+            const uint32_t c = pl.solve_code[(size_t)w * pl.solve_pad + k];
+            if (k < cnt) {
+                if (c != pl.phase_slot_code[pl.woff[w] + k]) ++bad;
+                if ((int)((c >> 16) & 0x7fffu) >= pl.zero_slot || (int)(c & 0x7fffu) >= pl.zero_slot) ++bad;
+            } else if (c != zero) {
+                ++bad;
+            }
+        }
+    }
     return bad;
 }
 

@@ -198,6 +198,7 @@ def test_solve_on_identical_inputs(torch_cuda):
     (128, 40, 16, 40, 1, 200, 200, 8),     # the largest R, a low cut-off, 3x3 patches at a short stride
     (64, 20, 5, 24, 0, 100, 90, 9),        # no taper, odd F, clamped last row and column
     (64, 31, 3, 32, 1, 96, 130, 6),        # the smallest usual R
+    (64, 3, 2, 32, 1, 96, 96, 5),          # |S| = 44, fewer samples than one padded code block
 ])
 def test_other_geometries_accumulate_and_solve(torch_cuda, N, u_cut, R, stride, window, H, W, F):
     """Parameter sets away from the benchmark's: the bispectrum work plan
