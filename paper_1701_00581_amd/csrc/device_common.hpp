@@ -109,7 +109,7 @@ template <int N> struct SpecRows {
 // radix-R2 pass over stride-R1 subsequences with twiddles, then a radix-R1
 // pass over contiguous groups.  Ends with a barrier.
 template <int N, int NT>
-__device__ void fft2d_lds(float2 *z, const float2 *tw) {
+__device__ __forceinline__ void fft2d_lds_inline(float2 *z, const float2 *tw) {
     constexpr int R1 = FftGeom<N>::R1, R2 = FftGeom<N>::R2, P = LdsPitch<N>::v;
     const int tid = threadIdx.x;
     // axis 0 = along x (rows), axis 1 = along y (columns)
@@ -147,6 +147,12 @@ __device__ void fft2d_lds(float2 *z, const float2 *tw) {
         }
         __syncthreads();
     }
+}
+// The same, left to the compiler to inline or call (a call keeps the
+// transform's registers out of a caller that holds many of its own).
+template <int N, int NT>
+__device__ void fft2d_lds(float2 *z, const float2 *tw) {
+    fft2d_lds_inline<N, NT>(z, tw);
 }
 
 // A wave-uniform pointer held in scalar registers, opaque to the optimizer:

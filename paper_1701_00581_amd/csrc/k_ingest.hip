@@ -16,7 +16,8 @@ namespace {
 
 constexpr int NT = 256;
 // The transform kernels hold one workgroup per CU (the tile fills most of
-// LDS), so they run 8 waves to hide latency.
+// LDS), so they run at least 8 waves to hide latency (the ingest of 16-bit
+// pixels 16, see ingest_threads).
 constexpr int FT = 512;
 
 // Four consecutive pixels of a row, loaded as one vector when the layout
@@ -56,21 +57,28 @@ template <typename T> struct Quad<T, false> {
     __device__ float operator[](int i) const { return e[i]; }
 };
 
+// Threads of an ingest workgroup: 16 waves (4 per SIMD, 128 registers per
+// lane) for 16-bit pixels, 8 for 32-bit pixels, whose registers would not
+// fit 128.  The transform is inlined into the kernel (as a call it kept
+// registers of its own and made the kernel wait at the call).
+template <typename T> constexpr int ingest_threads() { return sizeof(T) <= 2 ? 1024 : 512; }
+
 template <int N, typename T, bool VEC>
-__global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, int chunk_frames, int window,
+__global__ __launch_bounds__(ingest_threads<T>()) void k_ingest(const BurstTable bt, int stride, int chunk_frames, int window,
                                                float inv_wsum, const float2 *__restrict__ twiddle,
                                                const float *__restrict__ hann,
                                                float2 *__restrict__ spectra, float *__restrict__ ppart,
                                                float *__restrict__ mpart, float *__restrict__ mupart) {
+    constexpr int IT = ingest_threads<T>();
     constexpr int P = LdsPitch<N>::v;
     constexpr int HALF = N / 2;
     constexpr int NP = (HALF + 1) * N;           // power rows 0..N/2
-    constexpr int NPT = (NP + FT - 1) / FT;
-    constexpr int QPT = N * N / 4 / FT;          // pixel quads per thread and frame
+    constexpr int NPT = (NP + IT - 1) / IT;
+    constexpr int QPT = N * N / 4 / IT;          // pixel quads per thread and frame
     __shared__ float2 z[N * P];
     __shared__ float2 tw[N];
     __shared__ float hw[N];
-    __shared__ float red[2][FT / 64];
+    __shared__ float red[2][IT / 64];
 
     const int L = xcd_remap(blockIdx.x, bt.ingest_wgs);
     const int b = burst_of(bt, L, [](const BurstDesc &d) { return (int64_t)d.ingest0; });
@@ -85,7 +93,7 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
     const int y0 = min(py * stride, H - N), x0 = min(px * stride, W - N);
     const int f0 = chunk * chunk_frames, f1 = min(F, f0 + chunk_frames);
     const int tid = threadIdx.x;
-    for (int i = tid; i < N; i += FT) {
+    for (int i = tid; i < N; i += IT) {
         tw[i] = twiddle[i];
         hw[i] = window ? hann[i] : 1.0f;
     }
@@ -113,7 +121,7 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid_l) : "v"(tid));
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * FT + tid_l, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * IT + tid_l, y = (4 * q) / N, x = (4 * q) % N;
             const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(T);
             qa[j].load(pa, off);
             qb[j].load(pb, off);
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
         float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * IT + tid, y = (4 * q) / N, x = (4 * q) % N;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float va = qa[j][e], vb = hasb ? qb[j][e] : 0.f;
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
         __syncthreads();
         float mua = 0.f, mub = 0.f;
 #pragma unroll
-        for (int k = 0; k < FT / 64; ++k) { mua += red[0][k]; mub += red[1][k]; }
+        for (int k = 0; k < IT / 64; ++k) { mua += red[0][k]; mub += red[1][k]; }
         mua *= inv_wsum;
         mub *= inv_wsum;
         if (tid == 0) {
@@ -157,7 +165,7 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
         // transform was read before the loop's last barrier)
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
+            const int q = j * IT + tid, y = (4 * q) / N, x = (4 * q) % N;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
             }
         }
         __syncthreads();
-        fft2d_lds<N, FT>(z, tw);
+        fft2d_lds_inline<N, IT>(z, tw);
         // the next pair's pixels, requested now (into the registers this
         // pair's pixels left), before this pair's record stores: loads and
         // stores share one counter, so the next pair then waits for its
@@ -188,26 +196,26 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
             Ib = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
         };
         // rows 0..N/2-1: the record rows and the power; row N/2: the power
-        static_assert(HALF * N % FT == 0 && SPEC_NEG_ROWS * N % FT == 0, "whole rows per pass");
+        static_assert(HALF * N % IT == 0 && SPEC_NEG_ROWS * N % IT == 0, "whole rows per pass");
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int j = k * FT + tid_o;
-            if (k * FT + tid < NP) {
+            const int j = k * IT + tid_o;
+            if (k * IT + tid < NP) {
                 const int uy = j / N, ux = j % N;
                 float2 Ia, Ib;
                 split(ux, uy, Ia, Ib);
                 ps[k] += Ia.x * Ia.x + Ia.y * Ia.y;
                 if (hasb) ps[k] += Ib.x * Ib.x + Ib.y * Ib.y;
-                if (k * FT < HALF * N) {
+                if (k * IT < HALF * N) {
                     const unsigned o = ((uy + SPEC_NEG_ROWS) * N + ux) * (unsigned)sizeof(float2);
                     store_global_f2(rec_b, o, Ib);
                     store_global_f2(rec_a, o, Ia);
                 }
-                if (k * FT + tid == 1) {   // u = (1, 0)
+                if (k * IT + tid == 1) {   // u = (1, 0)
                     kahan_add(m10s[0], m10c[0], Ia.x); kahan_add(m10s[1], m10c[1], Ia.y);
                     if (hasb) { kahan_add(m10s[0], m10c[0], Ib.x); kahan_add(m10s[1], m10c[1], Ib.y); }
                 }
-                if (k * FT + tid == N) {   // u = (0, 1)
+                if (k * IT + tid == N) {   // u = (0, 1)
                     kahan_add(m01s[0], m01c[0], Ia.x); kahan_add(m01s[1], m01c[1], Ia.y);
                     if (hasb) { kahan_add(m01s[0], m01c[0], Ib.x); kahan_add(m01s[1], m01c[1], Ib.y); }
                 }
@@ -215,8 +223,8 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
         }
         // the conjugate mirrors I(-u) = conj I(u) of rows 1..16 in rows -1..-16
 #pragma unroll
-        for (int k = 0; k < SPEC_NEG_ROWS * N / FT; ++k) {
-            const int j = k * FT + tid_o;
+        for (int k = 0; k < SPEC_NEG_ROWS * N / IT; ++k) {
+            const int j = k * IT + tid_o;
             const int uy = 1 + j / N, ux = j % N;
             float2 Ia, Ib;
             split(ux, uy, Ia, Ib);
@@ -230,12 +238,12 @@ __global__ __launch_bounds__(FT) void k_ingest(const BurstTable bt, int stride, 
     float *pp = ppart + (size_t)L * NP;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int j = k * FT + tid;
+        const int j = k * IT + tid;
         if (j < NP) pp[j] = ps[k];
     }
     float *mp = mpart + (size_t)L * 4;
-    if (tid == 1 % FT) { mp[0] = m10s[0] - m10c[0]; mp[1] = m10s[1] - m10c[1]; }
-    if (tid == N % FT) { mp[2] = m01s[0] - m01c[0]; mp[3] = m01s[1] - m01c[1]; }
+    if (tid == 1 % IT) { mp[0] = m10s[0] - m10c[0]; mp[1] = m10s[1] - m10c[1]; }
+    if (tid == N % IT) { mp[2] = m01s[0] - m01c[0]; mp[3] = m01s[1] - m01c[1]; }
     if (tid == 0) mupart[L] = mus - muc;
 }
 
@@ -322,11 +330,11 @@ __global__ __launch_bounds__(NT) void k_acc_stream(int nchunks, const float *__r
 template <int N, typename T>
 hipError_t launch_ingest_t(const IngestArgs &a, hipStream_t st) {
     if (a.vec)
-        hipLaunchKernelGGL((k_ingest<N, T, true>), dim3(a.bt.ingest_wgs), dim3(FT), 0, st, a.bt, a.stride,
+        hipLaunchKernelGGL((k_ingest<N, T, true>), dim3(a.bt.ingest_wgs), dim3(ingest_threads<T>()), 0, st, a.bt, a.stride,
                            a.chunk_frames, a.window, a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart,
                            a.mupart);
     else
-        hipLaunchKernelGGL((k_ingest<N, T, false>), dim3(a.bt.ingest_wgs), dim3(FT), 0, st, a.bt, a.stride,
+        hipLaunchKernelGGL((k_ingest<N, T, false>), dim3(a.bt.ingest_wgs), dim3(ingest_threads<T>()), 0, st, a.bt, a.stride,
                            a.chunk_frames, a.window, a.inv_wsum, a.twiddle, a.hann, a.spectra, a.ppart, a.mpart,
                            a.mupart);
     hipError_t e = hipGetLastError();

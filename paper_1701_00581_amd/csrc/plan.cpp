@@ -237,12 +237,12 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     // part of the |v| <= R disk on w's side of a line through the origin
     // normal to w, so w of similar direction share most of their v and the
     // union of their sets (the v slots the wave runs) is little larger
-    // than each set.  Groups: radial bands (8 wide up to 24, then about 10
+    // than each set.  Groups: radial bands (8 wide up to 16, then about 10
     // wide), each sorted by angle and cut into equal groups of <= 64.
     // Wider bands give narrower angles (fewer idle lanes) but larger staged
     // regions.
     std::vector<int> edges = {0};
-    for (int e = 8; e <= 24; e += 8)
+    for (int e = 8; e <= 16; e += 8)
         if (e < uc + 1) edges.push_back(e);
     {
         const int lo = edges.back(), parts = std::max(1, (int)std::lround((uc + 1 - lo) / 10.0));
