@@ -106,7 +106,7 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(15 | (7 
 // past a chunk's real v hold a valid v of the item; their results are
 // dropped.  The frame's slot loop is one branch-free block, so its LDS reads
 // can be issued ahead.
-template <int N, int K, int NS, int MODE>
+template <int N, int K, int NS, int MODE, int PERW>
 __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const float2 *__restrict__ spec,
                                             int64_t rec0, int F, int patch, int g, const int *__restrict__ it,
                                             const int *__restrict__ group_xy, const int *__restrict__ slot,
@@ -115,7 +115,6 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     constexpr int HALF = N / 2;
     constexpr int FS = SpecRows<N>::FS;
     constexpr int FB = FS * (int)sizeof(float2);               // bytes per stored frame
-    constexpr int PERW = Region<K>::PERW;
     const int *gxy = group_xy + it[0] * (2 * BS_LANES);
     const int rx0 = it[1], ry0 = it[2], npts = it[5], pitch = it[6];
     const int tid = threadIdx.x;
@@ -141,6 +140,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     // byte offset in the frame's record: region points beyond the stored
     // rows are never used by a sample and read a clamped row; pairs past
     // the region read offset 0 into the unused tail of the LDS record.
+    // PERW is the fewest chunks per wave that hold the item's region.
     // Every wave issues all PERW loads, so that their number is known when
     // the compiler places the waits for the loads issued before them.
     unsigned src[PERW];
@@ -292,10 +292,16 @@ __device__ __forceinline__ void bispec_dispatch(int nq, float2 *lds0, float2 *ld
                                                 const int *slot, const int *out_idx, float2 *bispec,
                                                 int64_t s_count, const AccState &acc) {
     if constexpr (Q > 0) {
-        if (nq == Q)
-            bispec_item<N, K, 4 * Q, MODE>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec, s_count,
-                                     acc);
-        else
+        if (nq == Q) {
+            // regions of up to half the capacity (most items) move half the chunks
+            constexpr int PW = Region<K>::PERW, PH = PW > 1 ? PW / 2 : 1;
+            if (it[5] <= 128 * BS_WAVES * PH)
+                bispec_item<N, K, 4 * Q, MODE, PH>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx,
+                                                 bispec, s_count, acc);
+            else
+                bispec_item<N, K, 4 * Q, MODE, PW>(lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx,
+                                                 bispec, s_count, acc);
+        } else
             bispec_dispatch<N, K, Q - 1, MODE>(nq, lds0, lds1, spec, rec0, F, patch, g, it, group_xy, slot, out_idx, bispec,
                                          s_count, acc);
     }
