@@ -210,10 +210,14 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         const int fn = min(f + 1, F - 1);
         fetch(fn, nxt);
         const char *rb = (const char *)rg;
-        // p = I(w - v) I(v);  t += p conj I(w)
+        // p = I(w - v) I(v);  t += p conj I(w).  The gather of slot k + 1 is
+        // requested before slot k is computed, so that its LDS latency runs
+        // under slot k's arithmetic.
+        float2 an = *(const float2 *)(rb + addr[0]);
         auto slot_k = [&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value, q = k / 16, r = k % 16;
-            const float2 a = *(const float2 *)(rb + addr[k]);
+            const float2 a = an;
+            if constexpr (k + 1 < NS) an = *(const float2 *)(rb + addr[k + 1]);
             const float pr = fmac_bc<r>(mul_bc_neg<r>(bv[q].y, a.y), bv[q].x, a.x);
             const float pi = fmac_bc<r>(mul_bc<r>(bv[q].x, a.y), bv[q].y, a.x);
             t[k].x = fmaf(pr, cw.x, fmaf(pi, cw.y, t[k].x));
