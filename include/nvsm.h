@@ -149,8 +149,8 @@ nvsm_status nvsm_prepare(nvsm_context *ctx, const nvsm_params *p);
  * terms in expectation wherever the taper's transform vanishes at w, v and
  * w - v (for the Hann taper: each has a component of modulus >= 2; with no
  * taper: all of them), in the manner of the photon-counting corrections of
- * speckle interferometry and speckle masking.  The streaming calls reject
- * noise_bias 2 (NVSM_ERR_NOT_IMPLEMENTED). */
+ * speckle interferometry and speckle masking.  The streaming calls carry
+ * these terms too (their sums run over the groups like the others'). */
 nvsm_status nvsm_accumulate(nvsm_context *ctx, const nvsm_params *p,
                             const void *frames, nvsm_dtype dtype, int32_t F,
                             int32_t H, int32_t W, int64_t row_pitch,
@@ -263,7 +263,8 @@ nvsm_status nvsm_reconstruct_batch(nvsm_context *ctx, const nvsm_params *p, nvsm
  *   state (one per burst in flight): the running compensated (Kahan)
  *     sums, (sum, compensation) pairs, of the bispectrum terms, kept in the
  *     kernel's own order so that every pass over them is coalesced, and of
- *     the power spectrum, mean spectrum and mean level;
+ *     the power spectrum, mean spectrum and mean level (with noise_bias 2
+ *     also those of the photon-noise terms C, q0 and T);
  *   ws (one per stream of calls): scratch for one group of frames and the
  *     final buffers.  After the last group its first P * |S| * 8 bytes
  *     hold the bispectrum means, float [P][|S|][2] in S order, as
@@ -278,7 +279,8 @@ nvsm_status nvsm_reconstruct_batch(nvsm_context *ctx, const nvsm_params *p, nvsm
  *     and the call writes the means over all frames into ws.  Within a
  *     group frames are summed in blocks as usual; each group's sums are
  *     folded into the running pairs.  One group of all F frames gives
- *     exactly nvsm_accumulate's values.
+ *     exactly nvsm_accumulate's values (noise_bias 2: the last group
+ *     subtracts the photon-noise terms' means over all frames).
  *   nvsm_stream_finish: modulus, phase, subimages and mosaic (as
  *     nvsm_solve + nvsm_synthesize) from ws after the last group, into out
  *     [H][W].

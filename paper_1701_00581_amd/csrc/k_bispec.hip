@@ -259,7 +259,10 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     const int *oi = out_idx + (size_t)(g * BS_WAVES + wave) * K * 64 + lane_e;
     float2 *bo = bispec + (size_t)patch * s_count;
     const float inv = MODE == 1 ? acc.inv_total : 1.0f / (float)F;
-    if constexpr (MODE == 2) {
+    // (the streaming form's last group carries the photon-noise terms too)
+    if (MODE == 2 || (MODE == 1 && acc.noise_c != nullptr)) {
+        // (no fused multiply-adds here: both forms round these steps alike)
+#pragma clang fp contract(off)
         // photon-noise terms: B -= C(w) + conj C(v) + conj C(w - v) - 2T,
         // C of the patch in the record layout of the spectra (the slot
         // table gives v's record index; w - v lies within the record's rows)
@@ -450,7 +453,9 @@ hipError_t launch_bispec(const BispecArgs &a, hipStream_t st) {
     if (total64 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const int total = (int)total64;
     if (a.acc.mode < 0 || a.acc.mode > 2) return hipErrorInvalidValue;
-    if (a.acc.mode != 0 && a.acc.noise_c) return hipErrorInvalidValue;   // no photon terms when streaming
+    // photon-noise terms in the streaming form: the last group only
+    if (a.acc.mode == 1 && a.acc.noise_c) return hipErrorInvalidValue;
+    if (a.acc.noise_c && !a.acc.noise_t) return hipErrorInvalidValue;
     if (a.acc.mode != 0) {
         if (a.slots == 16) return a.N == 128 ? launch_bispec_t<128, 16, 1>(a, total, st) : launch_bispec_t<64, 16, 1>(a, total, st);
         if (a.slots == 24) return a.N == 128 ? launch_bispec_t<128, 24, 1>(a, total, st) : launch_bispec_t<64, 24, 1>(a, total, st);

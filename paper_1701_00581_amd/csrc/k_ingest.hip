@@ -527,6 +527,78 @@ __global__ __launch_bounds__(NT) void k_noise_finalize(const BurstTable bt, int 
     for (int j = threadIdx.x; j < N * N; j += NT) pw[j] -= q0;
 }
 
+// The streaming form of k_noise_finalize: one workgroup per patch adds the
+// group's sums (its frame chunks in order, compensated) to the running
+// pairs; the last group writes the means as k_noise_finalize does.  With
+// one group holding every frame the means are those of k_noise_finalize bit
+// for bit.
+template <int N>
+__global__ __launch_bounds__(NT) void k_noise_stream(const BurstTable bt, int chunk_frames,
+                                                     const float2 *__restrict__ cpart,
+                                                     const float *__restrict__ spart, int mode, int first,
+                                                     float inv_total, float4 *__restrict__ csc,
+                                                     float *__restrict__ ssc, float *__restrict__ power,
+                                                     float2 *__restrict__ cgrid, float *__restrict__ nbar) {
+    constexpr int HALF = N / 2, NP = (HALF + 1) * N;
+    constexpr int FS = SpecRows<N>::FS;
+    const int patch = blockIdx.x;
+    const BurstDesc &bd = bt.b[0];
+    const int nchunks = (bd.F + chunk_frames - 1) / chunk_frames;
+    const size_t wg0 = (size_t)bd.ingest0 + (size_t)patch * nchunks;
+    // every thread forms the same two sums in the same order
+    float q0 = 0.f, q0c = 0.f, t3 = 0.f, t3c = 0.f;
+    float *sp = ssc + (size_t)patch * 4;
+    if (!first) {
+        q0 = sp[0]; t3 = sp[1]; q0c = sp[2]; t3c = sp[3];
+    }
+    for (int k = 0; k < nchunks; ++k) {
+        kahan_add(q0, q0c, spart[(wg0 + k) * 2]);
+        kahan_add(t3, t3c, spart[(wg0 + k) * 2 + 1]);
+    }
+    __syncthreads();                              // every thread has read the running pair
+    if (mode == 1) {
+        if (threadIdx.x == 0) {
+            sp[0] = q0; sp[1] = t3; sp[2] = q0c; sp[3] = t3c;
+        }
+    } else {
+        q0 = (q0 - q0c) * inv_total;
+        t3 = (t3 - t3c) * inv_total;
+        if (threadIdx.x == 0) {
+            nbar[(size_t)patch * 2] = q0;
+            nbar[(size_t)patch * 2 + 1] = t3;
+        }
+    }
+    const float2 *cp = cpart + wg0 * NP;
+    float4 *cs = csc + (size_t)patch * NP;
+    float2 *cg = cgrid + (size_t)patch * FS;
+    for (int j = threadIdx.x; j < NP; j += NT) {
+        float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f;
+        if (!first) {
+            const float4 r = cs[j];
+            sx = r.x; sy = r.y; cx = r.z; cy = r.w;
+        }
+        for (int k = 0; k < nchunks; ++k) {
+            const float2 v = cp[(size_t)k * NP + j];
+            kahan_add(sx, cx, v.x);
+            kahan_add(sy, cy, v.y);
+        }
+        if (mode == 1) {
+            cs[j] = make_float4(sx, sy, cx, cy);
+            continue;
+        }
+        // means at their record place (rows 0 .. N/2 - 1), and the conjugate
+        // mirrors of rows 1 .. SPEC_NEG_ROWS in rows -1 .. -SPEC_NEG_ROWS
+        const int y = j / N, x = j % N;
+        const float mx = (sx - cx) * inv_total, my = (sy - cy) * inv_total;
+        if (y < HALF) cg[(y + SPEC_NEG_ROWS) * N + x] = make_float2(mx, my);
+        if (y >= 1 && y <= SPEC_NEG_ROWS) cg[(SPEC_NEG_ROWS - y) * N + ((N - x) & (N - 1))] = make_float2(mx, -my);
+    }
+    if (mode == 2) {
+        float *pw = power + (size_t)patch * N * N;
+        for (int j = threadIdx.x; j < N * N; j += NT) pw[j] -= q0;
+    }
+}
+
 template <int N, typename T>
 hipError_t launch_noise_t(const NoiseArgs &na, hipStream_t st) {
     const IngestArgs &a = na.in;
@@ -540,8 +612,13 @@ hipError_t launch_noise_t(const NoiseArgs &na, hipStream_t st) {
                            na.spart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_noise_finalize<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames, na.cpart,
-                       na.spart, a.power, na.cgrid, na.nbar);
+    if (a.stream_mode == 0)
+        hipLaunchKernelGGL((k_noise_finalize<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames, na.cpart,
+                           na.spart, a.power, na.cgrid, na.nbar);
+    else
+        hipLaunchKernelGGL((k_noise_stream<N>), dim3(a.bt.patches), dim3(NT), 0, st, a.bt, a.chunk_frames, na.cpart,
+                           na.spart, a.stream_mode, a.stream_first, a.inv_total, na.csc, na.ssc, a.power, na.cgrid,
+                           na.nbar);
     return hipGetLastError();
 }
 

@@ -67,6 +67,11 @@ struct NoiseArgs {
     float *spart = nullptr;               // [ingest wgs][2] sums of q0 and T
     float2 *cgrid = nullptr;              // [P][N/2 + 16][N] mean C, record layout
     float *nbar = nullptr;                // [P][2] mean q0 and T
+    // streaming (in.stream_mode 1 or 2, one burst): the group's sums go into
+    // running (sum, compensation) pairs, from zero when in.stream_first; the
+    // last group (mode 2) writes the means over in.inv_total frames
+    float4 *csc = nullptr;                // [P][N/2 + 1][N] C: (sum re, sum im, comp re, comp im)
+    float *ssc = nullptr;                 // [P][4] q0 and T: (sum, sum, comp, comp)
 };
 hipError_t launch_noise(const NoiseArgs &a, hipStream_t st);
 
@@ -123,9 +128,9 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 // kernel's lane order (coalesced), starting from zero when first.  mode 2:
 // as 1 for the last group, then writes the mean, (sum - comp) * inv_total,
 // to the bispectrum array in S order.
-// noise_c/noise_t (mode 0 only): photon-noise terms to subtract from the
-// mean, C per patch in the record layout of the spectra ([P][N/2 + 16][N])
-// and (q0, T) per patch (see NoiseArgs).
+// noise_c/noise_t (mode 0, or mode 2 of the streaming form): photon-noise
+// terms to subtract from the mean, C per patch in the record layout of the
+// spectra ([P][N/2 + 16][N]) and (q0, T) per patch (see NoiseArgs).
 struct AccState {
     float2 *sum = nullptr, *comp = nullptr;   // [P * n_items * 4 * slots * 64]
     int mode = 0, first = 0, n_items = 0;

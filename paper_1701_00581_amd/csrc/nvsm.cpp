@@ -202,19 +202,23 @@ constexpr int STREAM_SLOTS = 16;
 // bispectrum in S order first), the solve and synthesis buffers, then the
 // scratch for one group of frames.
 struct StreamSizes {
-    size_t acc_s = 0, acc_c = 0, psc = 0, msc = 0, musc = 0;            // state
+    size_t acc_s = 0, acc_c = 0, psc = 0, msc = 0, musc = 0, csc = 0, ssc = 0;   // state
     size_t bis = 0, power = 0, mean = 0, mu = 0, amp = 0, phasor = 0, patches = 0, group = 0;   // workspace
-    size_t state() const { return acc_s + acc_c + psc + msc + musc; }
+    size_t state() const { return acc_s + acc_c + psc + msc + musc + csc + ssc; }
     size_t ws() const { return bis + power + mean + mu + amp + phasor + patches + group; }
 };
 
-void stream_sizes(int N, int64_t P, int64_t nW, int64_t S, int64_t lane_terms, size_t group, StreamSizes *z) {
+// noise: the state also carries the photon-noise sums (noise_bias 2)
+void stream_sizes(int N, int64_t P, int64_t nW, int64_t S, int64_t lane_terms, size_t group, StreamSizes *z,
+                  bool noise = false) {
     const int64_t NP = (N / 2 + 1) * N;
     z->acc_s = align_up((size_t)P * lane_terms * 8);
     z->acc_c = align_up((size_t)P * lane_terms * 8);
     z->psc = align_up((size_t)P * NP * 8);
     z->msc = align_up((size_t)P * 4 * 8);
     z->musc = align_up((size_t)P * 8);
+    z->csc = noise ? align_up((size_t)P * NP * 16) : 0;       // C: (sum, compensation) of re and im
+    z->ssc = noise ? align_up((size_t)P * 4 * 4) : 0;         // q0 and T: (sum, compensation)
     z->bis = align_up((size_t)P * S * 8);
     z->power = align_up((size_t)P * N * N * 4);
     z->mean = align_up((size_t)P * 4 * 4);
@@ -227,6 +231,8 @@ void stream_sizes(int N, int64_t P, int64_t nW, int64_t S, int64_t lane_terms, s
 
 struct StreamView {
     float2 *acc_s, *acc_c, *psc, *msc, *musc;            // state
+    float4 *csc;                                          // photon-noise sums (noise_bias 2)
+    float *ssc;
     float2 *bis;                                          // workspace
     float *power, *mean, *mu;
     double *amp, *phasor;
@@ -241,7 +247,9 @@ StreamView stream_view(char *st, char *ws, const StreamSizes &z) {
         v.acc_c = (float2 *)st; st += z.acc_c;
         v.psc = (float2 *)st; st += z.psc;
         v.msc = (float2 *)st; st += z.msc;
-        v.musc = (float2 *)st;
+        v.musc = (float2 *)st; st += z.musc;
+        v.csc = z.csc ? (float4 *)st : nullptr; st += z.csc;
+        v.ssc = z.ssc ? (float *)st : nullptr;
     }
     v.bis = (float2 *)ws; ws += z.bis;
     v.power = (float *)ws; ws += z.power;
@@ -1077,7 +1085,6 @@ nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t
     if (!state_bytes || !ws_bytes) return NVSM_ERR_INVALID_ARG;
     nvsm_status s = check_params(p, &msg);
     if (s != NVSM_OK) return s;
-    if (p->noise_bias == 2) return NVSM_ERR_NOT_IMPLEMENTED;
     if ((s = check_shape(p, H, W, group_frames, &msg)) != NVSM_OK) return s;
     HostPlan h;
     try {
@@ -1094,7 +1101,8 @@ nvsm_status nvsm_stream_plan(const nvsm_params *p, int32_t H, int32_t W, int32_t
     Sizes z;
     sizes_for(p->patch, bt, rec, (int64_t)h.W.size() / 2, h.s_count, &z, p->noise_bias == 2);
     StreamSizes ss;
-    stream_sizes(p->patch, bt.patches, (int64_t)h.W.size() / 2, h.s_count, lane_terms, ws_acc(z), &ss);
+    stream_sizes(p->patch, bt.patches, (int64_t)h.W.size() / 2, h.s_count, lane_terms, ws_acc(z), &ss,
+                 p->noise_bias == 2);
     *state_bytes = ss.state();
     *ws_bytes = ss.ws();
     return NVSM_OK;
@@ -1105,8 +1113,6 @@ static nvsm_status stream_prep(nvsm_context *ctx, const nvsm_params *p, int32_t 
     std::string msg;
     nvsm_status s = check_params(p, &msg);
     if (s != NVSM_OK) return fail(ctx, s, msg);
-    if (p->noise_bias == 2)
-        return fail(ctx, NVSM_ERR_NOT_IMPLEMENTED, "the streaming calls do not carry the photon-noise terms");
     if ((s = check_shape(p, H, W, G, &msg)) != NVSM_OK) return fail(ctx, s, msg);
     if ((s = get_plan(ctx, p, STREAM_SLOTS, dp)) != NVSM_OK) return s;
     BurstIn bi;
@@ -1116,7 +1122,7 @@ static nvsm_status stream_prep(nvsm_context *ctx, const nvsm_params *p, int32_t 
     sizes_for(p->patch, *bt, rec, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, z, p->noise_bias == 2);
     const int64_t lane_terms = (int64_t)(*dp)->h.n_items * BS_WAVES * (*dp)->h.slots * 64;
     stream_sizes(p->patch, bt->patches, (int64_t)((*dp)->h.W.size() / 2), (*dp)->h.s_count, lane_terms, ws_acc(*z),
-                 ss);
+                 ss, p->noise_bias == 2);
     return NVSM_OK;
 }
 
@@ -1167,9 +1173,24 @@ nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void 
     a.stream_mode = mode; a.stream_first = first;
     a.psc = v.psc; a.msc = v.msc; a.musc = v.musc; a.inv_total = inv_total;
     hipError_t e;
+    NoiseArgs na;
+    if (p->noise_bias == 2) {
+        // the group's photon-noise sums go into the state's running sums;
+        // the last group writes their means where the bispectrum launch
+        // reads them (the layout of the accumulate scratch)
+        char *q = gw + z.spectra + z.ppart + z.mpart + z.mupart;
+        na.in = a;
+        na.inv_gain = (float)(1.0 / p->photons_per_adu);
+        na.cpart = (float2 *)q; q += z.cpart;
+        na.spart = (float *)q; q += z.spart;
+        na.cgrid = (float2 *)q; q += z.cw;
+        na.nbar = (float *)q;
+        na.csc = v.csc; na.ssc = v.ssc;
+    }
     {
         StageTimer t(ctx, ST_INGEST, st);
         e = launch_ingest(a, st);
+        if (e == hipSuccess && p->noise_bias == 2) e = launch_noise(na, st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "stream ingest");
     BispecArgs b;
@@ -1180,6 +1201,10 @@ nvsm_status nvsm_stream_add(nvsm_context *ctx, const nvsm_params *p, const void 
     b.form = choice_of(ctx, p).second; b.queue = queue_of(gw, z);
     b.acc.sum = v.acc_s; b.acc.comp = v.acc_c; b.acc.mode = mode; b.acc.first = first;
     b.acc.n_items = dp->h.n_items; b.acc.inv_total = inv_total;
+    if (p->noise_bias == 2 && mode == 2) {
+        b.acc.noise_c = na.cgrid;
+        b.acc.noise_t = na.nbar;
+    }
     {
         StageTimer t(ctx, ST_BISPEC, st);
         e = launch_bispec(b, st);

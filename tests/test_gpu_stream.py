@@ -211,3 +211,58 @@ def test_persistent_form_on_two_streams(torch_cuda, setup):
             torch.cuda.synchronize()
     finally:
         nv.nvsm_destroy(ctx)
+
+
+def test_stream_photon_noise(torch_cuda, setup):
+    """noise_bias 2 in the streaming calls (a low photon level, so the terms
+    are large): one group gives nvsm_accumulate's corrected bispectrum and
+    nvsm_reconstruct's image bit for bit; five uneven groups stay within the
+    tolerances of the whole burst and of the oracle's corrected bispectrum."""
+    import dataclasses
+    import paper_1701_00581_amd as nv
+    import synth
+    torch = torch_cuda
+    photons = 40.0
+    say(f"case stream photon noise: burst1024 scene at {photons:.0f} photons/px, {H}x{W} F={F}, N=128, R=10")
+    cfg = dataclasses.replace(synth.CONFIGS["burst1024"], photons=photons, index=91)
+    fr = np.ascontiguousarray(synth.make_burst(cfg, frames=F)[:, :H, :W])
+    gain = photons / 2048.0
+    p = nv.default_params(128, v_radius=10, noise_bias=2, photons_per_adu=gain, filter=1)
+    d = to_device(fr)
+    info = nv.nvsm_plan(p, H, W, F)
+    ctx = setup["ctx"]
+    bis_ref = torch.empty((info.patches, info.s_count, 2), device="cuda")
+    nv.nvsm_accumulate(ctx, p, d, torch.empty((info.patches, 128, 128), device="cuda"),
+                       torch.empty((info.patches, 2, 2), device="cuda"), torch.empty(info.patches, device="cuda"),
+                       bis_ref, torch.empty(info.ws_accumulate, dtype=torch.uint8, device="cuda"))
+    img_ref = torch.empty((H, W), device="cuda")
+    nv.nvsm_reconstruct(ctx, p, d, setup["stf"], img_ref,
+                        torch.empty(info.ws_reconstruct, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    s = dict(setup, p=p, d=d, fr=fr)
+    img, bis = _stream(nv, torch, s, [F])
+    same_b = torch.equal(bis, bis_ref)
+    same_i = torch.equal(img, img_ref)
+    say(f"[stream photon] one group: bispectrum identical={same_b}, image identical={same_i}")
+    assert same_b and same_i
+    groups = [7, 7, 9, 6, 1]
+    img, bis = _stream(nv, torch, s, groups)
+    b = as_complex(bis)
+    br = as_complex(bis_ref)
+    rel = float(np.linalg.norm(b - br) / np.linalg.norm(br))
+    say(f"[stream photon] groups {groups}: bispectrum vs whole-burst {rel:.2e}")
+    assert rel < BISPEC_TOL and torch.isfinite(img).all()
+    op = oparams(p)
+    op0 = oparams(nv.default_params(128, v_radius=10, filter=1))
+    S = nv.nvsm_bispectrum_index(p)
+    for k in (0, info.patches - 1):
+        c = cube(fr, p, k)
+        acc = oracle.accumulate_patch(c, op, S)
+        raw = oracle.accumulate_patch(c, op0, S)
+        I, _ = oracle.patch_spectra(c, op.window)
+        A = abs_bispectrum(I, S)
+        nrm, mx = bispec_errors(b[k], acc["B"], A)
+        moved = float(np.max(np.abs(acc["B"] - raw["B"]) / A))
+        say(f"[stream photon] patch {k} vs oracle: B norm {nrm:.2e} B/A max {mx:.2e} (correction B/A up to {moved:.2e})")
+        assert nrm < BISPEC_TOL and mx < BISPEC_TOL
+        assert moved > 100 * BISPEC_TOL

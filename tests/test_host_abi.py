@@ -88,7 +88,7 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_OK
     p.lsq_iters = 0
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG
-    # photon-noise model: a positive finite gain; larger workspaces; not in the streaming calls
+    # photon-noise model: a positive finite gain; larger workspaces
     p = nv.default_params(128)
     assert p.photons_per_adu == 1.0
     assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_OK
@@ -99,10 +99,18 @@ def test_invalid_parameters_are_rejected_before_anything_runs():
     for bad in (0.0, -1.0, float("inf"), float("nan")):
         p.photons_per_adu = bad
         assert L.nvsm_plan(ctypes.byref(p), 1024, 1024, 100, ctypes.byref(info)) == _lib.NVSM_ERR_INVALID_ARG
+    # the streaming state then also holds the photon-noise sums: (sum,
+    # compensation) of C over the half plane, and of q0 and T, per patch
     p.photons_per_adu = 4.0
-    with pytest.raises(nv.NvsmError) as e:
-        nv.nvsm_stream_plan(p, 1024, 1024, 10)
-    assert e.value.status == _lib.NVSM_ERR_NOT_IMPLEMENTED
+    st2, ws2 = nv.nvsm_stream_plan(p, 1024, 1024, 10)
+    p.noise_bias = 0
+    st0, ws0 = nv.nvsm_stream_plan(p, 1024, 1024, 10)
+    P = info.patches
+
+    def up(n):
+        return (n + 255) // 256 * 256
+    assert st2 - st0 == up(P * 65 * 128 * 16) + up(P * 16)
+    assert ws2 > ws0
     # model STF workspace: partial sums of min(pairs, 256) workgroups over the half plane
     p = nv.default_params(128)
     assert nv.nvsm_model_stf_plan(p, 1000) == 256 * 65 * 128 * 12
