@@ -97,11 +97,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
         double acc = 0.0;
         int cnt = 0;
         const double lim = (N / 2 + 2.0) * (N / 2 + 2.0);
+        // (every value is loaded, so that the loads of the unrolled passes go
+        // out together; the sum runs in the same order)
+        static_assert(N * N % NT == 0, "whole passes");
+#pragma unroll 8
         for (int j = tid; j < N * N; j += NT) {
             int ux = j % N, uy = j / N;
             ux = ux >= N / 2 ? ux - N : ux;
             uy = uy >= N / 2 ? uy - N : uy;
-            if ((double)(ux * ux + uy * uy) > lim) { acc += (double)P[j]; ++cnt; }
+            const double pj = (double)P[j];
+            if ((double)(ux * ux + uy * uy) > lim) { acc += pj; ++cnt; }
         }
         acc = wave_sum_d(acc);
         double c = wave_sum_d((double)cnt);
@@ -116,16 +121,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
         for (int k = 0; k < NWAVE; ++k) ctot += red[k];
         nb = tot / ctot;
     }
-    // modulus, Eq. 1
+    // modulus, Eq. 1 (loads unconditional, so that unrolled passes overlap)
+#pragma unroll 4
     for (int i = tid; i < nW; i += NT) {
         const int wx = Wxy[2 * i], wy = Wxy[2 * i + 1];
         const int j = (wy & (N - 1)) * N + (wx & (N - 1));
         const double s = stf[j];
+        const double num = (double)P[j] - nb;
         double a = 0.0;
-        if (s >= floor_) {
-            const double num = (double)P[j] - nb;
-            a = sqrt((num > 0.0 ? num : 0.0) / s);
-        }
+        if (s >= floor_) a = sqrt((num > 0.0 ? num : 0.0) / s);
         amp[(size_t)patch * nW + i] = a;
     }
     // seeds (1,0) and (0,1) are W[0] and W[1], inner entries
@@ -281,8 +285,16 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, 
     const float2 *B = bispec + (size_t)patch * s_count;
     for (int i = tid; i < nW; i += LSQ_NT) e[i] = ph[i];
     // fixed-point scale from sum |Re B| + |Im B| (fixed summation order)
+    // (eight loads in flight per thread: clamped past the end, and weighted 0)
     double s1 = 0.0;
-    for (int64_t t = tid; t < s_count; t += LSQ_NT) s1 += fabs((double)B[t].x) + fabs((double)B[t].y);
+    for (int64_t t0 = tid; t0 < s_count; t0 += 8 * LSQ_NT) {
+        float2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = B[min(t0 + (int64_t)k * LSQ_NT, s_count - 1)];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (t0 + (int64_t)k * LSQ_NT < s_count) s1 += fabs((double)v[k].x) + fabs((double)v[k].y);
+    }
     s1 = wave_sum_d(s1);
     if (lane == 0) red[wave] = s1;
     __syncthreads();
@@ -321,11 +333,14 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, 
                 for (int tb = t0; tb < t1; tb += 64 * LSQ_UNROLL) {
                     unsigned cd[LSQ_UNROLL];
                     float2 bb[LSQ_UNROLL];
+                    // every lane loads (past the segment's end: its last sample
+                    // again, unused), so that the loads go out together and are
+                    // awaited once rather than one by one
 #pragma unroll
                     for (int k = 0; k < LSQ_UNROLL; ++k) {
-                        const int t = tb + 64 * k + lane;
-                        cd[k] = t < t1 ? code[t] : 0u;
-                        bb[k] = t < t1 ? B[t] : make_float2(0.f, 0.f);
+                        const int t = min(tb + 64 * k + lane, t1 - 1);
+                        cd[k] = code[t];
+                        bb[k] = B[t];
                     }
 #pragma unroll
                     for (int k = 0; k < LSQ_UNROLL; ++k) {
