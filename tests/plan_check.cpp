@@ -131,6 +131,28 @@ static long check_solve_units(const HostPlan &pl) {
         if ((flag != 0) != end) ++bad;
     }
     if (expect != nW) ++bad;
+    // the phasor window: every sample reads each side at the slot where that
+    // side's phasor was written (w_slot), and the ring entries live while a
+    // shell is solved (from the lowest one its samples read to its own last
+    // w) hold distinct slots, so none was overwritten in between
+    for (int sh = 1; sh < (int)pl.shell_wb.size() - 1; ++sh) {
+        int lo = pl.shell_wb[sh];
+        for (int w = pl.shell_wb[sh]; w < pl.shell_wb[sh + 1]; ++w)
+            for (int32_t t = pl.woff[w]; t < pl.woff[w + 1]; ++t) {
+                const uint32_t c = pl.phase_code[t], sc = pl.phase_slot_code[t];
+                const int x[2] = {(int)((c >> 16) & 0x7fffu), (int)(c & 0x7fffu)};
+                const int sl[2] = {(int)((sc >> 16) & 0x7fffu), (int)(sc & 0x7fffu)};
+                for (int k = 0; k < 2; ++k) {
+                    if (sl[k] != pl.w_slot[x[k]]) ++bad;
+                    if (x[k] >= pl.n_inner) lo = std::min(lo, x[k]);
+                }
+            }
+        std::vector<int> seen(pl.zero_slot, 0);
+        for (int x = 0; x < pl.n_inner; ++x) ++seen[pl.w_slot[x]];
+        for (int x = std::max(lo, pl.n_inner); x < pl.shell_wb[sh + 1]; ++x) ++seen[pl.w_slot[x]];
+        for (int v : seen)
+            if (v > 1) ++bad;
+    }
     // the padded code blocks: w's codes, then reads of the zero slot, which
     // lies past every phasor slot
     if (pl.zero_slot != pl.n_inner + pl.ring_size || pl.zero_slot > 0x7fff) ++bad;
