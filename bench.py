@@ -444,8 +444,8 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for traffic counters)")
     ap.add_argument("--batch-ws-gib", type=float, default=96.0, help="workspace cap of the batch16 workload")
-    ap.add_argument("--tune-tol", type=float, default=0.3,
-                    help="batch16: phase agreement (rad, power-weighted RMS) that sets each class's v radius")
+    ap.add_argument("--tune-tol", type=float, default=0.1,
+                    help="batch16: phase agreement (rad, RMS weighted by the power above the noise floor) that sets each class's v radius")
     ap.add_argument("--sim-seconds", type=float, default=600.0, help="serve3: simulated seconds of arrivals")
     ap.add_argument("--compress", type=float, default=20.0, help="serve3: simulated clock / wall clock")
     ap.add_argument("--group", type=int, default=10, help="serve3: frames per streaming group when the GPU is idle")

@@ -330,10 +330,12 @@ nvsm_status nvsm_set_launch(nvsm_context *ctx, const nvsm_params *p, int32_t slo
  * On the patches of the burst's central crop (at most 512 x 512 px) the
  * path runs at R = r_max and then at r_min, r_min + 1, ... (p otherwise),
  * and stops at the first R whose phases agree with those at r_max within
- * tol radians: the power-weighted RMS of the wrapped phase difference over
- * W and the crop's patches, sqrt(sum P dphi^2 / sum P), P(w) the mean power
- * spectrum of the frames (the frequencies the frames carry strongly count
- * most; the STF-divided modulus would weight the noise-dominated high
+ * tol radians: the weighted RMS of the wrapped phase difference over W and
+ * the crop's patches, sqrt(sum P dphi^2 / sum P), P(w) the mean power
+ * spectrum of the frames less its noise floor (the mean power where
+ * |u| > N/2 + 2, per patch), 0 where below it: the frequencies the frames
+ * carry strongly count most and those at the floor, whose phases are noise,
+ * not at all (the STF-divided modulus would weight the noise-dominated high
  * frequencies most).  *r_out receives that R (r_max when none is closer);
  * err (host double [r_max - r_min + 1], or NULL) the measure of every R
  * tried (0 at r_max, NaN where not run).  frames, stf as nvsm_reconstruct;

@@ -1029,12 +1029,29 @@ nvsm_status nvsm_tune_radius(nvsm_context *ctx, const nvsm_params *p, const void
         if (h == hipSuccess) h = hipStreamSynchronize(st);
         if (h != hipSuccess) return hip_fail(ctx, h, "radius tuning");
         if (wt) {
+            // weight: the mean power above the patch's noise floor (the mean
+            // power where |u| > N/2 + 2, the level noise_bias 1 removes), so
+            // that frequencies at the floor, whose phases carry no signal,
+            // do not count
             wt->resize((size_t)z.P * z.nW);
             const std::vector<int32_t> &Wl = dp->h.W;
-            for (int64_t k = 0; k < z.P; ++k)
-                for (int64_t i = 0; i < z.nW; ++i)
-                    (*wt)[k * z.nW + i] =
-                        pw[(size_t)k * N * N + (size_t)(Wl[2 * i + 1] & (N - 1)) * N + (Wl[2 * i] & (N - 1))];
+            const double lim = (N / 2 + 2.0) * (N / 2 + 2.0);
+            for (int64_t k = 0; k < z.P; ++k) {
+                const float *pk = pw.data() + (size_t)k * N * N;
+                double acc = 0.0;
+                int64_t cnt = 0;
+                for (int j = 0; j < N * N; ++j) {
+                    int ux = j % N, uy = j / N;
+                    ux = ux >= N / 2 ? ux - N : ux;
+                    uy = uy >= N / 2 ? uy - N : uy;
+                    if ((double)(ux * ux + uy * uy) > lim) { acc += pk[j]; ++cnt; }
+                }
+                const double floor_k = cnt ? acc / (double)cnt : 0.0;
+                for (int64_t i = 0; i < z.nW; ++i) {
+                    const double pwi = pk[(size_t)(Wl[2 * i + 1] & (N - 1)) * N + (Wl[2 * i] & (N - 1))];
+                    (*wt)[k * z.nW + i] = std::max(pwi - floor_k, 0.0);
+                }
+            }
         }
         return NVSM_OK;
     };
