@@ -27,7 +27,7 @@ namespace nvsm {
 namespace {
 
 constexpr int NT = BS_WAVES * 64;
-constexpr int KB = 25;                     // frames per compensated block
+constexpr int KB = 50;                     // frames per compensated block
 
 // LDS record of one frame: the item's region of I (w - v values, row pitch =
 // region width), moved in chunks of 128 complex values (one wave-wide
