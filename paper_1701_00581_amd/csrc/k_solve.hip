@@ -28,10 +28,12 @@ namespace {
 
 constexpr int NT = 512;
 constexpr int NWAVE = NT / 64;
-// units of samples in registers (DEPTH - 1 loading): as many as keep the
-// kernel at its occupancy (80 VGPRs at 6 waves per SIMD with 4 samples per
-// lane, 128 at 4 with 8)
-template <int TPL> constexpr int depth_of() { return TPL <= 4 ? 5 : 3; }
+// units of samples in registers (DEPTH - 1 loading).  Two units ahead
+// cover the memory latency (a unit takes about 1.7 us); with 4 samples per
+// lane the registers a deeper ring would hold go to the unit's phasor
+// gathers, which are all issued before its arithmetic (80 VGPRs at 6 waves
+// per SIMD; 128 at 4 with 8 samples per lane)
+template <int TPL> constexpr int depth_of() { return TPL <= 2 ? 5 : 3; }
 static_assert(NWAVE == SOLVE_WAVES, "one w per wave and unit");
 
 __device__ __forceinline__ double2 unit_or_one(double2 z) {
@@ -186,11 +188,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TPL <= 4 ? 6
     auto solve = [&](const UnitRegs<TPL> &r) __attribute__((always_inline)) {
         if (r.w < 0) return;                      // no w of this unit in this wave
         double zx = 0.0, zy = 0.0;
+        // every gather of the unit first, so that their LDS latency is paid
+        // once (the scheduler otherwise waited for each sample's pair in turn)
+        double2 ga[TPL], gb[TPL];
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            ga[i] = e[(r.code[i] >> 16) & 0x7fffu];
+            gb[i] = e[r.code[i] & 0x7fffu];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
             const unsigned cd = r.code[i];
-            double2 ea = e[(cd >> 16) & 0x7fffu];
-            double2 eb = e[cd & 0x7fffu];
+            double2 ea = ga[i];
+            double2 eb = gb[i];
             // conjugation: the flag bit moved onto the sign of the imaginary part
             ea.y = __longlong_as_double(__double_as_longlong(ea.y) ^ ((long long)(cd & 0x80000000u) << 32));
             eb.y = __longlong_as_double(__double_as_longlong(eb.y) ^ ((long long)((cd << 16) & 0x80000000u) << 32));
