@@ -57,6 +57,13 @@ template <typename T> struct Quad<T, false> {
     __device__ float operator[](int i) const { return e[i]; }
 };
 
+// Storage position of frequency k after the transform (as fft_pos), in
+// unsigned arithmetic for indices the optimizer cannot bound.
+template <int N>
+__device__ __forceinline__ unsigned fft_pos_u(unsigned k) {
+    return FftGeom<N>::R1 * (k % FftGeom<N>::R2) + k / FftGeom<N>::R2;
+}
+
 // Threads of an ingest workgroup: 16 waves (4 per SIMD, 128 registers per
 // lane) for 16-bit pixels, 8 for 32-bit pixels, whose registers would not
 // fit 128.  The transform is inlined into the kernel (as a call it kept
@@ -116,13 +123,17 @@ __global__ __launch_bounds__(ingest_threads<T>()) void k_ingest(const BurstTable
         const gptr_c pa = uniform_ptr(frames + (size_t)fa * H * pitch + (size_t)y0 * pitch + x0);
         const gptr_c pb = uniform_ptr(frames + (size_t)fb * H * pitch + (size_t)y0 * pitch + x0);
         // the thread index, opaque to the optimizer: the offsets are formed
-        // here rather than kept (spilled) across the loop
-        int tid_l;
+        // here rather than kept (spilled) across the loop.  Quad j of a
+        // thread lies 4 IT / N rows below its quad 0, in the same columns, so
+        // one per-lane offset and a uniform step give them all (unsigned:
+        // the offsets are 32-bit by the host's checks).
+        unsigned tid_l;
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid_l) : "v"(tid));
+        static_assert(4 * IT % N == 0, "whole rows between the quads of a thread");
+        const unsigned off0 = ((4u * tid_l) / N * (unsigned)pitch + (4u * tid_l) % N) * (unsigned)sizeof(T);
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int q = j * IT + tid_l, y = (4 * q) / N, x = (4 * q) % N;
-            const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(T);
+            const unsigned off = off0 + (unsigned)(j * (4 * IT / N)) * (unsigned)pitch * (unsigned)sizeof(T);
             qa[j].load(pa, off);
             qb[j].load(pb, off);
         }
@@ -186,12 +197,12 @@ __global__ __launch_bounds__(ingest_threads<T>()) void k_ingest(const BurstTable
         // records of the two frames: wave-uniform bases, 32-bit lane offsets
         const gptr_m rec_a = uniform_ptr_m(spectra + spec_patch + (size_t)fa * FS);
         const gptr_m rec_b = uniform_ptr_m(spectra + spec_patch + (size_t)(hasb ? fb : fa) * FS);
-        int tid_o;                   // opaque thread index (addresses formed here)
+        unsigned tid_o;              // opaque thread index (addresses formed here, unsigned)
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid_o) : "v"(tid));
         // I_a and I_b of frequency (ux, uy) from the transform of z = a + i b
-        auto split = [&](int ux, int uy, float2 &Ia, float2 &Ib) __attribute__((always_inline)) {
-            const float2 Z = z[fft_pos<N>(uy) * P + fft_pos<N>(ux)];
-            const float2 Zm = z[fft_pos<N>((N - uy) & (N - 1)) * P + fft_pos<N>((N - ux) & (N - 1))];
+        auto split = [&](unsigned ux, unsigned uy, float2 &Ia, float2 &Ib) __attribute__((always_inline)) {
+            const float2 Z = z[fft_pos_u<N>(uy) * P + fft_pos_u<N>(ux)];
+            const float2 Zm = z[fft_pos_u<N>((N - uy) & (N - 1)) * P + fft_pos_u<N>((N - ux) & (N - 1))];
             Ia = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
             Ib = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
         };
@@ -199,9 +210,9 @@ __global__ __launch_bounds__(ingest_threads<T>()) void k_ingest(const BurstTable
         static_assert(HALF * N % IT == 0 && SPEC_NEG_ROWS * N % IT == 0, "whole rows per pass");
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int j = k * IT + tid_o;
+            const unsigned j = k * IT + tid_o;
             if (k * IT + tid < NP) {
-                const int uy = j / N, ux = j % N;
+                const unsigned uy = j / N, ux = j % N;
                 float2 Ia, Ib;
                 split(ux, uy, Ia, Ib);
                 ps[k] += Ia.x * Ia.x + Ia.y * Ia.y;
@@ -224,8 +235,8 @@ __global__ __launch_bounds__(ingest_threads<T>()) void k_ingest(const BurstTable
         // the conjugate mirrors I(-u) = conj I(u) of rows 1..16 in rows -1..-16
 #pragma unroll
         for (int k = 0; k < SPEC_NEG_ROWS * N / IT; ++k) {
-            const int j = k * IT + tid_o;
-            const int uy = 1 + j / N, ux = j % N;
+            const unsigned j = k * IT + tid_o;
+            const unsigned uy = 1 + j / N, ux = j % N;
             float2 Ia, Ib;
             split(ux, uy, Ia, Ib);
             const unsigned om = ((SPEC_NEG_ROWS - uy) * N + ((N - ux) & (N - 1))) * (unsigned)sizeof(float2);
