@@ -420,16 +420,28 @@ __global__ __launch_bounds__(FT) void k_noise(const BurstTable bt, int stride, i
 #pragma unroll
     for (int i = 0; i < NPT; ++i) cs[i] = make_float2(0.f, 0.f);
     float q0s = 0.f, q0c = 0.f, ts = 0.f, tc = 0.f;
+    // the pixels of a frame stay in registers until tapered; the next
+    // frame's are requested once the tile is written, so that they arrive
+    // during the transform (wave-uniform frame base, 32-bit lane offsets)
+    Quad<T, VEC> v[QPT];
+    auto load_frame = [&](int f) __attribute__((always_inline)) {
+        const gptr_c pf = uniform_ptr(frames + (size_t)f * H * pitch + (size_t)y0 * pitch + x0);
+        unsigned tid_l;                // opaque: the offsets are formed here, not kept
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid_l) : "v"(tid));
+        static_assert(4 * FT % N == 0, "whole rows between the quads of a thread");
+        const unsigned off0 = ((4u * tid_l) / N * (unsigned)pitch + (4u * tid_l) % N) * (unsigned)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < QPT; ++j)
+            v[j].load(pf, off0 + (unsigned)(j * (4 * FT / N)) * (unsigned)pitch * (unsigned)sizeof(T));
+    };
     __syncthreads();
 
+    load_frame(f0);
     for (int f = f0; f < f1; ++f) {
-        const T *pf = frames + (size_t)f * H * pitch + (size_t)y0 * pitch + x0;
         float s1 = 0.f, c1 = 0.f, s2 = 0.f, s3 = 0.f;
-        Quad<T, VEC> v[QPT];           // the pixels stay in registers until tapered
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
             const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
-            v[j].load(pf + (size_t)y * pitch + x);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float w = hw[y] * hw[x + e];
@@ -461,7 +473,8 @@ __global__ __launch_bounds__(FT) void k_noise(const BurstTable bt, int stride, i
             }
         }
         __syncthreads();
-        fft2d_lds<N, FT>(z, tw);
+        load_frame(min(f + 1, f1 - 1));   // (past the group's end: the last frame again, unused)
+        fft2d_lds_inline<N, FT>(z, tw);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int j = k * FT + tid;
