@@ -14,10 +14,10 @@
 // (computed on the host), so a lookup is a plain LDS read.  Each phasor is
 // written to the output as soon as it is known.  The samples of the next
 // DEPTH - 1 units are loaded into registers while the current unit is
-// computed: a unit's own work is far shorter than a load from HBM, so with
-// a single unit in flight the chain of shells waited on memory latency
-// (one w per wave and unit keeps a register set small enough for three in
-// flight at six waves per SIMD).
+// computed: a unit's own work is shorter than a load from HBM, so with a
+// single unit in flight the chain of shells waited on memory latency (one w
+// per wave and unit keeps a register set small enough for several in flight
+// at six waves per SIMD).
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
