@@ -16,8 +16,7 @@ namespace {
 
 constexpr int NT = 256;
 // The transform kernels hold one workgroup per CU (the tile fills most of
-// LDS), so they run at least 8 waves to hide latency (the ingest of 16-bit
-// pixels 16, see ingest_threads).
+// LDS), so they run 8 waves to hide latency.
 constexpr int FT = 512;
 
 // Four consecutive pixels of a row, loaded as one vector when the layout
@@ -64,11 +63,12 @@ __device__ __forceinline__ unsigned fft_pos_u(unsigned k) {
     return FftGeom<N>::R1 * (k % FftGeom<N>::R2) + k / FftGeom<N>::R2;
 }
 
-// Threads of an ingest workgroup: 16 waves (4 per SIMD, 128 registers per
-// lane) for 16-bit pixels, 8 for 32-bit pixels, whose registers would not
-// fit 128.  The transform is inlined into the kernel (as a call it kept
-// registers of its own and made the kernel wait at the call).
-template <typename T> constexpr int ingest_threads() { return sizeof(T) <= 2 ? 1024 : 512; }
+// Threads of an ingest workgroup: 8 waves (2 per SIMD), whose registers
+// hold the next frame pair's pixels through the transform (16 waves at 128
+// registers per lane could not).  The transform is inlined into the kernel
+// (as a call it kept registers of its own and waited for every load in
+// flight at its entry).
+template <typename T> constexpr int ingest_threads() { return 512; }
 
 template <int N, typename T, bool VEC>
 __global__ __launch_bounds__(ingest_threads<T>()) void k_ingest(const BurstTable bt, int stride, int chunk_frames, int window,
@@ -185,15 +185,16 @@ __global__ __launch_bounds__(ingest_threads<T>()) void k_ingest(const BurstTable
             }
         }
         __syncthreads();
-        fft2d_lds_inline<N, IT>(z, tw);
         // the next pair's pixels, requested now (into the registers this
-        // pair's pixels left), before this pair's record stores: loads and
-        // stores share one counter, so the next pair then waits for its
-        // pixels only.  Every pass issues the same loads and stores (past the
-        // group's end the last frame is loaded again, unused; a missing
-        // second frame's stores go to the first frame's record, ahead of the
-        // first frame's own), so the compiler knows how many are in flight.
+        // pair's pixels left), so that they arrive during the transform, and
+        // before this pair's record stores: loads and stores share one
+        // counter, so the next pair then waits for its pixels only.  Every
+        // pass issues the same loads and stores (past the group's end the
+        // last frame is loaded again, unused; a missing second frame's stores
+        // go to the first frame's record, ahead of the first frame's own), so
+        // the compiler knows how many are in flight.
         load_pair(min(fa + 2, f1 - 1));
+        fft2d_lds_inline<N, IT>(z, tw);
         // records of the two frames: wave-uniform bases, 32-bit lane offsets
         const gptr_m rec_a = uniform_ptr_m(spectra + spec_patch + (size_t)fa * FS);
         const gptr_m rec_b = uniform_ptr_m(spectra + spec_patch + (size_t)(hasb ? fb : fa) * FS);
