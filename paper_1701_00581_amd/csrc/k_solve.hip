@@ -278,7 +278,7 @@ constexpr int LSQ_MAXW = 6240;
 constexpr int LSQ_NT = 1024;                 // 16 waves: the one workgroup a CU holds hides latency
 constexpr int LSQ_NWAVE = LSQ_NT / 64;
 constexpr int LSQ_SLOTS = (LSQ_MAXW + LSQ_NT - 1) / LSQ_NT;
-constexpr int LSQ_UNROLL = 4;
+constexpr int LSQ_UNROLL = 2;
 static_assert(LSQ_ROUND % LSQ_NWAVE == 0, "a round gives every wave the same number of segments");
 
 __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, const int *__restrict__ woff,
@@ -337,27 +337,47 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, 
         for (int i = tid; i < 2 * LSQ_ACC; i += LSQ_NT) acc[i] = 0ull;
         __syncthreads();
         for (int r = 0; r < rounds; ++r) {
-            for (int w = r * LSQ_ROUND + wave; w < min(nW, (r + 1) * LSQ_ROUND); w += LSQ_NWAVE) {
-                const int t0 = woff[w], t1 = woff[w + 1];
-                const double2 cw = e[w];
-                double gx = 0.0, gy = 0.0;
-                for (int tb = t0; tb < t1; tb += 64 * LSQ_UNROLL) {
-                    unsigned cd[LSQ_UNROLL];
-                    float2 bb[LSQ_UNROLL];
-                    // every lane loads (past the segment's end: its last sample
-                    // again, unused), so that the loads go out together and are
-                    // awaited once rather than one by one
+            // This wave's segments of the round, w = r LSQ_ROUND + wave, + LSQ_NWAVE, ...,
+            // taken in chunks of 64 LSQ_UNROLL samples.  The loads of the next chunk
+            // (of this segment or the next) are issued before the current chunk is
+            // computed, so their latency runs under its arithmetic.  Every lane loads
+            // (past a segment's end: its last sample, or sample 0 of an empty one,
+            // unused), so the compiler knows how many loads are in flight.
+            const int wend = min(nW, (r + 1) * LSQ_ROUND);
+            int w = r * LSQ_ROUND + wave;
+            if (w < wend) {
+                unsigned cd[2][LSQ_UNROLL];
+                float2 bb[2][LSQ_UNROLL];
+                auto load = [&](int buf, int tb, int t1) __attribute__((always_inline)) {
 #pragma unroll
                     for (int k = 0; k < LSQ_UNROLL; ++k) {
-                        const int t = min(tb + 64 * k + lane, t1 - 1);
-                        cd[k] = code[t];
-                        bb[k] = B[t];
+                        const int t = max(min(tb + 64 * k + lane, t1 - 1), 0);
+                        cd[buf][k] = code[t];
+                        bb[buf][k] = B[t];
                     }
+                };
+                int t1 = woff[w + 1], tb = woff[w];
+                load(0, tb, t1);
+                double gx = 0.0, gy = 0.0;
+                double2 cw = e[w];
+                auto step = [&](int cur) __attribute__((always_inline)) {
+                    // the next chunk: the rest of this segment, else the next segment
+                    int nw = w, ntb = tb + 64 * LSQ_UNROLL, nt1 = t1;
+                    const bool seg_end = ntb >= t1;
+                    if (seg_end) {
+                        nw = w + LSQ_NWAVE;
+                        if (nw < wend) { ntb = woff[nw]; nt1 = woff[nw + 1]; }
+                    }
+                    const bool more = nw < wend;
+                    // (unconditional: past the round's last chunk the indices clamp
+                    // to a sample of this segment, unused)
+                    load(cur ^ 1, ntb, nt1);
 #pragma unroll
                     for (int k = 0; k < LSQ_UNROLL; ++k) {
                         if (tb + 64 * k + lane >= t1) continue;
-                        const double2 a = get(cd[k] >> 16), b = get(cd[k] & 0xffffu);
-                        const double bx = (double)bb[k].x, by = (double)bb[k].y;
+                        const unsigned c = cd[cur][k];
+                        const double2 a = get(c >> 16), b = get(c & 0xffffu);
+                        const double bx = (double)bb[cur][k].x, by = (double)bb[cur][k].y;
                         // own: (a b) conj(B)
                         const double px = a.x * b.x - a.y * b.y, py = a.x * b.y + a.y * b.x;
                         gx += px * bx + py * by;
@@ -365,18 +385,30 @@ __global__ __launch_bounds__(LSQ_NT) void k_lsq(int nW, int n_inner, int iters, 
                         {   // side w - v: conj(b) e(w) B
                             const double qx = b.x * cw.x + b.y * cw.y, qy = b.x * cw.y - b.y * cw.x;
                             const double ry = qx * by + qy * bx;
-                            add(slot((cd[k] >> 16) & 0x7fffu), qx * bx - qy * by, (cd[k] >> 31) ? -ry : ry);
+                            add(slot((c >> 16) & 0x7fffu), qx * bx - qy * by, (c >> 31) ? -ry : ry);
                         }
                         {   // side v: conj(a) e(w) B
                             const double qx = a.x * cw.x + a.y * cw.y, qy = a.x * cw.y - a.y * cw.x;
                             const double ry = qx * by + qy * bx;
-                            add(slot(cd[k] & 0x7fffu), qx * bx - qy * by, (cd[k] & 0x8000u) ? -ry : ry);
+                            add(slot(c & 0x7fffu), qx * bx - qy * by, (c & 0x8000u) ? -ry : ry);
                         }
                     }
+                    if (seg_end) {
+                        gx = wave_sum_d(gx);
+                        gy = wave_sum_d(gy);
+                        if (lane == 0) add(slot((unsigned)w), gx, gy);
+                        gx = 0.0;
+                        gy = 0.0;
+                        if (more) cw = e[nw];
+                    }
+                    w = nw;
+                    tb = ntb;
+                    t1 = nt1;
+                    return more;
+                };
+                // two chunks per pass, so that the register sets alternate statically
+                while (step(0) && step(1)) {
                 }
-                gx = wave_sum_d(gx);
-                gy = wave_sum_d(gy);
-                if (lane == 0) add(slot((unsigned)w), gx, gy);
             }
             __syncthreads();
             // entries no later round targets: new phasors, accumulators cleared
