@@ -301,6 +301,7 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
     __shared__ double mre[MAXE], mim[MAXE], pw[MAXE], val[MAXE];
     __shared__ double eq[RATIO_MAX_BINS], cq[RATIO_MAX_BINS];
     __shared__ double err[RATIO_MAX_POINTS];
+    __shared__ int bin[MAXE];
     const int cube = blockIdx.x, tid = threadIdx.x;
     const int B = a.B, bw = 2 * B + 1, nbox = (B + 1) * bw, Q = a.Q, F = a.F;
     const double invF = 1.0 / F;
@@ -315,15 +316,17 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
         mre[e] = s0 * invF;
         mim[e] = s1 * invF;
         pw[e] = s2 * invF;
+        // annulus of the entry (the half plane only), 0 if none; formed once
+        // here, since the annulus means of every model point scan it
+        const int uy = e / bw, ux = e % bw - B;
+        int q = 0;
+        if (!(uy == 0 && ux <= 0)) {
+            q = (int)floor(sqrt((double)(uy * uy + ux * ux)) + 0.5);
+            if (q > Q) q = 0;
+        }
+        bin[e] = q;
     }
     __syncthreads();
-    // annulus of a box entry of the half plane, 0 if none
-    auto bin_of = [&](int e) {
-        const int uy = e / bw, ux = e % bw - B;
-        if (uy == 0 && ux <= 0) return 0;
-        const int q = (int)floor(sqrt((double)(uy * uy + ux * ux)) + 0.5);
-        return q <= Q ? q : 0;
-    };
     // P at (vy, vx), |vx| <= B, -1 <= vy <= B (P(-v) = P(v))
     auto p_at = [&](int vy, int vx) {
         if (vy < 0) { vy = -vy; vx = -vx; }
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
     };
     for (int e = tid; e < nbox; e += 256) {
         double v = 0.0;
-        if (bin_of(e)) {
+        if (bin[e]) {
             const double m2 = mre[e] * mre[e] + mim[e] * mim[e], P = pw[e];
             v = P > 0.0 ? (m2 - P * invF) / (P * (1.0 - invF)) : 0.0;
         }
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
         double sum = 0.0;
         int cnt = 0;
         for (int e = 0; e < nbox; ++e)
-            if (bin_of(e) == tid + 1) { sum += val[e]; ++cnt; }
+            if (bin[e] == tid + 1) { sum += val[e]; ++cnt; }
         eq[tid] = sum / cnt;
         if (a.curves) a.curves[(size_t)cube * Q + tid] = eq[tid];
     }
@@ -353,7 +356,7 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
         const double2 *A = a.tab_a + (size_t)j * N * N;
         for (int e = tid; e < nbox; e += 256) {
             double v = 0.0;
-            if (bin_of(e)) {
+            if (bin[e]) {
                 const int uy = e / bw, ux = e % bw - B;
                 double num = 0.0, den = 0.0;
                 for (int ky = -kr; ky <= kr; ++ky)
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
             double sum = 0.0;
             int cnt = 0;
             for (int e = 0; e < nbox; ++e)
-                if (bin_of(e) == tid + 1) { sum += val[e]; ++cnt; }
+                if (bin[e] == tid + 1) { sum += val[e]; ++cnt; }
             cq[tid] = sum / cnt;
         }
         __syncthreads();
