@@ -81,8 +81,18 @@ __global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, const double *
     __shared__ float2 z[N * P];
     __shared__ float2 tw[N];
     __shared__ float2 sh[24];                     // subharmonic coefficients
+    __shared__ float2 sct[3][N];                  // (cos, sin)(2 pi t / (N 3^p)), t = 0 .. N - 1
     const int tid = threadIdx.x;
     for (int i = tid; i < N; i += ST) tw[i] = twiddle[i];
+    // the subharmonic phases depend on one coordinate and the level only:
+    // formed once here (by the same calls the per-pixel form made)
+    for (int i = tid; i < 3 * N; i += ST) {
+        const int p = i / N + 1, t = i % N;
+        const float inv = 1.0f / ((float)N * (p == 1 ? 3.f : p == 2 ? 9.f : 27.f));
+        float sn, cs;
+        sincospif(2.0f * (float)t * inv, &sn, &cs);
+        sct[p - 1][t] = make_float2(cs, sn);
+    }
     if (x_dev) {                                   // D/r0 from device memory: r0 = (N/2) / (D/r0) px
         const double r0 = (N / 2.0) / *x_dev;
         amp = (float)(0.15165750888103102 * pow(r0, -5.0 / 6.0) * pow((double)N, 5.0 / 6.0));   // sqrt(0.023)
@@ -153,10 +163,8 @@ __global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, const double *
 #pragma unroll
                 for (int p = 1; p <= 3; ++p) {
                     // exp(2 pi i x / (N 3^p)) and the same for y
-                    const float inv = 1.0f / ((float)N * (p == 1 ? 3.f : p == 2 ? 9.f : 27.f));
-                    float sx, cx, sy, cy;
-                    sincospif(2.0f * (float)x * inv, &sx, &cx);
-                    sincospif(2.0f * (float)y * inv, &sy, &cy);
+                    const float2 tx = sct[p - 1][x], ty = sct[p - 1][y];
+                    const float cx = tx.x, sx = tx.y, cy = ty.x, sy = ty.y;
 #pragma unroll
                     for (int kk = 0; kk < 8; ++kk) {
                         int iy, ix;
@@ -302,6 +310,8 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
     __shared__ double eq[RATIO_MAX_BINS], cq[RATIO_MAX_BINS];
     __shared__ double err[RATIO_MAX_POINTS];
     __shared__ int bin[MAXE];
+    __shared__ int lst[MAXE];                 // the entries of each annulus, e ascending
+    __shared__ int lo[RATIO_MAX_BINS + 1];    // annulus q: lst[lo[q - 1] .. lo[q])
     const int cube = blockIdx.x, tid = threadIdx.x;
     const int B = a.B, bw = 2 * B + 1, nbox = (B + 1) * bw, Q = a.Q, F = a.F;
     const double invF = 1.0 / F;
@@ -327,6 +337,31 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
         bin[e] = q;
     }
     __syncthreads();
+    // the annulus lists: counts, offsets, then each annulus's entries in
+    // ascending order (so the annulus means add in the order of a plain scan)
+    if (tid < Q) {
+        int c = 0;
+        for (int e = 0; e < nbox; ++e) c += bin[e] == tid + 1;
+        lo[tid + 1] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        lo[0] = 0;
+        for (int q = 1; q <= Q; ++q) lo[q] += lo[q - 1];
+    }
+    __syncthreads();
+    if (tid < Q) {
+        int k = lo[tid];
+        for (int e = 0; e < nbox; ++e)
+            if (bin[e] == tid + 1) lst[k++] = e;
+    }
+    __syncthreads();
+    // mean of val over annulus tid + 1 (threads tid < Q)
+    auto annulus_mean = [&]() {
+        double sum = 0.0;
+        for (int k = lo[tid]; k < lo[tid + 1]; ++k) sum += val[lst[k]];
+        return sum / (lo[tid + 1] - lo[tid]);
+    };
     // P at (vy, vx), |vx| <= B, -1 <= vy <= B (P(-v) = P(v))
     auto p_at = [&](int vy, int vx) {
         if (vy < 0) { vy = -vy; vx = -vx; }
@@ -342,11 +377,7 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
     }
     __syncthreads();
     if (tid < Q) {
-        double sum = 0.0;
-        int cnt = 0;
-        for (int e = 0; e < nbox; ++e)
-            if (bin[e] == tid + 1) { sum += val[e]; ++cnt; }
-        eq[tid] = sum / cnt;
+        eq[tid] = annulus_mean();
         if (a.curves) a.curves[(size_t)cube * Q + tid] = eq[tid];
     }
     __syncthreads();
@@ -375,13 +406,7 @@ __global__ __launch_bounds__(256) void k_seeing_fit(const SeeingFitArgs a) {
             val[e] = v;
         }
         __syncthreads();
-        if (tid < Q) {
-            double sum = 0.0;
-            int cnt = 0;
-            for (int e = 0; e < nbox; ++e)
-                if (bin[e] == tid + 1) { sum += val[e]; ++cnt; }
-            cq[tid] = sum / cnt;
-        }
+        if (tid < Q) cq[tid] = annulus_mean();
         __syncthreads();
         if (tid == 0) {
             double e2 = 0.0;
