@@ -13,8 +13,11 @@
 // origin in the order iy, ix = -1, 0, 1.
 //
 // One workgroup takes screen pairs j = blockIdx.x, + gridDim.x, ...; per
-// screen: field = pupil exp(i phi) -> FFT -> |.|^2 (PSF) -> FFT (OTF) ->
-// normalised by OTF(0), accumulated over the half plane of frequencies.
+// pair the screens' transform is made once, and per screen: field = pupil
+// exp(i phi) -> FFT -> |.|^2 (PSF) -> FFT (OTF) -> normalised by OTF(0),
+// accumulated over the half plane of frequencies.  The second screen's
+// phases over the pupil's bounding box wait in LDS while the first screen
+// is used.
 // The transforms leave their output in the storage order of fft2d_lds;
 // element-wise steps work there, and each thread moves its pixels back to
 // natural order through registers before the next transform.
@@ -82,6 +85,8 @@ __global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, const double *
     __shared__ float2 tw[N];
     __shared__ float2 sh[24];                     // subharmonic coefficients
     __shared__ float2 sct[3][N];                  // (cos, sin)(2 pi t / (N 3^p)), t = 0 .. N - 1
+    constexpr int PB = N / 2, PB0 = N / 4;        // the pupil's bounding box: [PB0, PB0 + PB)^2
+    __shared__ float side[PB * PB];               // the second screen's phases over that box
     const int tid = threadIdx.x;
     for (int i = tid; i < N; i += ST) tw[i] = twiddle[i];
     // the subharmonic phases depend on one coordinate and the level only:
@@ -114,13 +119,12 @@ __global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, const double *
 
     // storage position -> natural index along one axis of the transform
     auto nat = [](int p) { return (p % FftGeom<N>::R1) * FftGeom<N>::R2 + p / FftGeom<N>::R1; };
-    // A pair's screens are the real and imaginary parts of one transform;
-    // the transform is made again for the second screen, so that neither
-    // screen has to be held while the other one is used.
+    // A pair's screens are the real and imaginary parts of one transform:
+    // the first screen's field goes to registers, the second screen's
+    // phases inside the pupil to the side buffer, until its turn.
     for (int j = blockIdx.x; j < pairs; j += gridDim.x) {
-#pragma unroll 1
-        for (int scr = 0; scr < 2; ++scr) {
-            __syncthreads();                       // previous use of z and sh done
+        {
+            __syncthreads();                       // previous use of z, sh and side done
             // spectrum of the screen pair, natural order
 #pragma unroll 1
             for (int q = 0; q < WD; ++q) {
@@ -180,19 +184,35 @@ __global__ __launch_bounds__(ST) void k_stf(int pairs, float amp, const double *
                 z[row * P + col] = v;
             }
             __syncthreads();
-            // field = pupil exp(i phi) of this screen, to natural order
-            float2 t[PX];
+        }
+        // field = pupil exp(i phi) of the first screen, to natural order; the
+        // second screen's phases to the side buffer
+        float2 t[PX];
 #pragma unroll
-            for (int k = 0; k < PX; ++k) {
-                const int e = k * ST + tid, y = e / N, x = e % N;
-                float s = 0.f, c = 0.f;
-                if (in_pupil(y, x)) {
-                    const float2 v = z[fft_pos<N>(y) * P + fft_pos<N>(x)];
-                    sincosf(scr ? v.y : v.x, &s, &c);
-                }
-                t[k] = make_float2(c, s);
+        for (int k = 0; k < PX; ++k) {
+            const int e = k * ST + tid, y = e / N, x = e % N;
+            float s = 0.f, c = 0.f;
+            if (in_pupil(y, x)) {
+                const float2 v = z[fft_pos<N>(y) * P + fft_pos<N>(x)];
+                sincosf(v.x, &s, &c);
+                side[(y - PB0) * PB + (x - PB0)] = v.y;
             }
-            __syncthreads();
+            t[k] = make_float2(c, s);
+        }
+        // (unrolled: the first screen's field is dead once in LDS, so it is
+        // not held through the second screen's steps)
+#pragma unroll
+        for (int scr = 0; scr < 2; ++scr) {
+            if (scr) {
+#pragma unroll
+                for (int k = 0; k < PX; ++k) {
+                    const int e = k * ST + tid, y = e / N, x = e % N;
+                    float s = 0.f, c = 0.f;
+                    if (in_pupil(y, x)) sincosf(side[(y - PB0) * PB + (x - PB0)], &s, &c);
+                    t[k] = make_float2(c, s);
+                }
+            }
+            __syncthreads();                       // the transform (or the last OTF) was read
 #pragma unroll
             for (int k = 0; k < PX; ++k) {
                 const int e = k * ST + tid;
