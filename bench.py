@@ -353,9 +353,9 @@ def model_stf(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     nv.nvsm_destroy(ctx)
-    # per screen: the pair's transform (made once per screen) and two
-    # transforms of the field and the PSF, 5 N^2 log2(N^2) flop each
-    flop = K * 3 * 5 * N * N * math.log2(N * N)
+    # per screen: half of the pair's transform (one per pair of screens) and
+    # the transforms of the field and the PSF, 5 N^2 log2(N^2) flop each
+    flop = K * 2.5 * 5 * N * N * math.log2(N * N)
     out = {
         "metric": f"model STF tables/s ({N}x{N} patch grid, D/r0 {x:g}, {K} screens)",
         "value": 1e3 / ms, "unit": "tables/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
