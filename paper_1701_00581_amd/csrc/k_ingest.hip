@@ -679,20 +679,33 @@ __global__ __launch_bounds__(FT) void k_ratio(const RatioArgs a) {
     float sm[EPT][3];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) sm[k][0] = sm[k][1] = sm[k][2] = 0.f;
+    // the pixels of a frame pair (a lone last frame: loaded twice, the copy
+    // unused); the next pair's are requested once the tile is written, so
+    // that they arrive during the transform, as in k_ingest
     Quad<T, VEC> qa[QPT], qb[QPT];
-    __syncthreads();
-    for (int fa = f0; fa < f1; fa += 2) {
-        const bool hasb = fa + 1 < f1;
-        const int fb = hasb ? fa + 1 : fa;
+    auto load_pair = [&](int fa) __attribute__((always_inline)) {
+        const int fb = min(fa + 1, f1 - 1);
         const gptr_c pa = uniform_ptr(frames + (size_t)fa * a.H * pitch + (size_t)y0 * pitch + x0);
         const gptr_c pb = uniform_ptr(frames + (size_t)fb * a.H * pitch + (size_t)y0 * pitch + x0);
+        unsigned tid_l;                // opaque: the offsets are formed here, not kept
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid_l) : "v"(tid));
+        static_assert(4 * FT % N == 0, "whole rows between the quads of a thread");
+        const unsigned off0 = ((4u * tid_l) / N * (unsigned)pitch + (4u * tid_l) % N) * (unsigned)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const unsigned off = off0 + (unsigned)(j * (4 * FT / N)) * (unsigned)pitch * (unsigned)sizeof(T);
+            qa[j].load(pa, off);
+            qb[j].load(pb, off);
+        }
+    };
+    __syncthreads();
+    load_pair(f0);
+    for (int fa = f0; fa < f1; fa += 2) {
+        const bool hasb = fa + 1 < f1;
         float sa = 0.f, ca = 0.f, sb = 0.f, cb = 0.f;
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
             const int q = j * FT + tid, y = (4 * q) / N, x = (4 * q) % N;
-            const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(T);
-            qa[j].load(pa, off);
-            qb[j].load(pb, off);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float va = qa[j][e], vb = hasb ? qb[j][e] : 0.f;
@@ -720,7 +733,8 @@ __global__ __launch_bounds__(FT) void k_ratio(const RatioArgs a) {
             }
         }
         __syncthreads();
-        fft2d_lds<N, FT>(z, tw);
+        load_pair(min(fa + 2, f1 - 1));
+        fft2d_lds_inline<N, FT>(z, tw);
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             const int e = k * FT + tid;
