@@ -159,12 +159,19 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     // the patch's spectra as one buffer resource; frame f at byte f * FB
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void *)(spec + (size_t)rec0 * FS), (short)0, F * FB, 0x00020000);
-    // the region loads of frame f into buf
+    // With the photon-noise terms, the last frame stages the same region of
+    // the patch's C table (record layout) instead of a spare copy of itself,
+    // so that the correction reads C(w - v) from LDS at the slots' offsets.
+    const bool photon = MODE == 2 || (MODE == 1 && acc.noise_c != nullptr);
+    const __amdgpu_buffer_rsrc_t rsrc_c = __builtin_amdgcn_make_buffer_rsrc(
+        photon ? (void *)(acc.noise_c + (size_t)patch * FS) : (void *)spec, (short)0, photon ? FB : 0, 0x00020000);
+    // the region loads of frame f into buf (f = F: the C table's region)
     auto fetch = [&](int f, float2 *buf) __attribute__((always_inline)) {
+        const bool c = photon && f == F;
 #pragma unroll
         for (int j = 0; j < PERW; ++j)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_ptr)(buf + 128 * (wave + BS_WAVES * j)), 16,
-                                                     (int)src[j], f * FB, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(c ? rsrc_c : rsrc, (lds_ptr)(buf + 128 * (wave + BS_WAVES * j)), 16,
+                                                     (int)src[j], c ? 0 : f * FB, 0, 0);
     };
     auto load_vals = [&](int f, float2 &cw, float2 (&bv)[NQ]) __attribute__((always_inline)) {
         cw = as_f2(__builtin_amdgcn_raw_buffer_load_b64(rsrc, wo, f * FB, 0));
@@ -206,9 +213,10 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
     // the 1 + NQ value loads were issued last).  Loads are issued without
     // branches, so the compiler knows how many are in flight at each use.
     auto frame = [&](int f, const float2 *rg, float2 *nxt) __attribute__((always_inline)) {
-        // the last frame fetches itself again (unused) rather than branch
+        // the last frame fetches itself again (unused) rather than branch, or
+        // with the photon-noise terms the C region
         const int fn = min(f + 1, F - 1);
-        fetch(fn, nxt);
+        fetch(photon ? f + 1 : fn, nxt);
         const char *rb = (const char *)rg;
         // p = I(w - v) I(v);  t += p conj I(w).  The gather of slot k + 1 is
         // requested before slot k is computed, so that its LDS latency runs
@@ -270,6 +278,9 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         const float2 *Cp = acc.noise_c + (size_t)patch * FS;
         const float t2 = 2.0f * acc.noise_t[(size_t)patch * 2 + 1];
         const int wi = wo / (int)sizeof(float2);
+        // C(w - v) from the C region the last frame staged (in the buffer
+        // after the last frame's)
+        const char *cr = (const char *)((F & 1) ? lds1 : lds0);
         // the means first, so the block-sum registers are free for the loads
 #pragma unroll
         for (int k = 0; k < NS; ++k) s[k] = make_float2((s[k].x + t[k].x) * inv, (s[k].y + t[k].y) * inv);
@@ -278,7 +289,7 @@ __device__ __forceinline__ void bispec_item(float2 *lds0, float2 *lds1, const fl
         for (int k = 0; k < NS; ++k) {
             const int vo = sl[2 * k + 1];
             const float2 c_v = Cp[vo];
-            const float2 c_d = Cp[(wi / N - vo / N + SPEC_NEG_ROWS) * N + ((wi - vo) & (N - 1))];
+            const float2 c_d = *(const float2 *)(cr + addr[k]);
             const int o = oi[k * 64];
             if (o >= 0)
                 bo[o] = make_float2(s[k].x - (c_w.x + c_v.x + c_d.x - t2), s[k].y - (c_w.y - c_v.y - c_d.y));
