@@ -2,20 +2,23 @@
 //
 // One workgroup per patch.  Frequencies are visited shell by shell (|w|^2
 // ascending); every w of a shell reads only strictly shorter frequencies,
-// so a shell's w are independent.  The planner cuts each shell into units
-// of at most 8 w; in a unit wave j takes w number j, its lanes split that
-// w's bispectrum samples, and a wave reduction (DPP) gives
+// so a shell's w are independent.  The planner joins consecutive shells
+// into groups while no w of a group reads another w of it (1161 shells
+// make 996 groups at N = 128, |w| <= 63, R = 12), and cuts each group
+// into units of at most 8 w; in a unit wave j takes w
+// number j, its lanes split that w's bispectrum samples, and a wave
+// reduction (DPP) gives
 //   z(w) = sum_v e(w - v) e(v) conj B(w, v),  e(w) = z / |z|.
-// The workgroup waits at a barrier only after the last unit of a shell.
-// Since |v| <= R, a shell only reads phasors with |x| <= R or
+// The workgroup waits at a barrier only after the last unit of a group.
+// Since |v| <= R, a group only reads phasors with |x| <= R or
 // |x| >= |w| - R: those stay in LDS (the inner disk, plus a ring for the
 // annulus), which keeps the workgroup small enough for three per CU.  The
-// sample codes hold the LDS slot of each phasor for the sample's shell
+// sample codes hold the LDS slot of each phasor for the sample's group
 // (computed on the host), so a lookup is a plain LDS read.  Each phasor is
 // written to the output as soon as it is known.  The samples of the next
 // DEPTH - 1 units are loaded into registers while the current unit is
 // computed: a unit's own work is shorter than a load from HBM, so with a
-// single unit in flight the chain of shells waited on memory latency (one w
+// single unit in flight the chain of groups waited on memory latency (one w
 // per wave and unit keeps a register set small enough for several in flight
 // at six waves per SIMD).
 #include "device_common.hpp"

@@ -124,34 +124,46 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     pl->shell_wb.push_back(nW);
     pl->s_count = pl->woff[nW];
 
+    // phase-solve groups: a shell joins the group before it when none of
+    // its samples reads a w of that group (reads always go to shorter w)
+    pl->group_wb.assign(1, 0);
+    for (size_t sh = 1; sh + 1 < pl->shell_wb.size(); ++sh) {
+        const int g0 = pl->group_wb.back();
+        bool reads_group = sh == 1;  // the seed shell is a group of its own
+        for (int32_t t = pl->woff[pl->shell_wb[sh]]; t < pl->woff[pl->shell_wb[sh + 1]] && !reads_group; ++t)
+            reads_group = (int)((pl->phase_code[t] >> 16) & 0x7fffu) >= g0 || (int)(pl->phase_code[t] & 0x7fffu) >= g0;
+        if (reads_group) pl->group_wb.push_back(pl->shell_wb[sh]);
+    }
+    pl->group_wb.push_back(nW);
+
     // sample indices are kept in 30 bits by the kernels' tables
     if (pl->s_count >= (int64_t)1 << 30) { *err = "bispectrum set too large"; return false; }
 
     // phasor window: inner entries |w| <= R, the rest in a ring; each
-    // shell's lowest ring entry read comes from its sample codes
+    // group's lowest ring entry read comes from its sample codes
     pl->n_inner = 0;
     while (pl->n_inner < nW) {
         const int x = pl->W[2 * pl->n_inner], y = pl->W[2 * pl->n_inner + 1];
         if (x * x + y * y > R * R) break;
         ++pl->n_inner;
     }
-    const int nshell = (int)pl->shell_wb.size() - 1;
-    std::vector<int32_t> lo(nshell);
+    const int ngroup = (int)pl->group_wb.size() - 1;
+    std::vector<int32_t> lo(ngroup);
     int span = 1;
-    for (int sh = 0; sh < nshell; ++sh) {
-        int l = pl->shell_wb[sh];
-        for (int32_t t = pl->woff[pl->shell_wb[sh]]; t < pl->woff[pl->shell_wb[sh + 1]]; ++t) {
+    for (int g = 0; g < ngroup; ++g) {
+        int l = pl->group_wb[g];
+        for (int32_t t = pl->woff[pl->group_wb[g]]; t < pl->woff[pl->group_wb[g + 1]]; ++t) {
             const int ia = (int)((pl->phase_code[t] >> 16) & 0x7fffu), ib = (int)(pl->phase_code[t] & 0x7fffu);
             if (ia >= pl->n_inner) l = std::min(l, ia);
             if (ib >= pl->n_inner) l = std::min(l, ib);
         }
-        lo[sh] = std::max(l, pl->n_inner);
-        span = std::max(span, pl->shell_wb[sh + 1] - lo[sh]);
+        lo[g] = std::max(l, pl->n_inner);
+        span = std::max(span, pl->group_wb[g + 1] - lo[g]);
     }
     pl->ring_size = span;
-    pl->shell_ring_off.resize(nshell);
-    for (int sh = 0; sh < nshell; ++sh)
-        pl->shell_ring_off[sh] = (lo[sh] - pl->n_inner) / span * span;
+    pl->group_ring_off.resize(ngroup);
+    for (int g = 0; g < ngroup; ++g)
+        pl->group_ring_off[g] = (lo[g] - pl->n_inner) / span * span;
     auto slot_of = [&](int i, int ro) {
         if (i < pl->n_inner) return i;
         int q = i - pl->n_inner - ro;
@@ -160,9 +172,9 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
     };
     pl->phase_slot_code.resize(pl->phase_code.size());
     pl->w_slot.resize(nW);
-    for (int sh = 0; sh < nshell; ++sh) {
-        const int ro = pl->shell_ring_off[sh];
-        for (int w = pl->shell_wb[sh]; w < pl->shell_wb[sh + 1]; ++w) {
+    for (int g = 0; g < ngroup; ++g) {
+        const int ro = pl->group_ring_off[g];
+        for (int w = pl->group_wb[g]; w < pl->group_wb[g + 1]; ++w) {
             pl->w_slot[w] = slot_of(w, ro);
             for (int32_t t = pl->woff[w]; t < pl->woff[w + 1]; ++t) {
                 const uint32_t c = pl->phase_code[t];
@@ -190,15 +202,16 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
                       pl->solve_code.begin() + (size_t)w * pl->solve_pad);
     }
 
-    // phase-solve units: shells 1.. cut into runs of SOLVE_WAVES w
+    // phase-solve units: groups 1.. cut into runs of SOLVE_WAVES w
     pl->solve_units.clear();
     pl->n_units = 0;
-    for (int sh = 1; sh < nshell; ++sh) {
-        for (int w0 = pl->shell_wb[sh]; w0 < pl->shell_wb[sh + 1]; w0 += SOLVE_WAVES) {
-            const int last = w0 + SOLVE_WAVES >= pl->shell_wb[sh + 1];
+    for (size_t g = 1; g + 1 < pl->group_wb.size(); ++g) {
+        const int end = pl->group_wb[g + 1];
+        for (int w0 = pl->group_wb[g]; w0 < end; w0 += SOLVE_WAVES) {
+            const int last = w0 + SOLVE_WAVES >= end;
             for (int j = 0; j < SOLVE_WAVES; ++j) {
                 const int w = w0 + j;
-                if (w < pl->shell_wb[sh + 1])
+                if (w < end)
                     pl->solve_units.insert(pl->solve_units.end(),
                                            {w, pl->woff[w], (pl->woff[w + 1] - pl->woff[w]) | (last << 16), pl->w_slot[w]});
                 else

@@ -48,14 +48,19 @@ struct HostPlan {
     std::vector<int32_t> W;
     std::vector<int32_t> woff;          // |W|+1
     std::vector<int32_t> shell_wb;      // shells+1: W range of each shell
+    // Phase-solve groups: runs of consecutive shells in which no sample
+    // reads a w of its own run (both sides lie before the run's first w),
+    // so that all w of a group can be solved at once.  group_wb: groups+1,
+    // W range of each group; group 0 is the seed shell.
+    std::vector<int32_t> group_wb;
     // Phasor window of the phase solve: W entries [0, n_inner) (|w| <= R)
     // stay resident; the others live in a ring of ring_size entries.  A
-    // shell reads ring entries >= its lowest index, so entry i sits at ring
-    // slot (i - n_inner - shell_ring_off[s]) reduced once by ring_size.
+    // group reads ring entries >= its lowest index, so entry i sits at ring
+    // slot (i - n_inner - group_ring_off[g]) reduced once by ring_size.
     int n_inner = 0, ring_size = 0;
-    std::vector<int32_t> shell_ring_off;  // shells: multiple of ring_size
+    std::vector<int32_t> group_ring_off;  // groups: multiple of ring_size
     // phase_code with W indices replaced by the LDS slot each phasor has
-    // while the sample's shell is solved, and the slot of every w.
+    // while the sample's group is solved, and the slot of every w.
     std::vector<uint32_t> phase_slot_code;
     std::vector<int32_t> w_slot;
     // phase_slot_code as the phase-solve kernel reads it: one block of
@@ -67,12 +72,12 @@ struct HostPlan {
     // has more than SOLVE_MAX_SAMPLES samples.
     int max_sw = 0, solve_pad = 0, zero_slot = 0;
     std::vector<uint32_t> solve_code;
-    // Phase-solve units: each shell after the first (the seeds) cut into
+    // Phase-solve units: each group after the first (the seeds) cut into
     // units of at most SOLVE_WAVES w, one w per wave.  solve_units[(u *
     // SOLVE_WAVES + j) * 4 + 0..3] = (w of wave j or -1, its first S index,
-    // its sample count + 65536 if u is the last unit of its shell, the LDS
-    // slot of its phasor).  The units of one shell are independent; a
-    // shell's results are read only by later shells.
+    // its sample count + 65536 if u is the last unit of its group, the LDS
+    // slot of its phasor).  The units of one group are independent; a
+    // group's results are read only by later groups.
     int n_units = 0;
     std::vector<int32_t> solve_units;
     // Least-squares rounds: before round r (segments [r, r + 1) * LSQ_ROUND)

@@ -95,22 +95,29 @@ static long check_lsq_rounds(const HostPlan &pl) {
     return bad;
 }
 
-// Phase-solve units: every w of shells 1.. exactly once, in storage order,
-// with its S range; at most SOLVE_WAVES w per unit, all of one shell; the
-// barrier flag set exactly on each shell's last unit; and every sample's
-// sides come from strictly earlier shells (so the units of a shell are
-// independent).
+// Phase-solve units: groups are runs of whole shells; every w of groups 1..
+// exactly once, in storage order, with its S range; at most SOLVE_WAVES w
+// per unit, all of one group; the barrier flag set exactly on each group's
+// last unit; and every sample's sides come from strictly earlier groups (so
+// the units of a group are independent).
 static long check_solve_units(const HostPlan &pl) {
     long bad = 0;
-    const int nW = (int)pl.W.size() / 2, nshell = (int)pl.shell_wb.size() - 1;
+    const int nW = (int)pl.W.size() / 2, ngroup = (int)pl.group_wb.size() - 1;
     if ((int)pl.solve_units.size() != pl.n_units * SOLVE_WAVES * 4) return 1;
-    std::vector<int> shell_of(nW);
-    for (int sh = 0; sh < nshell; ++sh)
-        for (int w = pl.shell_wb[sh]; w < pl.shell_wb[sh + 1]; ++w) shell_of[w] = sh;
-    int expect = pl.shell_wb[1];
+    // groups are runs of whole shells, the first of them the seed shell
+    if (ngroup < 1 || pl.group_wb[0] != 0 || pl.group_wb[ngroup] != nW) return 1;
+    if (ngroup > 1 && pl.group_wb[1] != pl.shell_wb[1]) ++bad;
+    for (int g = 1; g <= ngroup; ++g) {
+        if (pl.group_wb[g] <= pl.group_wb[g - 1]) return bad + 1;
+        if (!std::binary_search(pl.shell_wb.begin(), pl.shell_wb.end(), pl.group_wb[g])) ++bad;
+    }
+    std::vector<int> group_of(nW);
+    for (int g = 0; g < ngroup; ++g)
+        for (int w = pl.group_wb[g]; w < pl.group_wb[g + 1]; ++w) group_of[w] = g;
+    int expect = ngroup > 1 ? pl.group_wb[1] : nW;
     for (int u = 0; u < pl.n_units; ++u) {
         const int32_t *t = &pl.solve_units[(size_t)u * SOLVE_WAVES * 4];
-        const int sh = shell_of[t[0]];
+        const int g = group_of[t[0]];
         const int flag = t[2] >> 16;
         for (int j = 0; j < SOLVE_WAVES; ++j) {
             const int w = t[4 * j], o = t[4 * j + 1], c = t[4 * j + 2] & 0xffff, last = t[4 * j + 2] >> 16;
@@ -119,25 +126,25 @@ static long check_solve_units(const HostPlan &pl) {
                 if (o != 0 || c != 0) ++bad;
                 continue;
             }
-            if (w != expect || shell_of[w] != sh) ++bad;
+            if (w != expect || group_of[w] != g) ++bad;
             ++expect;
             if (o != pl.woff[w] || c != pl.woff[w + 1] - pl.woff[w] || t[4 * j + 3] != pl.w_slot[w]) ++bad;
             for (int32_t k = o; k < o + c; ++k) {
                 const int ia = (int)((pl.phase_code[k] >> 16) & 0x7fffu), ib = (int)(pl.phase_code[k] & 0x7fffu);
-                if (shell_of[ia] >= sh || shell_of[ib] >= sh) ++bad;
+                if (group_of[ia] >= g || group_of[ib] >= g) ++bad;
             }
         }
-        const bool end = expect == pl.shell_wb[sh + 1];
+        const bool end = expect == pl.group_wb[g + 1];
         if ((flag != 0) != end) ++bad;
     }
     if (expect != nW) ++bad;
     // the phasor window: every sample reads each side at the slot where that
     // side's phasor was written (w_slot), and the ring entries live while a
-    // shell is solved (from the lowest one its samples read to its own last
+    // group is solved (from the lowest one its samples read to its own last
     // w) hold distinct slots, so none was overwritten in between
-    for (int sh = 1; sh < (int)pl.shell_wb.size() - 1; ++sh) {
-        int lo = pl.shell_wb[sh];
-        for (int w = pl.shell_wb[sh]; w < pl.shell_wb[sh + 1]; ++w)
+    for (int g = 1; g < ngroup; ++g) {
+        int lo = pl.group_wb[g];
+        for (int w = pl.group_wb[g]; w < pl.group_wb[g + 1]; ++w)
             for (int32_t t = pl.woff[w]; t < pl.woff[w + 1]; ++t) {
                 const uint32_t c = pl.phase_code[t], sc = pl.phase_slot_code[t];
                 const int x[2] = {(int)((c >> 16) & 0x7fffu), (int)(c & 0x7fffu)};
@@ -149,7 +156,7 @@ static long check_solve_units(const HostPlan &pl) {
             }
         std::vector<int> seen(pl.zero_slot, 0);
         for (int x = 0; x < pl.n_inner; ++x) ++seen[pl.w_slot[x]];
-        for (int x = std::max(lo, pl.n_inner); x < pl.shell_wb[sh + 1]; ++x) ++seen[pl.w_slot[x]];
+        for (int x = std::max(lo, pl.n_inner); x < pl.group_wb[g + 1]; ++x) ++seen[pl.w_slot[x]];
         for (int v : seen)
             if (v > 1) ++bad;
     }
@@ -189,9 +196,9 @@ int main(int argc, char **argv) {
             continue;
         }
         const long b1 = check_bispectrum(pl, N, K), b2 = check_lsq_rounds(pl), b3 = check_solve_units(pl);
-        std::printf("N=%d uc=%d R=%d K=%d items=%d units=%d |S|=%lld bispectrum bad=%ld rounds bad=%ld "
-                    "units bad=%ld bad=%ld\n", N, uc, R, K, pl.n_items, pl.n_units, (long long)pl.s_count, b1, b2, b3,
-                    b1 + b2 + b3);
+        std::printf("N=%d uc=%d R=%d K=%d items=%d shells=%d groups=%d units=%d ring=%d |S|=%lld bispectrum bad=%ld "
+                    "rounds bad=%ld units bad=%ld bad=%ld\n", N, uc, R, K, pl.n_items, (int)pl.shell_wb.size() - 1,
+                    (int)pl.group_wb.size() - 1, pl.n_units, pl.ring_size, (long long)pl.s_count, b1, b2, b3, b1 + b2 + b3);
     }
     return 0;
 }
