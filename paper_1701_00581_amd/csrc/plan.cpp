@@ -83,62 +83,8 @@ int count_shells(const std::vector<int32_t> &W) {
     return n;
 }
 
-bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
-    if (K < 8 || K > BS_MAX_SLOTS || K % 8) { *err = "slots per wave must be 8..32, a multiple of 8"; return false; }
-    pl->slots = K;
-    if (N != 64 && N != 128) { *err = "patch must be 64 or 128"; return false; }
-    if (uc < 2 || uc >= N / 2) { *err = "u_cut must be in [2, N/2)"; return false; }
-    if (R < 1 || R > 16 || R >= uc) { *err = "v_radius must be in [1, min(16, u_cut))"; return false; }
-    pl->N = N; pl->uc = uc; pl->R = R;
-    enumerate_W(uc, &pl->W);
-    const int nW = (int)pl->W.size() / 2;
-    if (nW >= 0x8000) { *err = "too many frequencies"; return false; }
-
-    // index of each upper-half frequency
-    const int side = 2 * uc + 1;
-    std::vector<int32_t> widx((size_t)side * side, -1);
-    auto at = [&](int x, int y) -> int32_t & { return widx[(size_t)(y + uc) * side + (x + uc)]; };
-    for (int i = 0; i < nW; ++i) at(pl->W[2 * i], pl->W[2 * i + 1]) = i;
-    auto code = [&](int x, int y) -> uint32_t {
-        if (upper_half(x, y)) return (uint32_t)at(x, y);
-        return (uint32_t)at(-x, -y) | 0x8000u;
-    };
-
-    // S offsets, phase lookup codes, shells; per-w rank maps for the kernel
-    pl->woff.assign(nW + 1, 0);
-    pl->phase_code.clear();
-    pl->shell_wb.clear();
-    std::vector<std::vector<int32_t>> Sw(nW);
-    int last = -1;
-    for (int i = 0; i < nW; ++i) {
-        int wx = pl->W[2 * i], wy = pl->W[2 * i + 1];
-        int r2 = wx * wx + wy * wy;
-        if (r2 != last) { pl->shell_wb.push_back(i); last = r2; }
-        samples_of(wx, wy, R, &Sw[i]);
-        for (size_t j = 0; j < Sw[i].size() / 2; ++j) {
-            int vx = Sw[i][2 * j], vy = Sw[i][2 * j + 1];
-            pl->phase_code.push_back((code(wx - vx, wy - vy) << 16) | code(vx, vy));
-        }
-        pl->woff[i + 1] = pl->woff[i] + (int32_t)(Sw[i].size() / 2);
-    }
-    pl->shell_wb.push_back(nW);
-    pl->s_count = pl->woff[nW];
-
-    // phase-solve groups: a shell joins the group before it when none of
-    // its samples reads a w of that group (reads always go to shorter w)
-    pl->group_wb.assign(1, 0);
-    for (size_t sh = 1; sh + 1 < pl->shell_wb.size(); ++sh) {
-        const int g0 = pl->group_wb.back();
-        bool reads_group = sh == 1;  // the seed shell is a group of its own
-        for (int32_t t = pl->woff[pl->shell_wb[sh]]; t < pl->woff[pl->shell_wb[sh + 1]] && !reads_group; ++t)
-            reads_group = (int)((pl->phase_code[t] >> 16) & 0x7fffu) >= g0 || (int)(pl->phase_code[t] & 0x7fffu) >= g0;
-        if (reads_group) pl->group_wb.push_back(pl->shell_wb[sh]);
-    }
-    pl->group_wb.push_back(nW);
-
-    // sample indices are kept in 30 bits by the kernels' tables
-    if (pl->s_count >= (int64_t)1 << 30) { *err = "bispectrum set too large"; return false; }
-
+bool plan_phase_solve(HostPlan *pl, std::string *err) {
+    const int nW = (int)pl->W.size() / 2, R = pl->R;
     // phasor window: inner entries |w| <= R, the rest in a ring; each
     // group's lowest ring entry read comes from its sample codes
     pl->n_inner = 0;
@@ -220,6 +166,66 @@ bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
             ++pl->n_units;
         }
     }
+    return true;
+}
+
+bool build_plan(int N, int uc, int R, int K, HostPlan *pl, std::string *err) {
+    if (K < 8 || K > BS_MAX_SLOTS || K % 8) { *err = "slots per wave must be 8..32, a multiple of 8"; return false; }
+    pl->slots = K;
+    if (N != 64 && N != 128) { *err = "patch must be 64 or 128"; return false; }
+    if (uc < 2 || uc >= N / 2) { *err = "u_cut must be in [2, N/2)"; return false; }
+    if (R < 1 || R > 16 || R >= uc) { *err = "v_radius must be in [1, min(16, u_cut))"; return false; }
+    pl->N = N; pl->uc = uc; pl->R = R;
+    enumerate_W(uc, &pl->W);
+    const int nW = (int)pl->W.size() / 2;
+    if (nW >= 0x8000) { *err = "too many frequencies"; return false; }
+
+    // index of each upper-half frequency
+    const int side = 2 * uc + 1;
+    std::vector<int32_t> widx((size_t)side * side, -1);
+    auto at = [&](int x, int y) -> int32_t & { return widx[(size_t)(y + uc) * side + (x + uc)]; };
+    for (int i = 0; i < nW; ++i) at(pl->W[2 * i], pl->W[2 * i + 1]) = i;
+    auto code = [&](int x, int y) -> uint32_t {
+        if (upper_half(x, y)) return (uint32_t)at(x, y);
+        return (uint32_t)at(-x, -y) | 0x8000u;
+    };
+
+    // S offsets, phase lookup codes, shells; per-w rank maps for the kernel
+    pl->woff.assign(nW + 1, 0);
+    pl->phase_code.clear();
+    pl->shell_wb.clear();
+    std::vector<std::vector<int32_t>> Sw(nW);
+    int last = -1;
+    for (int i = 0; i < nW; ++i) {
+        int wx = pl->W[2 * i], wy = pl->W[2 * i + 1];
+        int r2 = wx * wx + wy * wy;
+        if (r2 != last) { pl->shell_wb.push_back(i); last = r2; }
+        samples_of(wx, wy, R, &Sw[i]);
+        for (size_t j = 0; j < Sw[i].size() / 2; ++j) {
+            int vx = Sw[i][2 * j], vy = Sw[i][2 * j + 1];
+            pl->phase_code.push_back((code(wx - vx, wy - vy) << 16) | code(vx, vy));
+        }
+        pl->woff[i + 1] = pl->woff[i] + (int32_t)(Sw[i].size() / 2);
+    }
+    pl->shell_wb.push_back(nW);
+    pl->s_count = pl->woff[nW];
+
+    // phase-solve groups: a shell joins the group before it when none of
+    // its samples reads a w of that group (reads always go to shorter w)
+    pl->group_wb.assign(1, 0);
+    for (size_t sh = 1; sh + 1 < pl->shell_wb.size(); ++sh) {
+        const int g0 = pl->group_wb.back();
+        bool reads_group = sh == 1;  // the seed shell is a group of its own
+        for (int32_t t = pl->woff[pl->shell_wb[sh]]; t < pl->woff[pl->shell_wb[sh + 1]] && !reads_group; ++t)
+            reads_group = (int)((pl->phase_code[t] >> 16) & 0x7fffu) >= g0 || (int)(pl->phase_code[t] & 0x7fffu) >= g0;
+        if (reads_group) pl->group_wb.push_back(pl->shell_wb[sh]);
+    }
+    pl->group_wb.push_back(nW);
+
+    // sample indices are kept in 30 bits by the kernels' tables
+    if (pl->s_count >= (int64_t)1 << 30) { *err = "bispectrum set too large"; return false; }
+
+    if (!plan_phase_solve(pl, err)) return false;
 
     // least-squares rounds: the last segment that targets each entry (as
     // its own w or as a side of one of its samples), then the prefixes of

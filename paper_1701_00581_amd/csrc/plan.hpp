@@ -121,6 +121,12 @@ struct HostPlan {
 // Builds everything above; returns false with *err set on bad sizes.
 bool build_plan(int N, int uc, int R, int slots, HostPlan *out, std::string *err);
 
+// The phase solve's part of the plan for the groups in group_wb (W, woff,
+// phase_code, shell_wb and R already set): the phasor window, the slot
+// codes, the padded code blocks and the units.  build_plan calls it after
+// forming the groups; returns false with *err set on bad sizes.
+bool plan_phase_solve(HostPlan *pl, std::string *err);
+
 // S in storage order, 4 ints per entry (wx, wy, vx, vy).
 void enumerate_S(int uc, int R, std::vector<int32_t> *wv);
 // W in storage order, 2 ints per entry.

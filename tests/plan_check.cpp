@@ -12,6 +12,9 @@
 //  * the phase-solve units cover W in order, and each w's padded code block
 //    holds its own sample codes followed by reads of the zero phasor's slot.
 // Prints one line per case ending in "bad=<count>"; exit status 0.
+// A case written shells:N:uc:R:K re-plans the phase solve with one group
+// per shell; merge:N:uc:R:K joins the first two groups after the seeds,
+// whose second reads the first, so its check must report a bad count.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -185,19 +188,28 @@ static long check_solve_units(const HostPlan &pl) {
 int main(int argc, char **argv) {
     for (int i = 1; i < argc; ++i) {
         int N = 0, uc = 0, R = 0, K = 0;
-        if (std::sscanf(argv[i], "%d:%d:%d:%d", &N, &uc, &R, &K) != 4) {
+        const std::string arg = argv[i];
+        const bool shells = arg.rfind("shells:", 0) == 0, merge = arg.rfind("merge:", 0) == 0;
+        const char *spec = argv[i] + (shells ? 7 : merge ? 6 : 0);
+        if (std::sscanf(spec, "%d:%d:%d:%d", &N, &uc, &R, &K) != 4) {
             std::printf("%s: bad argument bad=1\n", argv[i]);
             continue;
         }
         HostPlan pl;
         std::string err;
-        if (!build_plan(N, uc, R, K, &pl, &err)) {
-            std::printf("N=%d uc=%d R=%d K=%d: plan failed (%s) bad=1\n", N, uc, R, K, err.c_str());
+        bool ok = build_plan(N, uc, R, K, &pl, &err);
+        if (ok && (shells || merge)) {
+            if (shells) pl.group_wb = pl.shell_wb;
+            if (merge && pl.group_wb.size() > 3) pl.group_wb.erase(pl.group_wb.begin() + 2);
+            ok = plan_phase_solve(&pl, &err);
+        }
+        if (!ok) {
+            std::printf("%s: plan failed (%s) bad=1\n", argv[i], err.c_str());
             continue;
         }
         const long b1 = check_bispectrum(pl, N, K), b2 = check_lsq_rounds(pl), b3 = check_solve_units(pl);
-        std::printf("N=%d uc=%d R=%d K=%d items=%d shells=%d groups=%d units=%d ring=%d |S|=%lld bispectrum bad=%ld "
-                    "rounds bad=%ld units bad=%ld bad=%ld\n", N, uc, R, K, pl.n_items, (int)pl.shell_wb.size() - 1,
+        std::printf("%s items=%d shells=%d groups=%d units=%d ring=%d |S|=%lld bispectrum bad=%ld "
+                    "rounds bad=%ld units bad=%ld bad=%ld\n", argv[i], pl.n_items, (int)pl.shell_wb.size() - 1,
                     (int)pl.group_wb.size() - 1, pl.n_units, pl.ring_size, (long long)pl.s_count, b1, b2, b3, b1 + b2 + b3);
     }
     return 0;

@@ -1,7 +1,8 @@
 """The planner's work plans checked on the host (no GPU): the bispectrum
-kernel's LDS offsets, staged regions and output indices, and the
-least-squares rounds' accumulator windows, for the benchmark's parameters
-and others (tests/plan_check.cpp, built here with the host compiler)."""
+kernel's LDS offsets, staged regions and output indices, the least-squares
+rounds' accumulator windows, and the phase solve's groups and units, for
+the benchmark's parameters and others (tests/plan_check.cpp, built here with
+the host compiler)."""
 import os
 import shutil
 import subprocess
@@ -32,3 +33,26 @@ def test_work_plans_are_in_bounds_and_cover_every_sample_once(checker):
     assert len(lines) == len(CASES)
     for line in lines:
         assert line.endswith(" bad=0"), line
+
+
+def test_phase_solve_groups_join_only_independent_shells(checker):
+    """The solve's barriers fall between groups of shells.  Re-planned with
+    one group per shell (the order of the recursion itself) the units still
+    pass the checks; with the first two groups after the seeds joined, where
+    the second reads phasors of the first, the check must flag the plan, and
+    the planner's own grouping must need fewer units than one group per shell."""
+    geos = ["128:63:12:16", "64:31:3:16", "64:5:2:16", "128:40:16:16"]
+    cases = geos + [f"shells:{g}" for g in geos] + [f"merge:{g}" for g in geos]
+    r = subprocess.run([checker, *cases], check=True, capture_output=True, text=True)
+    lines = dict(zip(cases, r.stdout.strip().splitlines()))
+    assert len(lines) == len(cases)
+
+    def field(line, name):
+        return int(line.split(f" {name}=")[1].split()[0])
+
+    for g in geos:
+        assert lines[g].endswith(" bad=0"), lines[g]
+        assert lines[f"shells:{g}"].endswith(" bad=0"), lines[f"shells:{g}"]
+        assert field(lines[f"merge:{g}"], "units bad") > 0, lines[f"merge:{g}"]
+        assert field(lines[g], "groups") < field(lines[g], "shells")
+        assert field(lines[g], "units") < field(lines[f"shells:{g}"], "units")
