@@ -154,9 +154,9 @@ struct BispecArgs {
 hipError_t launch_bispec(const BispecArgs &a, hipStream_t st);
 
 struct SolveArgs {
-    int N = 0, nW = 0, nshell = 0, max_sw = 0;
+    int N = 0, nW = 0, max_sw = 0;
     BurstTable bt;                        // patches and the STF of each burst
-    const int *shell_wb = nullptr, *woff = nullptr, *Wxy = nullptr;
+    const int *woff = nullptr, *Wxy = nullptr;
     const int *w_slot = nullptr;          // LDS slot of each w's phasor
     const int *units = nullptr;           // phase-solve units (see plan.hpp)
     int n_units = 0;

@@ -31,9 +31,9 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct DevicePlan {
     HostPlan h;
-    int nshell = 0, max_sw = 0;
+    int max_sw = 0;
     std::vector<void *> bufs;
-    int *W = nullptr, *woff = nullptr, *shell_wb = nullptr, *w_slot = nullptr, *items = nullptr, *units = nullptr,
+    int *W = nullptr, *woff = nullptr, *w_slot = nullptr, *items = nullptr, *units = nullptr,
         *group_xy = nullptr, *slot = nullptr, *out_idx = nullptr, *lsq_fin = nullptr;
     unsigned *code = nullptr, *wcode = nullptr;
     float2 *twiddle = nullptr;
@@ -309,12 +309,9 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
         return fail(ctx, NVSM_ERR_OOM, "host allocation failed while planning");
     }
     const HostPlan &h = dp->h;
-    dp->nshell = (int)h.shell_wb.size() - 1;
-    int max_per_shell = 0;
-    for (int s = 0; s < dp->nshell; ++s) max_per_shell = std::max(max_per_shell, h.shell_wb[s + 1] - h.shell_wb[s]);
     dp->max_sw = h.max_sw;
-    if (max_per_shell > 16 || h.solve_code.empty() || h.n_inner > 512 || h.ring_size > 3072)
-        return fail(ctx, NVSM_ERR_INVALID_ARG, "shell or phasor window too large for the phase kernel");
+    if (h.solve_code.empty() || h.n_inner > 512 || h.ring_size > 3072)
+        return fail(ctx, NVSM_ERR_INVALID_ARG, "sample count or phasor window too large for the phase kernel");
     if (h.n_inner + h.lsq_span > LSQ_ACC)
         return fail(ctx, NVSM_ERR_INVALID_ARG, "least-squares accumulator window too large");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NVSM_ERR_HIP, "hipSetDevice failed");
@@ -323,7 +320,6 @@ nvsm_status get_plan(nvsm_context *ctx, const nvsm_params *p, int slots, DeviceP
     for (int k = 0; k < h.N; ++k) tw[k] = make_float2(h.twiddle[2 * k], h.twiddle[2 * k + 1]);
     if ((s = upload(dp.get(), h.W, &dp->W, &msg)) ||
         (s = upload(dp.get(), h.woff, &dp->woff, &msg)) ||
-        (s = upload(dp.get(), h.shell_wb, &dp->shell_wb, &msg)) ||
         (s = upload(dp.get(), h.w_slot, &dp->w_slot, &msg)) ||
         (s = upload(dp.get(), h.solve_units, &dp->units, &msg)) ||
         (s = upload(dp.get(), h.solve_code, &dp->code, &msg)) ||
@@ -448,8 +444,8 @@ hipError_t run_solve(nvsm_context *ctx, DevicePlan *dp, const nvsm_params *p, co
                      const float *power, const float *mean_spec, const float *bispec, double *amp,
                      double *phasor, hipStream_t st) {
     SolveArgs a;
-    a.N = p->patch; a.bt = bt; a.nW = (int)(dp->h.W.size() / 2); a.nshell = dp->nshell;
-    a.max_sw = dp->max_sw; a.shell_wb = dp->shell_wb; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
+    a.N = p->patch; a.bt = bt; a.nW = (int)(dp->h.W.size() / 2);
+    a.max_sw = dp->max_sw; a.woff = dp->woff; a.Wxy = dp->W; a.code = dp->code;
     a.zero_slot = dp->h.zero_slot;
     a.w_slot = dp->w_slot; a.n_inner = dp->h.n_inner; a.ring = dp->h.ring_size;
     a.units = dp->units; a.n_units = dp->h.n_units;
