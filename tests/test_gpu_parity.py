@@ -196,6 +196,7 @@ def test_solve_on_identical_inputs(torch_cuda):
 
 @pytest.mark.parametrize("N,u_cut,R,stride,window,H,W,F", [
     (128, 40, 16, 40, 1, 200, 200, 8),     # the largest R, a low cut-off, 3x3 patches at a short stride
+    (128, 63, 16, 32, 1, 128, 160, 3),     # the phase kernel's large window (2768 ring entries), 8 samples a lane
     (64, 20, 5, 24, 0, 100, 90, 9),        # no taper, odd F, clamped last row and column
     (64, 31, 3, 32, 1, 96, 130, 6),        # the smallest usual R
     (64, 3, 2, 32, 1, 96, 96, 5),          # |S| = 44, fewer samples than one padded code block
